@@ -1,0 +1,268 @@
+"""Plain FP64 CPU oracle of MITHRA's boosted-frame FDTD/PIC step.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The
+product library never loads it and shares no code with it.
+
+The arithmetic lives in ``mithra_oracle.c`` (plain C, scalar loops, SI units,
+double precision).  This module builds it with gcc and marshals arrays with
+ctypes; it does no arithmetic of the method itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mithra_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NDIAG = 16
+DIAG_COLUMNS = ("step", "t", "total_charge", "continuity_residual", "power",
+                "field_energy", "kinetic_energy", "Ex", "Ey", "Ez", "Bx", "By",
+                "Bz", "lost", "nonfinite", "spare")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O3", "-std=c99", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-fno-fast-math", "-Wall",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    I = ctypes.c_int
+    L = ctypes.c_long
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.orc_create.restype = P
+    lib.orc_create.argtypes = [ip, dp, dp, D, D, I, I, ip, D, D, D, D]
+    lib.orc_destroy.argtypes = [P]
+    lib.orc_set_particles.argtypes = [P, L, dp, dp, D, D]
+    lib.orc_set_particles.restype = I
+    lib.orc_set_background.argtypes = [P, dp]
+    lib.orc_config_diag.argtypes = [P, I, I, I, I]
+    for name in ("orc_field_update", "orc_vertex_fields", "orc_push", "orc_deposit",
+                 "orc_rotate"):
+        getattr(lib, name).argtypes = [P]
+    lib.orc_step.argtypes = [P, L]
+    lib.orc_diag_row.argtypes = [P, dp]
+    lib.orc_array.restype = dp
+    lib.orc_array.argtypes = [P, I]
+    lib.orc_alive.restype = ctypes.POINTER(ctypes.c_ubyte)
+    lib.orc_alive.argtypes = [P]
+    lib.orc_info.restype = L
+    lib.orc_info.argtypes = [P, I]
+    lib.orc_constants.argtypes = [P, dp]
+    lib.orc_undulator.argtypes = [P, D, D, D, D, dp, dp]
+    lib.orc_boris.argtypes = [D, D, D, dp, dp, dp]
+    lib.orc_gather.argtypes = [P, dp, dp, dp]
+    lib.orc_deposit_current.argtypes = [P, dp, dp]
+    _lib = lib
+    return lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+CONSTANT_NAMES = ("dt", "dtb", "A", "a1", "a2", "a4", "a6", "a8", "gamma0", "beta0",
+                  "B0", "ku", "mur_b0", "mur_b1", "mu0", "eps0", "c", "e", "me")
+
+
+class OracleSim:
+    """One simulation held by the C oracle.
+
+    Arrays are returned as numpy views shaped (nz, ny, nx) (x fastest), so
+    ``a[k, j, i]`` is grid point (i, j, k).  Potential components are
+    0: A_x at (i+1/2, j, k), 1: A_y at (i, j+1/2, k), 2: A_z at (i, j, k+1/2),
+    3: phi at (i, j, k).
+    """
+
+    def __init__(self, n, d, origin, courant=0.9, nsfd_A=-1.0, substeps=1,
+                 space_charge=1, bc=(0, 0, 0), lambda_u=0.015, K=1.0,
+                 gamma_beam=100.0, z_e=0.0):
+        lib = _load()
+        self._lib = lib
+        self.n = tuple(int(v) for v in n)
+        n_c = (ctypes.c_int * 3)(*self.n)
+        d_c = (ctypes.c_double * 3)(*[float(v) for v in d])
+        o_c = (ctypes.c_double * 3)(*[float(v) for v in origin])
+        bc_c = (ctypes.c_int * 3)(*[int(v) for v in bc])
+        self._h = lib.orc_create(n_c, d_c, o_c, float(courant), float(nsfd_A), int(substeps),
+                                 int(space_charge), bc_c, float(lambda_u), float(K),
+                                 float(gamma_beam), float(z_e))
+        if not self._h:
+            raise MemoryError("oracle allocation failed")
+        out = np.zeros(len(CONSTANT_NAMES))
+        lib.orc_constants(self._h, _dptr(out))
+        self.const = dict(zip(CONSTANT_NAMES, out.tolist()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc_destroy(h)
+            self._h = None
+
+    # ---- inputs ------------------------------------------------------------
+    def set_particles(self, x, u, q, m):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1, 3)
+        if x.shape != u.shape:
+            raise ValueError("x and u must both be (np, 3)")
+        self._lib.orc_set_particles(self._h, x.shape[0], _dptr(x), _dptr(u), float(q), float(m))
+
+    def set_background(self, bg):
+        bg = np.ascontiguousarray(bg, dtype=np.float64).reshape(-1)
+        self._lib.orc_set_background(self._h, _dptr(bg))
+
+    def config_diag(self, probe, kp):
+        self._lib.orc_config_diag(self._h, int(probe[0]), int(probe[1]), int(probe[2]), int(kp))
+
+    # ---- stepping ----------------------------------------------------------
+    def step(self, nsteps=1):
+        self._lib.orc_step(self._h, int(nsteps))
+
+    def field_update(self):
+        self._lib.orc_field_update(self._h)
+
+    def vertex_fields(self):
+        self._lib.orc_vertex_fields(self._h)
+
+    def push(self):
+        self._lib.orc_push(self._h)
+
+    def deposit(self):
+        self._lib.orc_deposit(self._h)
+
+    def rotate(self):
+        self._lib.orc_rotate(self._h)
+
+    # ---- state ---------------------------------------------------------------
+    def _mesh(self, which):
+        nx, ny, nz = self.n
+        ptr = self._lib.orc_array(self._h, which)
+        return np.ctypeslib.as_array(ptr, shape=(nz, ny, nx))
+
+    def pot(self, comp, level="cur"):
+        base = {"cur": 0, "prev": 4, "next": 8}[level]
+        return self._mesh(base + comp)
+
+    def J(self, comp):
+        return self._mesh(12 + comp)
+
+    @property
+    def rho(self):
+        return self._mesh(15)
+
+    @property
+    def rho_prev(self):
+        return self._mesh(16)
+
+    def E(self, comp):
+        return self._mesh(17 + comp)
+
+    def B(self, comp):
+        return self._mesh(20 + comp)
+
+    @property
+    def np(self):
+        return int(self._lib.orc_info(self._h, 0))
+
+    @property
+    def step_count(self):
+        return int(self._lib.orc_info(self._h, 1))
+
+    @property
+    def lost(self):
+        return int(self._lib.orc_info(self._h, 2))
+
+    def _parts(self, which):
+        npart = self.np
+        ptr = self._lib.orc_array(self._h, which)
+        return np.ctypeslib.as_array(ptr, shape=(max(npart, 1), 3))[:npart]
+
+    @property
+    def x(self):
+        return self._parts(23)
+
+    @property
+    def u(self):
+        return self._parts(24)
+
+    @property
+    def x_old(self):
+        return self._parts(25)
+
+    @property
+    def alive(self):
+        npart = self.np
+        ptr = self._lib.orc_alive(self._h)
+        return np.ctypeslib.as_array(ptr, shape=(max(npart, 1),))[:npart].astype(bool)
+
+    def diag(self):
+        nd = int(self._lib.orc_info(self._h, 3))
+        if nd == 0:
+            return np.zeros((0, NDIAG))
+        ptr = self._lib.orc_array(self._h, 26)
+        return np.ctypeslib.as_array(ptr, shape=(nd, NDIAG)).copy()
+
+    def diag_row_now(self):
+        row = np.zeros(NDIAG)
+        self._lib.orc_diag_row(self._h, _dptr(row))
+        return row
+
+    # ---- single pieces (for the pins) -----------------------------------------
+    def undulator(self, x, y, z, t):
+        E = np.zeros(3)
+        B = np.zeros(3)
+        self._lib.orc_undulator(self._h, float(x), float(y), float(z), float(t), _dptr(E), _dptr(B))
+        return E, B
+
+    def gather(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        E = np.zeros(3)
+        B = np.zeros(3)
+        self._lib.orc_gather(self._h, _dptr(x), _dptr(E), _dptr(B))
+        return E, B
+
+    def deposit_current(self, x0, x1):
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        x1 = np.ascontiguousarray(x1, dtype=np.float64)
+        self._lib.orc_deposit_current(self._h, _dptr(x0), _dptr(x1))
+
+
+def boris(q, m, dtb, u, E, B):
+    """One Boris step of eq. (BorisScheme) done by the C oracle."""
+    lib = _load()
+    u = np.array(u, dtype=np.float64)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    lib.orc_boris(float(q), float(m), float(dtb), _dptr(u), _dptr(E), _dptr(B))
+    return u
+
+
+def from_workload(w):
+    """Oracle simulation loaded with a workload from the seeded generator."""
+    s = OracleSim(w.n, w.d, w.origin, w.courant, w.nsfd_A, w.substeps, w.space_charge,
+                  w.bc, w.lambda_u, w.K, w.gamma_beam, w.z_e)
+    s.config_diag(w.probe, w.kp)
+    s.set_particles(w.x, w.u, w.q, w.m)
+    return s

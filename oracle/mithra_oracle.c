@@ -1,0 +1,752 @@
+/*
+ * Plain FP64 CPU oracle of the boosted-frame FDTD/PIC time step of MITHRA
+ * (Fallahi, Yahaghi, Kaertner, arXiv:1612.03310, chapter "Methodology").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no source with the GPU library.
+ *
+ * Everything is in SI units and double precision, with plain scalar loops in
+ * the order the paper describes the method.  No blocking, fusion or
+ * reordering beyond what the equations state.
+ *
+ * Readings of the paper taken here (each one is also listed in the design
+ * notes of the repository):
+ *   R1  the coefficient alpha'_6 = alpha'_7 of eq. (updateEquation) carries
+ *       -2A(c dt/dx)^2 - 2A(c dt/dy)^2 (the printed second dx is dy);
+ *   R2  source signs follow eqs. (HelmholtzA), (HelmholtzF):
+ *       A^{n+1} += (c dt)^2 mu0 J,  phi^{n+1} += (c dt)^2 rho / eps0;
+ *   R3  the n+1 term of B_z uses A_y on both sides;
+ *   R4  interpolation weights are the standard linear (cloud-in-cell)
+ *       weights 1-f and f;
+ *   R5  rho and phi live on vertices, A_l and J_l on the l-edges
+ *       (A_x at (i+1/2, j, k), ...; along l that grid has one point fewer,
+ *       so all grids span the same box); the vertex value of A_l used in the
+ *       E, B formulas is the mean of the two adjacent edge samples; the
+ *       current is deposited with Esirkepov's density decomposition so
+ *       that discrete charge continuity holds;
+ *   R6  with N > 1 particle sub-steps, the grid field is interpolated once
+ *       at the start position (where and when it is centred) and held;
+ *       the undulator field is evaluated at every sub-step;
+ *   R8  rest-frame undulator field: E_x = -g0 b0 c B'_y, B_y = g0 B'_y,
+ *       B_z = B'_z, phase k_u z' with z' = g0 (z - z_e + b0 c t);
+ *   R10 start from zero potentials, J^0 = 0, rho^{1/2} from the input
+ *       positions (taken as r^{1/2}; momenta as u^0);
+ *   R16 first-order Mur on faces, then edges, then corners; a point on
+ *       several faces uses the rule of its highest-priority axis
+ *       (z > y > x);
+ *   R17 a particle whose cell leaves [2, n_d - 3] on any axis is lost.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* CODATA 2018 */
+#define ORC_C 299792458.0
+#define ORC_QE 1.602176634e-19
+#define ORC_ME 9.1093837015e-31
+#define ORC_EPS0 8.8541878128e-12
+#define ORC_MU0 (1.0 / (ORC_EPS0 * ORC_C * ORC_C))
+#define ORC_PI 3.14159265358979323846
+
+#define ORC_NDIAG 16
+
+typedef struct orc_sim {
+    int n[3];
+    double d[3], o[3];
+    double nu, A;
+    int N, sc, bc[3]; /* bc: 0 = first-order Mur, 1 = periodic */
+    double lambda_u, K, gamma_beam, z_e;
+    /* derived constants */
+    double dt, dtb, a1, a2, a4, a6, a8;
+    double mur[3][5];
+    double gamma0, beta0, B0, ku;
+    /* mesh arrays, n[0]*n[1]*n[2] doubles each, x fastest */
+    long ncell;
+    double *pot[3][4]; /* [level slot][Ax, Ay, Az, phi] */
+    int lprev, lcur, lnext;
+    double *J[3], *rho, *rho_prev, *bg;
+    double *E[3], *B[3];
+    /* particles */
+    long np;
+    double *x, *u, *x_old;
+    unsigned char *alive;
+    double q, m;
+    long step, lost;
+    int nonfinite_u;
+    /* diagnostics */
+    int probe[3], kp;
+    double *diag;
+    long ndiag, cap;
+} orc_sim;
+
+/* ---- indexing ---------------------------------------------------------- */
+
+static inline long wrap(const orc_sim *s, int a, int i)
+{
+    int n = s->n[a];
+    if (i >= 0 && i < n) return i;
+    if (!s->bc[a]) abort(); /* an out-of-range read is an oracle bug */
+    return i < 0 ? i + n : i - n; /* periodic axis; offsets are at most 1 */
+}
+
+static inline long IX(const orc_sim *s, int i, int j, int k)
+{
+    long ii = wrap(s, 0, i);
+    long jj = wrap(s, 1, j);
+    long kk = wrap(s, 2, k);
+    return (kk * s->n[1] + jj) * s->n[0] + ii;
+}
+
+/* range of vertices where the E, B formulas are evaluated: [1, n-2] on a
+   Mur axis, every point on a periodic axis */
+static void interior(const orc_sim *s, int d, int *lo, int *hi)
+{
+    if (s->bc[d]) { *lo = 0; *hi = s->n[d] - 1; }
+    else { *lo = 1; *hi = s->n[d] - 2; }
+}
+
+/* number of points of component c's grid along axis a (reading R5): the
+   l-edge grid of A_l and J_l has one point fewer than the vertex grid along
+   l, so every grid spans the same box [0, (n-1) d]; the last layer of the
+   array is then unused.  On a periodic axis all n points are used. */
+static int extent(const orc_sim *s, int c, int a)
+{
+    return (c == a && !s->bc[a]) ? s->n[a] - 1 : s->n[a];
+}
+
+/* ---- set-up: constants of eqs. (updateEquation), (NSFDCoefficient),
+        the first-order Mur coefficients, and the Lorentz boost ----------- */
+
+orc_sim *orc_create(const int n[3], const double d[3], const double origin[3],
+                    double courant, double nsfd_A, int substeps, int space_charge,
+                    const int bc[3], double lambda_u, double K, double gamma_beam,
+                    double z_e)
+{
+    orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+    for (int a = 0; a < 3; a++) {
+        s->n[a] = n[a];
+        s->d[a] = d[a];
+        s->o[a] = origin[a];
+        s->bc[a] = bc[a];
+    }
+    s->nu = courant;
+    s->N = substeps;
+    s->sc = space_charge;
+    s->lambda_u = lambda_u;
+    s->K = K;
+    s->gamma_beam = gamma_beam;
+    s->z_e = z_e;
+
+    double dx = d[0], dy = d[1], dz = d[2];
+    /* time step from the longitudinal cell and the Courant number */
+    s->dt = courant * dz / ORC_C;
+    s->dtb = s->dt / substeps;
+    /* eq. (NSFDCoefficient) unless an explicit A is given */
+    if (nsfd_A < 0.0)
+        s->A = 0.25 * (1.0 + 0.02 / ((dz / dx) * (dz / dx) + (dz / dy) * (dz / dy)));
+    else
+        s->A = nsfd_A;
+    double nx2 = (ORC_C * s->dt / dx) * (ORC_C * s->dt / dx);
+    double ny2 = (ORC_C * s->dt / dy) * (ORC_C * s->dt / dy);
+    double nz2 = (ORC_C * s->dt / dz) * (ORC_C * s->dt / dz);
+    /* coefficients alpha' of eq. (updateEquation), reading R1 */
+    s->a1 = 2.0 * (1.0 - (1.0 - 2.0 * s->A) * nx2 - (1.0 - 2.0 * s->A) * ny2 - nz2);
+    s->a2 = nx2;
+    s->a4 = ny2;
+    s->a6 = nz2 - 2.0 * s->A * nx2 - 2.0 * s->A * ny2;
+    s->a8 = (ORC_C * s->dt) * (ORC_C * s->dt);
+    /* first-order Mur coefficients beta_0..beta_4, per face axis */
+    for (int a = 0; a < 3; a++) {
+        double cdt = ORC_C * s->dt, h = d[a];
+        s->mur[a][0] = (cdt - h) / (cdt + h);
+        s->mur[a][1] = 2.0 * h / (cdt + h);
+        s->mur[a][2] = -1.0;
+        s->mur[a][3] = 2.0 * h / (cdt + h);
+        s->mur[a][4] = (cdt - h) / (cdt + h);
+    }
+    /* average Lorentz factor in the undulator and the frame velocity */
+    s->gamma0 = gamma_beam / sqrt(1.0 + K * K / 2.0);
+    s->beta0 = sqrt(1.0 - 1.0 / (s->gamma0 * s->gamma0));
+    /* K = e B0 lambda_u / (2 pi m c) */
+    s->B0 = 2.0 * ORC_PI * ORC_ME * ORC_C * K / (ORC_QE * lambda_u);
+    s->ku = 2.0 * ORC_PI / lambda_u;
+
+    s->ncell = (long)n[0] * n[1] * n[2];
+    for (int l = 0; l < 3; l++)
+        for (int c = 0; c < 4; c++)
+            s->pot[l][c] = (double *)calloc(s->ncell, sizeof(double));
+    s->lprev = 0;
+    s->lcur = 1;
+    s->lnext = 2;
+    for (int c = 0; c < 3; c++) {
+        s->J[c] = (double *)calloc(s->ncell, sizeof(double));
+        s->E[c] = (double *)calloc(s->ncell, sizeof(double));
+        s->B[c] = (double *)calloc(s->ncell, sizeof(double));
+    }
+    s->rho = (double *)calloc(s->ncell, sizeof(double));
+    s->rho_prev = (double *)calloc(s->ncell, sizeof(double));
+    s->bg = NULL;
+    s->probe[0] = n[0] / 2;
+    s->probe[1] = n[1] / 2;
+    s->probe[2] = n[2] / 2;
+    s->kp = n[2] / 2;
+    s->cap = 1024;
+    s->diag = (double *)malloc(sizeof(double) * ORC_NDIAG * s->cap);
+    return s;
+}
+
+void orc_destroy(orc_sim *s)
+{
+    if (!s) return;
+    for (int l = 0; l < 3; l++)
+        for (int c = 0; c < 4; c++) free(s->pot[l][c]);
+    for (int c = 0; c < 3; c++) {
+        free(s->J[c]);
+        free(s->E[c]);
+        free(s->B[c]);
+    }
+    free(s->rho);
+    free(s->rho_prev);
+    free(s->bg);
+    free(s->x);
+    free(s->u);
+    free(s->x_old);
+    free(s->alive);
+    free(s->diag);
+    free(s);
+}
+
+/* static neutralising background charge (test fixture, not in the paper) */
+void orc_set_background(orc_sim *s, const double *bg)
+{
+    if (!s->bg) s->bg = (double *)calloc(s->ncell, sizeof(double));
+    memcpy(s->bg, bg, sizeof(double) * s->ncell);
+}
+
+void orc_config_diag(orc_sim *s, int pi, int pj, int pk, int kp)
+{
+    s->probe[0] = pi;
+    s->probe[1] = pj;
+    s->probe[2] = pk;
+    s->kp = kp;
+}
+
+/* ---- cloud-in-cell weights (eq. (fieldInterpolation), reading R4) ------ */
+
+static void cell_of(const orc_sim *s, const double *x, int c[3], double f[3])
+{
+    for (int a = 0; a < 3; a++) {
+        double xi = (x[a] - s->o[a]) / s->d[a];
+        double fl = floor(xi);
+        c[a] = (int)fl;
+        f[a] = xi - fl;
+    }
+}
+
+static int inside(const orc_sim *s, const int c[3])
+{
+    for (int a = 0; a < 3; a++)
+        if (c[a] < 2 || c[a] > s->n[a] - 3) return 0;
+    return 1;
+}
+
+/* ---- charge and current deposition ------------------------------------- */
+
+/* charge density of one macro-particle spread to the 8 vertices of its cell,
+   rho = q / (dx dy dz) times the linear weights (section "Current
+   Deposition") */
+static void deposit_rho(orc_sim *s, double *rho, const double *x)
+{
+    int c[3];
+    double f[3];
+    cell_of(s, x, c, f);
+    double q_dv = s->q / (s->d[0] * s->d[1] * s->d[2]);
+    for (int K = 0; K < 2; K++)
+        for (int J = 0; J < 2; J++)
+            for (int I = 0; I < 2; I++) {
+                double w = (I ? f[0] : 1.0 - f[0]) * (J ? f[1] : 1.0 - f[1]) *
+                           (K ? f[2] : 1.0 - f[2]);
+                rho[IX(s, c[0] + I, c[1] + J, c[2] + K)] += q_dv * w;
+            }
+}
+
+/* current of one macro-particle moving from x0 (time n+1/2) to x1 (time
+   n+3/2), eq. (currentIntegral) with reading R5: Esirkepov's decomposition
+   of the change of the linear-weight density into three directional parts
+   W^x, W^y, W^z; J_l on the l-edges is minus the running sum of W^l along l,
+   scaled by q dl / (dV dt). */
+void orc_deposit_current(orc_sim *s, const double *x0, const double *x1)
+{
+    int c0[3], c1[3], base[3];
+    double f0[3], f1[3];
+    cell_of(s, x0, c0, f0);
+    cell_of(s, x1, c1, f1);
+    double S0[3][3], DS[3][3];
+    for (int a = 0; a < 3; a++) {
+        base[a] = c0[a] < c1[a] ? c0[a] : c1[a];
+        double s1[3] = {0.0, 0.0, 0.0};
+        for (int m = 0; m < 3; m++) S0[a][m] = 0.0;
+        S0[a][c0[a] - base[a]] += 1.0 - f0[a];
+        S0[a][c0[a] - base[a] + 1] += f0[a];
+        s1[c1[a] - base[a]] += 1.0 - f1[a];
+        s1[c1[a] - base[a] + 1] += f1[a];
+        for (int m = 0; m < 3; m++) DS[a][m] = s1[m] - S0[a][m];
+    }
+    double dV = s->d[0] * s->d[1] * s->d[2];
+    /* W^l at the 3x3x3 vertices of the box starting at base */
+    for (int l = 0; l < 3; l++) {
+        int p = (l + 1) % 3, r = (l + 2) % 3; /* the two other axes */
+        double unit = s->q * s->d[l] / (dV * s->dt);
+        for (int b = 0; b < 3; b++)
+            for (int e = 0; e < 3; e++) {
+                double run = 0.0;
+                for (int a = 0; a < 2; a++) { /* edge (base+a) + 1/2 */
+                    double W = DS[l][a] * (S0[p][b] * S0[r][e] + 0.5 * DS[p][b] * S0[r][e] +
+                                           0.5 * S0[p][b] * DS[r][e] +
+                                           DS[p][b] * DS[r][e] / 3.0);
+                    run += W;
+                    int v[3];
+                    v[l] = base[l] + a;
+                    v[p] = base[p] + b;
+                    v[r] = base[r] + e;
+                    s->J[l][IX(s, v[0], v[1], v[2])] += -unit * run;
+                }
+            }
+    }
+}
+
+/* ---- particles ----------------------------------------------------------- */
+
+int orc_set_particles(orc_sim *s, long np, const double *x, const double *u, double q,
+                      double m)
+{
+    free(s->x);
+    free(s->u);
+    free(s->x_old);
+    free(s->alive);
+    s->np = np;
+    s->q = q;
+    s->m = m;
+    s->x = (double *)malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
+    s->u = (double *)malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
+    s->x_old = (double *)malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
+    s->alive = (unsigned char *)malloc(np > 0 ? np : 1);
+    memcpy(s->x, x, sizeof(double) * 3 * np);
+    memcpy(s->u, u, sizeof(double) * 3 * np);
+    memcpy(s->x_old, x, sizeof(double) * 3 * np);
+    s->lost = 0;
+    /* reading R10: rho^{1/2} from the initial positions, J^0 = 0 */
+    memset(s->rho, 0, sizeof(double) * s->ncell);
+    for (int c = 0; c < 3; c++) memset(s->J[c], 0, sizeof(double) * s->ncell);
+    for (long p = 0; p < np; p++) {
+        int c[3];
+        double f[3];
+        cell_of(s, &s->x[3 * p], c, f);
+        s->alive[p] = (unsigned char)inside(s, c);
+        if (!s->alive[p]) { s->lost++; continue; }
+        deposit_rho(s, s->rho, &s->x[3 * p]);
+    }
+    memcpy(s->rho_prev, s->rho, sizeof(double) * s->ncell);
+    return 0;
+}
+
+/* ---- O2: potential update, eq. (updateEquation) -------------------------- */
+
+static void boundary_mur1(orc_sim *s, int comp);
+
+void orc_field_update(orc_sim *s)
+{
+    double A = s->A;
+    for (int c = 0; c < 4; c++) {
+        double *P = s->pot[s->lcur][c], *Q = s->pot[s->lprev][c], *R = s->pot[s->lnext][c];
+        if (c == 3 && !s->sc) {
+            memset(R, 0, sizeof(double) * s->ncell);
+            continue;
+        }
+        /* interior points of this component's grid: [1, extent-2] on a Mur
+           axis, all points on a periodic axis */
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; a++) {
+            lo[a] = s->bc[a] ? 0 : 1;
+            hi[a] = s->bc[a] ? s->n[a] - 1 : extent(s, c, a) - 2;
+        }
+        for (int k = lo[2]; k <= hi[2]; k++)
+            for (int j = lo[1]; j <= hi[1]; j++)
+                for (int i = lo[0]; i <= hi[0]; i++) {
+                    long p = IX(s, i, j, k);
+                    /* z-weighted transverse neighbours, eq. (NSFDtrick) */
+                    double bxp = A * P[IX(s, i + 1, j, k - 1)] + (1.0 - 2.0 * A) * P[IX(s, i + 1, j, k)] +
+                                 A * P[IX(s, i + 1, j, k + 1)];
+                    double bxm = A * P[IX(s, i - 1, j, k - 1)] + (1.0 - 2.0 * A) * P[IX(s, i - 1, j, k)] +
+                                 A * P[IX(s, i - 1, j, k + 1)];
+                    double byp = A * P[IX(s, i, j + 1, k - 1)] + (1.0 - 2.0 * A) * P[IX(s, i, j + 1, k)] +
+                                 A * P[IX(s, i, j + 1, k + 1)];
+                    double bym = A * P[IX(s, i, j - 1, k - 1)] + (1.0 - 2.0 * A) * P[IX(s, i, j - 1, k)] +
+                                 A * P[IX(s, i, j - 1, k + 1)];
+                    /* source term, signs of reading R2 */
+                    double zeta;
+                    if (c < 3)
+                        zeta = ORC_MU0 * s->J[c][p];
+                    else
+                        zeta = (s->rho[p] + (s->bg ? s->bg[p] : 0.0)) / ORC_EPS0;
+                    R[p] = -Q[p] + s->a1 * P[p] + s->a2 * bxp + s->a2 * bxm + s->a4 * byp +
+                           s->a4 * bym + s->a6 * P[IX(s, i, j, k + 1)] + s->a6 * P[IX(s, i, j, k - 1)] +
+                           s->a8 * zeta;
+                }
+        boundary_mur1(s, c);
+    }
+}
+
+/* ---- O3: first-order Mur boundary, staged as reading R16 ----------------- */
+
+static void boundary_mur1(orc_sim *s, int c)
+{
+    double *P = s->pot[s->lcur][c], *Q = s->pot[s->lprev][c], *R = s->pot[s->lnext][c];
+    int ext[3];
+    for (int a = 0; a < 3; a++) ext[a] = extent(s, c, a);
+    for (int stage = 1; stage <= 3; stage++)
+        for (int k = 0; k < ext[2]; k++)
+            for (int j = 0; j < ext[1]; j++)
+                for (int i = 0; i < ext[0]; i++) {
+                    int v[3] = {i, j, k}, nb = 0, top = -1;
+                    for (int a = 0; a < 3; a++)
+                        if (!s->bc[a] && (v[a] == 0 || v[a] == ext[a] - 1)) {
+                            nb++;
+                            top = a; /* highest axis wins: z > y > x */
+                        }
+                    if (nb != stage) continue;
+                    int w[3] = {i, j, k};
+                    w[top] += (v[top] == 0) ? 1 : -1; /* inward neighbour */
+                    long p = IX(s, v[0], v[1], v[2]), q = IX(s, w[0], w[1], w[2]);
+                    const double *b = s->mur[top];
+                    R[p] = b[0] * Q[p] + b[1] * P[p] + b[2] * Q[q] + b[3] * P[q] + b[4] * R[q];
+                }
+}
+
+/* ---- O4: E and B at the vertices at t_{n+1/2} ------------------------------ */
+
+/* vertex value of the edge-sampled A_l: mean of the two adjacent edges */
+static inline double abar(const orc_sim *s, const double *Al, int l, int i, int j, int k)
+{
+    int v[3] = {i, j, k};
+    v[l] -= 1;
+    return 0.5 * (Al[IX(s, i, j, k)] + Al[IX(s, v[0], v[1], v[2])]);
+}
+
+void orc_vertex_fields(orc_sim *s)
+{
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; a++) interior(s, a, &lo[a], &hi[a]);
+    for (int c = 0; c < 3; c++) {
+        memset(s->E[c], 0, sizeof(double) * s->ncell);
+        memset(s->B[c], 0, sizeof(double) * s->ncell);
+    }
+    double *const *An = s->pot[s->lcur];
+    double *const *An1 = s->pot[s->lnext];
+    const double *phi = s->pot[s->lcur][3];
+    double dx = s->d[0], dy = s->d[1], dz = s->d[2], dt = s->dt;
+    for (int k = lo[2]; k <= hi[2]; k++)
+        for (int j = lo[1]; j <= hi[1]; j++)
+            for (int i = lo[0]; i <= hi[0]; i++) {
+                long p = IX(s, i, j, k);
+                /* eq. (EvsA) discretised at the vertex */
+                s->E[0][p] = -(abar(s, An1[0], 0, i, j, k) - abar(s, An[0], 0, i, j, k)) / dt -
+                             (phi[IX(s, i + 1, j, k)] - phi[IX(s, i - 1, j, k)]) / (2.0 * dx);
+                s->E[1][p] = -(abar(s, An1[1], 1, i, j, k) - abar(s, An[1], 1, i, j, k)) / dt -
+                             (phi[IX(s, i, j + 1, k)] - phi[IX(s, i, j - 1, k)]) / (2.0 * dy);
+                s->E[2][p] = -(abar(s, An1[2], 2, i, j, k) - abar(s, An[2], 2, i, j, k)) / dt -
+                             (phi[IX(s, i, j, k + 1)] - phi[IX(s, i, j, k - 1)]) / (2.0 * dz);
+                /* eq. (BvsA): mean of the central curls at levels n and n+1 */
+                double bx = 0.0, by = 0.0, bz = 0.0;
+                for (int lev = 0; lev < 2; lev++) {
+                    double *const *Ap = lev ? An1 : An;
+                    bx += (abar(s, Ap[2], 2, i, j + 1, k) - abar(s, Ap[2], 2, i, j - 1, k)) / (2.0 * dy) -
+                          (abar(s, Ap[1], 1, i, j, k + 1) - abar(s, Ap[1], 1, i, j, k - 1)) / (2.0 * dz);
+                    by += (abar(s, Ap[0], 0, i, j, k + 1) - abar(s, Ap[0], 0, i, j, k - 1)) / (2.0 * dz) -
+                          (abar(s, Ap[2], 2, i + 1, j, k) - abar(s, Ap[2], 2, i - 1, j, k)) / (2.0 * dx);
+                    bz += (abar(s, Ap[1], 1, i + 1, j, k) - abar(s, Ap[1], 1, i - 1, j, k)) / (2.0 * dx) -
+                          (abar(s, Ap[0], 0, i, j + 1, k) - abar(s, Ap[0], 0, i, j - 1, k)) / (2.0 * dy);
+                }
+                s->B[0][p] = 0.5 * bx;
+                s->B[1][p] = 0.5 * by;
+                s->B[2][p] = 0.5 * bz;
+            }
+}
+
+/* ---- O5: field at a particle, linear interpolation from the 8 vertices ---- */
+
+void orc_gather(const orc_sim *s, const double *x, double *E, double *B)
+{
+    int c[3];
+    double f[3];
+    cell_of(s, x, c, f);
+    for (int a = 0; a < 3; a++) E[a] = B[a] = 0.0;
+    for (int K = 0; K < 2; K++)
+        for (int J = 0; J < 2; J++)
+            for (int I = 0; I < 2; I++) {
+                double w = (I ? f[0] : 1.0 - f[0]) * (J ? f[1] : 1.0 - f[1]) *
+                           (K ? f[2] : 1.0 - f[2]);
+                long p = IX(s, c[0] + I, c[1] + J, c[2] + K);
+                for (int a = 0; a < 3; a++) {
+                    E[a] += w * s->E[a][p];
+                    B[a] += w * s->B[a][p];
+                }
+            }
+}
+
+/* ---- O6: static planar undulator seen in the rest frame ------------------ */
+
+/* eqs. (undulatorField), fringe field for z' < 0, and the boost of reading R8 */
+void orc_undulator(const orc_sim *s, double x, double y, double z, double t, double *E,
+                   double *B)
+{
+    (void)x;
+    double zp = s->gamma0 * (z - s->z_e + s->beta0 * ORC_C * t); /* lab z' */
+    double ph = s->ku * zp, by, bz;
+    if (zp >= 0.0) {
+        by = s->B0 * cosh(s->ku * y) * sin(ph);
+        bz = s->B0 * sinh(s->ku * y) * cos(ph);
+    } else {
+        double g = exp(-ph * ph / 2.0);
+        by = s->B0 * cosh(s->ku * y) * ph * g;
+        bz = s->B0 * sinh(s->ku * y) * g;
+    }
+    E[0] = -s->gamma0 * s->beta0 * ORC_C * by;
+    E[1] = 0.0;
+    E[2] = 0.0;
+    B[0] = 0.0;
+    B[1] = s->gamma0 * by;
+    B[2] = bz;
+}
+
+/* ---- O7: Boris scheme, eq. (BorisScheme), for a charge q and mass m ------- */
+
+void orc_boris(double q, double m, double dtb, double *u, const double *E, const double *B)
+{
+    double h = q * dtb / (2.0 * m * ORC_C);
+    double t1[3] = {u[0] + h * E[0], u[1] + h * E[1], u[2] + h * E[2]};
+    double alpha = q * dtb / (2.0 * m * sqrt(1.0 + t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]));
+    double t2[3] = {t1[0] + alpha * (t1[1] * B[2] - t1[2] * B[1]),
+                    t1[1] + alpha * (t1[2] * B[0] - t1[0] * B[2]),
+                    t1[2] + alpha * (t1[0] * B[1] - t1[1] * B[0])};
+    double fac = 2.0 * alpha / (1.0 + alpha * alpha * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]));
+    double w[3] = {fac * B[0], fac * B[1], fac * B[2]};
+    double t3[3] = {t1[0] + (t2[1] * w[2] - t2[2] * w[1]),
+                    t1[1] + (t2[2] * w[0] - t2[0] * w[2]),
+                    t1[2] + (t2[0] * w[1] - t2[1] * w[0])};
+    u[0] = t3[0] + h * E[0];
+    u[1] = t3[1] + h * E[1];
+    u[2] = t3[2] + h * E[2];
+}
+
+void orc_push(orc_sim *s)
+{
+    double t0 = (s->step + 0.5) * s->dt;
+    for (long p = 0; p < s->np; p++) {
+        double *x = &s->x[3 * p], *u = &s->u[3 * p];
+        s->x_old[3 * p + 0] = x[0];
+        s->x_old[3 * p + 1] = x[1];
+        s->x_old[3 * p + 2] = x[2];
+        if (!s->alive[p]) continue;
+        double Eg[3], Bg[3];
+        orc_gather(s, x, Eg, Bg); /* reading R6 */
+        for (int sub = 0; sub < s->N; sub++) {
+            double ts = t0 + sub * s->dtb, Eu[3], Bu[3], Et[3], Bt[3];
+            orc_undulator(s, x[0], x[1], x[2], ts, Eu, Bu);
+            for (int a = 0; a < 3; a++) {
+                Et[a] = Eg[a] + Eu[a];
+                Bt[a] = Bg[a] + Bu[a];
+            }
+            orc_boris(s->q, s->m, s->dtb, u, Et, Bt);
+            double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            for (int a = 0; a < 3; a++) x[a] += ORC_C * s->dtb * u[a] / g;
+        }
+        if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(x[0]) &&
+              isfinite(x[1]) && isfinite(x[2]))) {
+            s->nonfinite_u = 1;
+            s->alive[p] = 0;
+            s->lost++;
+            continue;
+        }
+        /* O8: loss (reading R17) */
+        int c[3];
+        double f[3];
+        cell_of(s, x, c, f);
+        if (!inside(s, c)) {
+            s->alive[p] = 0;
+            s->lost++;
+        }
+    }
+}
+
+/* ---- O9: deposit rho^{n+3/2} and J^{n+1} ---------------------------------- */
+
+void orc_deposit(orc_sim *s)
+{
+    memcpy(s->rho_prev, s->rho, sizeof(double) * s->ncell);
+    memset(s->rho, 0, sizeof(double) * s->ncell);
+    for (int c = 0; c < 3; c++) memset(s->J[c], 0, sizeof(double) * s->ncell);
+    for (long p = 0; p < s->np; p++) {
+        if (!s->alive[p]) continue;
+        deposit_rho(s, s->rho, &s->x[3 * p]);
+        orc_deposit_current(s, &s->x_old[3 * p], &s->x[3 * p]);
+    }
+}
+
+/* ---- O10: diagnostics, one row per step ------------------------------------
+   row: step, t, total charge, continuity residual, radiated power through the
+   plane k = kp, field energy, kinetic energy, probe E (3), probe B (3), lost,
+   non-finite flag, spare */
+
+void orc_diag_row(orc_sim *s, double *row)
+{
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; a++) interior(s, a, &lo[a], &hi[a]);
+    double dx = s->d[0], dy = s->d[1], dz = s->d[2], dV = dx * dy * dz;
+    double charge = 0.0, rmax = 0.0, resmax = 0.0;
+    for (long p = 0; p < s->ncell; p++) {
+        charge += s->rho[p] * dV;
+        if (fabs(s->rho[p]) > rmax) rmax = fabs(s->rho[p]);
+    }
+    for (int k = 1; k < s->n[2]; k++)
+        for (int j = 1; j < s->n[1]; j++)
+            for (int i = 1; i < s->n[0]; i++) {
+                long p = IX(s, i, j, k);
+                double div = (s->J[0][p] - s->J[0][IX(s, i - 1, j, k)]) / dx +
+                             (s->J[1][p] - s->J[1][IX(s, i, j - 1, k)]) / dy +
+                             (s->J[2][p] - s->J[2][IX(s, i, j, k - 1)]) / dz;
+                double r = fabs(s->rho[p] - s->rho_prev[p] + s->dt * div);
+                if (r > resmax) resmax = r;
+            }
+    double power = 0.0;
+    for (int j = lo[1]; j <= hi[1]; j++)
+        for (int i = lo[0]; i <= hi[0]; i++) {
+            long p = IX(s, i, j, s->kp);
+            power += (s->E[0][p] * s->B[1][p] - s->E[1][p] * s->B[0][p]) / ORC_MU0 * dx * dy;
+        }
+    double wf = 0.0;
+    for (int k = lo[2]; k <= hi[2]; k++)
+        for (int j = lo[1]; j <= hi[1]; j++)
+            for (int i = lo[0]; i <= hi[0]; i++) {
+                long p = IX(s, i, j, k);
+                double e2 = s->E[0][p] * s->E[0][p] + s->E[1][p] * s->E[1][p] + s->E[2][p] * s->E[2][p];
+                double b2 = s->B[0][p] * s->B[0][p] + s->B[1][p] * s->B[1][p] + s->B[2][p] * s->B[2][p];
+                wf += (0.5 * ORC_EPS0 * e2 + 0.5 * b2 / ORC_MU0) * dV;
+            }
+    double wk = 0.0;
+    for (long p = 0; p < s->np; p++) {
+        if (!s->alive[p]) continue;
+        const double *u = &s->u[3 * p];
+        wk += (sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) - 1.0) * s->m * ORC_C * ORC_C;
+    }
+    long pp = IX(s, s->probe[0], s->probe[1], s->probe[2]);
+    row[0] = (double)s->step;
+    row[1] = (s->step + 0.5) * s->dt;
+    row[2] = charge;
+    row[3] = rmax > 0.0 ? resmax / rmax : 0.0;
+    row[4] = power;
+    row[5] = wf;
+    row[6] = wk;
+    for (int a = 0; a < 3; a++) {
+        row[7 + a] = s->E[a][pp];
+        row[10 + a] = s->B[a][pp];
+    }
+    row[13] = (double)s->lost;
+    int nf = s->nonfinite_u;
+    for (int a = 2; a < 13; a++)
+        if (!isfinite(row[a])) nf = 1;
+    row[14] = nf;
+    row[15] = 0.0;
+}
+
+/* ---- O11: rotate the time levels ------------------------------------------ */
+
+void orc_rotate(orc_sim *s)
+{
+    int t = s->lprev;
+    s->lprev = s->lcur;
+    s->lcur = s->lnext;
+    s->lnext = t;
+    s->step++;
+}
+
+/* one full time step in the order of the method */
+void orc_step(orc_sim *s, long nsteps)
+{
+    for (long it = 0; it < nsteps; it++) {
+        orc_field_update(s);  /* potentials at n+1, Mur faces */
+        orc_vertex_fields(s); /* E, B at n+1/2 */
+        orc_push(s);          /* gather, undulator, Boris, loss */
+        orc_deposit(s);       /* rho^{n+3/2}, J^{n+1} */
+        if (s->ndiag == s->cap) {
+            s->cap *= 2;
+            s->diag = (double *)realloc(s->diag, sizeof(double) * ORC_NDIAG * s->cap);
+        }
+        orc_diag_row(s, &s->diag[ORC_NDIAG * s->ndiag]);
+        s->ndiag++;
+        orc_rotate(s);
+    }
+}
+
+/* ---- accessors for the Python wrapper -------------------------------------- */
+
+/* which: 0..3 potentials at level n (after a step: the newest level),
+   4..7 level n-1, 8..11 the scratch level, 12..14 J, 15 rho, 16 rho_prev,
+   17..19 E, 20..22 B, 23 x, 24 u, 25 x_old, 26 diag rows */
+double *orc_array(orc_sim *s, int which)
+{
+    if (which < 4) return s->pot[s->lcur][which];
+    if (which < 8) return s->pot[s->lprev][which - 4];
+    if (which < 12) return s->pot[s->lnext][which - 8];
+    if (which < 15) return s->J[which - 12];
+    if (which == 15) return s->rho;
+    if (which == 16) return s->rho_prev;
+    if (which < 20) return s->E[which - 17];
+    if (which < 23) return s->B[which - 20];
+    if (which == 23) return s->x;
+    if (which == 24) return s->u;
+    if (which == 25) return s->x_old;
+    if (which == 26) return s->diag;
+    return NULL;
+}
+
+unsigned char *orc_alive(orc_sim *s) { return s->alive; }
+
+long orc_info(orc_sim *s, int which)
+{
+    switch (which) {
+    case 0: return s->np;
+    case 1: return s->step;
+    case 2: return s->lost;
+    case 3: return s->ndiag;
+    case 4: return s->ncell;
+    default: return -1;
+    }
+}
+
+/* derived constants: dt, dtb, A, a1, a2, a4, a6, a8, gamma0, beta0, B0, ku,
+   mur-z beta0, beta1, mu0, eps0, c, e, me */
+void orc_constants(const orc_sim *s, double *out)
+{
+    out[0] = s->dt;
+    out[1] = s->dtb;
+    out[2] = s->A;
+    out[3] = s->a1;
+    out[4] = s->a2;
+    out[5] = s->a4;
+    out[6] = s->a6;
+    out[7] = s->a8;
+    out[8] = s->gamma0;
+    out[9] = s->beta0;
+    out[10] = s->B0;
+    out[11] = s->ku;
+    out[12] = s->mur[2][0];
+    out[13] = s->mur[2][1];
+    out[14] = ORC_MU0;
+    out[15] = ORC_EPS0;
+    out[16] = ORC_C;
+    out[17] = ORC_QE;
+    out[18] = ORC_ME;
+}

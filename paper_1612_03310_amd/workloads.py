@@ -1,0 +1,160 @@
+"""Seeded synthetic workloads: meshes and electron bunches in the bunch rest frame.
+
+This module only builds inputs.  It holds no step of the time-marching method
+and imports neither the GPU library nor the CPU oracle, so both can be fed
+from it.
+
+Recipe (the paper prints no performance workload, so the shapes follow its
+examples and the published configuration list):
+
+* the frame moves with the mean longitudinal velocity of the bunch in the
+  undulator, gamma0 = gamma / sqrt(1 + K^2 / 2) (section "Lorentz
+  Transformation");
+* the longitudinal cell is dz = lambda_u / (gamma0 * n_lambda), i.e.
+  n_lambda cells per rest-frame undulator period (= per rest-frame
+  radiation wavelength); the transverse cells are ``aspect`` times larger,
+  which keeps (dz/dx)^2 + (dz/dy)^2 < 1 as the NSFD scheme requires;
+* the mesh is centred on the undulator axis: x = y = z = 0 at its centre;
+* positions: independent Gaussian per axis with sigma = n_d / 8 cells,
+  truncated at 3 sigma by re-drawing (numpy PCG64, seeded);
+* lab energy gamma' = gamma * (1 + sigma_delta * N(0, 1)); momenta matched to
+  the undulator at the particle's lab phase, u'_x = -K cos(k_u z'),
+  u'_y = 0, u'_z from gamma', then boosted to the rest frame;
+* the undulator entrance z_e lies one cell behind the mesh, so every
+  particle starts inside the periodic field.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+# CODATA 2018
+C_LIGHT = 299792458.0
+Q_E = 1.602176634e-19
+M_E = 9.1093837015e-31
+
+BASE_SEED = 1612033100
+BUNCH_CHARGE = 29.5e-12  # C, the bunch charge of the paper's infrared example
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    n: Tuple[int, int, int]
+    d: Tuple[float, float, float]
+    origin: Tuple[float, float, float]
+    courant: float
+    nsfd_A: float
+    substeps: int
+    space_charge: int
+    bc: Tuple[int, int, int]
+    lambda_u: float
+    K: float
+    gamma_beam: float
+    z_e: float
+    x: np.ndarray  # (np, 3) rest-frame positions [m]
+    u: np.ndarray  # (np, 3) gamma * beta
+    q: float  # macro-particle charge [C]
+    m: float  # macro-particle mass [kg]
+    probe: Tuple[int, int, int]
+    kp: int
+    steps: int
+
+    @property
+    def ncell(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def np(self) -> int:
+        return int(self.x.shape[0])
+
+
+def _truncated_normal(rng: np.random.Generator, size: int, cut: float) -> np.ndarray:
+    out = rng.standard_normal(size)
+    bad = np.abs(out) > cut
+    while bad.any():
+        out[bad] = rng.standard_normal(int(bad.sum()))
+        bad = np.abs(out) > cut
+    return out
+
+
+def make_workload(name: str, n, n_particles: int, gamma: float, K: float, lambda_u: float,
+                  sigma_delta: float, seed: int, steps: int, *, n_lambda: int = 32,
+                  aspect: float = 4.0, courant: float = 0.9, sigma_cells=None,
+                  substeps: int = 1, space_charge: int = 1, bc=(0, 0, 0),
+                  charge: float = BUNCH_CHARGE, cut: float = 3.0) -> Workload:
+    n = tuple(int(v) for v in n)
+    gamma0 = gamma / math.sqrt(1.0 + K * K / 2.0)
+    beta0 = math.sqrt(1.0 - 1.0 / (gamma0 * gamma0))
+    dz = lambda_u / (gamma0 * n_lambda)
+    d = (aspect * dz, aspect * dz, dz)
+    origin = tuple(-(n[a] - 1) / 2.0 * d[a] for a in range(3))
+    z_e = origin[2] - d[2]
+    if sigma_cells is None:
+        sigma_cells = tuple(n[a] / 8.0 for a in range(3))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = np.empty((n_particles, 3))
+    for a in range(3):
+        x[:, a] = _truncated_normal(rng, n_particles, cut) * sigma_cells[a] * d[a]
+    ku = 2.0 * math.pi / lambda_u
+    gp = gamma * (1.0 + sigma_delta * rng.standard_normal(n_particles))
+    zlab = gamma0 * (x[:, 2] - z_e)  # lab undulator coordinate at t = 0
+    uxp = -K * np.cos(ku * zlab)
+    uzp = np.sqrt(gp * gp - 1.0 - uxp * uxp)
+    u = np.zeros((n_particles, 3))
+    u[:, 0] = uxp
+    u[:, 2] = gamma0 * (uzp - beta0 * gp)  # boost of the 4-momentum along z
+    q = -charge / n_particles
+    m = M_E * (charge / Q_E) / n_particles
+    kp = int(round(0.893 * n[2]))
+    kp = min(max(kp, 1), n[2] - 2)
+    probe = (n[0] // 2, n[1] // 2, kp)
+    return Workload(name=name, n=n, d=d, origin=origin, courant=courant, nsfd_A=-1.0,
+                    substeps=substeps, space_charge=space_charge, bc=tuple(bc),
+                    lambda_u=lambda_u, K=K, gamma_beam=gamma, z_e=z_e, x=x, u=u, q=q, m=m,
+                    probe=probe, kp=kp, steps=steps)
+
+
+# The published configurations, in order (index 0..4), plus the parity subcase.
+def config(index: int, *, n_particles: Optional[int] = None, steps: Optional[int] = None,
+           seed: Optional[int] = None) -> Workload:
+    s = BASE_SEED + index if seed is None else seed
+    if index in (0, 2):  # 32x32x64, 4096 particles, gamma 100, K 1.0, lambda_u 1.5 cm
+        return make_workload("tiny-32x32x64" if index == 0 else "precision-32x32x64",
+                             (32, 32, 64), n_particles or 4096, 100.0, 1.0, 0.015, 1e-4, s,
+                             steps or 200)
+    if index == 1:  # 128x128x512, 1M particles, 2000 steps
+        return make_workload("mid-128x128x512", (128, 128, 512), n_particles or 1 << 20, 100.0,
+                             1.0, 0.015, 1e-4, s, steps or 2000)
+    if index == 3:  # 256x256x2048, 16M particles, gamma 200, K 1.5, lambda_u 1.8 cm
+        return make_workload("large-256x256x2048", (256, 256, 2048), n_particles or 1 << 24,
+                             200.0, 1.5, 0.018, 2e-4, s, steps or 5000)
+    raise ValueError("config index must be 0..3 (4 is the batch, see batch_configs)")
+
+
+def mid_subcase(*, steps: int = 2000, n_particles: int = 65536) -> Workload:
+    """64x64x128 with 65536 particles: the oracle-checkable slice of the mid case."""
+    return make_workload("mid-subcase-64x64x128", (64, 64, 128), n_particles, 100.0, 1.0, 0.015,
+                         1e-4, BASE_SEED + 1, steps)
+
+
+def batch_configs(nsim: int = 64, *, steps: int = 1000, seed: Optional[int] = None,
+                  particle_scale: float = 1.0) -> List[Workload]:
+    """The undulator/beam parameter scan: uneven meshes and bunches, one per simulation."""
+    base = BASE_SEED + 4 if seed is None else seed
+    out = []
+    for s in range(nsim):
+        rng = np.random.Generator(np.random.PCG64(base + 1000 * s))
+        scale = rng.uniform(1.0, 3.0)
+        nx = 8 * int(round(4 * scale))
+        nz = 4 * nx
+        npart = 1024 * int(rng.integers(16, 257))
+        npart = max(256, int(npart * particle_scale))
+        gamma = float(rng.uniform(80.0, 250.0))
+        K = float(rng.uniform(0.8, 2.0))
+        out.append(make_workload("scan-%02d-%dx%dx%d" % (s, nx, nx, nz), (nx, nx, nz), npart,
+                                 gamma, K, 0.015, 1e-4, base + 1000 * s + 1, steps))
+    return out
