@@ -1,0 +1,289 @@
+"""Throughput of the boosted-frame FDTD/PIC step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--extra]
+
+Default workload: the 128x128x512 mesh with 1,048,576 macro-particles in
+double precision (the mid configuration).  One step is the whole hot path:
+potential update + Mur boundary, gather + undulator + Boris push, binning,
+charge-conserving deposition, and the double-precision diagnostics.  Inputs
+are synthetic (seeded generator) and resident in HBM before timing starts.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s + particle-pushes/s per step, FP32 vs FP64, % of HBM BW"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(kind, w, rs, nb_points=0):
+    """Algorithmic HBM bytes of one launch (each state array moved once)."""
+    ncell, npart = w.ncell, w.np
+    ncomp = 4 if w.space_charge else 3
+    if kind == "stencil":  # read psi^s, psi^{s-1}, source; write psi^{s+1}
+        return 4 * rs * ncomp * ncell
+    if kind == "push":  # key, offset, momentum in and out; start record out
+        return npart * (4 + 6 * rs + 4 + 6 * rs + 4 + 3 * rs)
+    if kind == "deposit":  # both positions in; J and rho written at every cell
+        return npart * (8 + 6 * rs) + ncell * 4 * rs
+    if kind == "scan":  # counts read twice, starts written
+        nkeys = 1
+        for a in range(3):
+            nkeys *= (w.n[a] + 7) // 8
+        return nkeys * 512 * 12
+    if kind == "scatter":  # key, id, offset, momentum moved
+        return 2 * npart * (8 + 6 * rs)
+    if kind == "boundary":  # six reads and one write per boundary point
+        return nb_points * 7 * rs
+    return 0
+
+
+def boundary_points(w):
+    nx, ny, nz = w.n
+    tot = 0
+    comps = 4 if w.space_charge else 3
+    for c in range(comps):
+        ext = [w.n[a] - (1 if c == a else 0) for a in range(3)]
+        tot += ext[0] * ext[1] * ext[2] - (ext[0] - 2) * (ext[1] - 2) * (ext[2] - 2)
+    return tot
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "mithra_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1612_03310_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kind, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when there is none or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.txt" % (kind, workload))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed_run(sim, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def measure(w, precision, steps, warmup, torch, native, tune=True, every=100):
+    """Graph-replayed timed region, then an event-timed region of the same
+    length for the per-kernel durations."""
+    t_setup = time.perf_counter()
+    sim = native.sim_from_workload(w, precision=precision, every=every)
+    if tune:
+        sim.tune(3)
+    sim.run(warmup)
+    sim.sync()
+    log("  set-up + warm-up %.1f s, tile %s" % (time.perf_counter() - t_setup,
+                                                sim.info()["stencil_tile"]))
+    dt = timed_run(sim, steps, torch)
+    sim.set_timing(True)
+    sim.get_timing(reset=True)
+    dt_ev = timed_run(sim, steps, torch)
+    ms, calls = sim.get_timing(reset=True)
+    sim.set_timing(False)
+    dg = sim.get_diag()
+    info = sim.info()
+    sim.close()
+    per_launch = {k: ms[k] / calls[k] for k in ms if calls[k] > 0}
+    return dt, dt_ev, per_launch, dg, info
+
+
+def cpu_baseline(w, steps):
+    """The oracle as it stands, single thread, on a bounded sample of the same
+    workload (whole steps of the full mesh and bunch; set-up excluded)."""
+    import oracle
+
+    sim = oracle.from_workload(w)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": w.ncell * steps / dt, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle", "particle_pushes_per_s": w.np * steps / dt,
+            "sample": "%d full steps of the %dx%dx%d mesh with %d particles (%.1f s, set-up "
+                      "excluded), plain C double precision, one thread"
+                      % (steps, w.n[0], w.n[1], w.n[2], w.np, dt)}
+
+
+def large_measurements(wl, kl, torch, native):
+    """The large configuration in float split form and the same shape in double."""
+    log("large configuration %s, %d particles, f32 split, %d steps" % (wl.n, wl.np, kl))
+    dtl, _, perl, dgl, _ = measure(wl, "f32", kl, 5, torch, native)
+    log("  %.3f ms/step" % (dtl * 1e3 / kl))
+    kl64 = max(10, kl // 4)
+    log("same shape in f64, %d steps" % kl64)
+    dtl64, _, perl64, _, _ = measure(wl, "f64", kl64, 3, torch, native)
+    log("  %.3f ms/step" % (dtl64 * 1e3 / kl64))
+    return {"fp32_large": {
+        "workload": "large-256x256x2048-16.8M-particles", "precision": "f32 split",
+        "steps": kl, "ms_per_step": round(dtl * 1e3 / kl, 4),
+        "cell_updates_per_s": wl.ncell * kl / dtl, "particle_pushes_per_s": wl.np * kl / dtl,
+        "kernels_ms": {k: round(v, 4) for k, v in perl.items()},
+        "stencil_frac_hbm": round(kernel_bytes("stencil", wl, 4) / (perl["stencil"] * 1e-3)
+                                  / 1e9 / HBM_PEAK_GBS, 4),
+        "push_frac_hbm": round(kernel_bytes("push", wl, 4) / (perl["push"] * 1e-3)
+                               / 1e9 / HBM_PEAK_GBS, 4),
+        "lost": int(dgl["lost"][-1]), "nonfinite": bool(dgl["nonfinite"].any()),
+        "fp64_same_shape_ms_per_step": round(dtl64 * 1e3 / kl64, 4),
+        "speedup_fp32_vs_fp64": round((dtl64 / kl64) / (dtl / kl), 3),
+    }}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--extra", action="store_true", help="also time the batched scan")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device-to-device 5 times (a kernel of known "
+                         "traffic, to scale hardware byte counters)")
+    ap.add_argument("--skip-large", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the z-slab sharding is a design note only); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1612_03310_amd import native
+    from paper_1612_03310_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    K, Wm = args.steps, args.warmup
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 5 x 1 GiB read + 1 GiB written")
+        del src, dst
+
+    # ---- headline: the mid configuration in double precision ----------------
+    w = W.config(1)
+    wname = "mid-128x128x512-1M-particles"
+    log("mid configuration %s, %d particles, f64, %d steps" % (w.n, w.np, K))
+    dt, dt_ev, per, dg, info = measure(w, "f64", K, Wm, torch, native)
+    ms_step = dt * 1e3 / K
+    value = w.ncell * K / dt
+    pushes = w.np * K * w.substeps / dt
+    log("  %.4f ms/step, %.3e cell-updates/s, %.3e pushes/s" % (ms_step, value, pushes))
+
+    rs = 8
+    nbp = boundary_points(w)
+    kernels = {}
+    for kind, t in per.items():
+        b = kernel_bytes(kind, w, rs, nbp)
+        kernels[kind] = {"ms": round(t, 5)}
+        if b:
+            kernels[kind]["algorithmic_GBs"] = round(b / (t * 1e-3) / 1e9, 1)
+            kernels[kind]["frac_hbm"] = round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    dom = max((k for k in per if kernel_bytes(k, w, rs, nbp)), key=lambda k: per[k])
+    dom_bytes = kernel_bytes(dom, w, rs, nbp)
+    achieved = dom_bytes / (per[dom] * 1e-3) / 1e9
+    traffic = traffic_from_profile(dom, "mid")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes_per_launch": dom_bytes,
+                "avg_launch_ms": round(per[dom], 5)}
+    step_bytes = sum(kernel_bytes(k, w, rs, nbp) for k in per)
+
+    # ---- the large float configuration and the same shape in double ---------
+    out_extra = {}
+    wl = None if args.skip_large else W.config(3)
+    kl = max(20, min(200, K // 10))
+    if wl is not None:
+        out_extra.update(large_measurements(wl, kl, torch, native))
+
+    if args.extra:
+        log("batched scan: 64 simulations")
+        ws = W.batch_configs(64, steps=100)
+        b = native.batch_from_workloads(ws, precision="f32", every=100)
+        b.tune(2)
+        b.run(8)
+        b.sync()
+        nb = 100
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(nb)
+        b.sync()
+        dtb = time.perf_counter() - t0
+        b.close()
+        seq = 0.0
+        for i, wi in enumerate(ws):
+            s = native.sim_from_workload(wi, precision="f32", every=100)
+            s.run(8)
+            s.sync()
+            seq += timed_run(s, nb, torch)
+            s.close()
+        cells = sum(x.ncell for x in ws)
+        out_extra["batch"] = {"simulations": 64, "steps": nb, "batched_s": round(dtb, 4),
+                              "sequential_s": round(seq, 4), "speedup": round(seq / dtb, 3),
+                              "cell_updates_per_s": cells * nb / dtb}
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline: oracle, %d steps of the mid configuration" % args.cpu_steps)
+        cpu = cpu_baseline(w, args.cpu_steps)
+        log("  %.3e cell-updates/s" % cpu["value"])
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": K,
+        "warmup": Wm, "ms_per_step": round(ms_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wname, "mesh": list(w.n), "particles": w.np,
+                   "precision": "f64", "courant": w.courant, "nsfd_A": info["nsfd_A"],
+                   "substeps": w.substeps, "space_charge": w.space_charge,
+                   "gamma": w.gamma_beam, "K": w.K, "lambda_u": w.lambda_u,
+                   "mesh_diag_every": 100, "stencil_tile": info["stencil_tile"]},
+        "particle_pushes_per_s": pushes,
+        "whole_step_algorithmic_GBs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "roofline": roofline,
+        "kernels": kernels,
+        "event_region_ms_per_step": round(dt_ev * 1e3 / K, 5),
+        "lost": int(dg["lost"][-1]) if len(dg) else 0,
+        "cpu_baseline": cpu,
+    }
+    line.update(out_extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

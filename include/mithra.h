@@ -1,0 +1,257 @@
+/*
+ * mithra.h -- C ABI of the MI355X (gfx950) implementation of the per-step
+ * particle-in-cell loop of MITHRA's full-wave FEL method (Fallahi, Yahaghi,
+ * Kaertner, arXiv:1612.03310), solved in the bunch rest frame:
+ *
+ *   1. potential update, eq. (updateEquation) (NSFD, eq. (NSFDtrick)),
+ *      for A_x, A_y, A_z and phi, with first-order Mur boundaries
+ *      (section "Boundary Truncation", first-order ABCs);
+ *   2. E and B at the cell vertices from the potentials (section "Field
+ *      Evaluation"), linear interpolation to each macro-particle
+ *      (eq. (fieldInterpolation)), plus the undulator field seen in the rest
+ *      frame (eqs. (undulatorField), (undulatorFieldRest), fringe field);
+ *   3. Boris push (eq. (BorisScheme)) with N sub-steps per field step;
+ *   4. charge and current deposition (section "Current Deposition",
+ *      eq. (currentIntegral)), charge-conserving;
+ *   5. double-precision diagnostics (charge, continuity, radiated power,
+ *      energies, field probe).
+ *
+ * Conventions used by every call:
+ *   - SI units in and out; the rest frame of the bunch (the frame moving with
+ *     beta0 = sqrt(1 - 1/gamma0^2), gamma0 = gamma / sqrt(1 + K^2/2),
+ *     section "Lorentz Transformation").
+ *   - Mesh arrays hold n[0]*n[1]*n[2] values, x fastest: element
+ *     (k*n[1] + j)*n[0] + i is grid point (i, j, k).  phi and rho sit on the
+ *     vertices origin + (i dx, j dy, k dz); A_l and J_l on the l-edges
+ *     (A_x at i+1/2, A_y at j+1/2, A_z at k+1/2).  Along its own axis an edge
+ *     grid has n-1 points on a Mur axis, so its last array layer is unused
+ *     and reads as zero.
+ *   - Time levels: after s completed steps the newest potentials are A^s,
+ *     phi^s (phi^s belongs to t = (s+1/2) dt, section "FDTD for Scalar
+ *     Potential"); particle positions belong to t = (s+1/2) dt and momenta
+ *     u = gamma*beta to t = s dt.  Input particles are taken as r^{1/2},
+ *     u^0; the potentials start at zero and J^0 = 0.
+ *   - Every call returns a mithra_status; nothing throws across the ABI.
+ *     On error mithra_last_error() gives a message naming the violated
+ *     condition (a thread-local string, valid until the next call on the
+ *     same thread).
+ *   - Host arrays belong to the caller.  The library copies them in and out
+ *     synchronously on the simulation's stream.  The library owns all device
+ *     memory of a simulation and frees it in mithra_destroy.
+ *   - A simulation and its stream must not be used from two threads at once.
+ */
+#ifndef MITHRA_H
+#define MITHRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mithra_sim mithra_sim;
+typedef struct mithra_batch mithra_batch;
+
+typedef enum {
+    MITHRA_OK = 0,
+    MITHRA_EINVAL = 1,   /* argument out of range, unstable mesh, bad size */
+    MITHRA_ENOMEM = 2,   /* device or host allocation failed */
+    MITHRA_EDEVICE = 3,  /* HIP runtime error, no gfx950 device */
+    MITHRA_ENUMERIC = 4, /* a non-finite momentum or diagnostic was produced */
+    MITHRA_ESTATE = 5    /* call not valid in the current state */
+} mithra_status;
+
+typedef enum {
+    MITHRA_F64 = 0,      /* fields, push and positions in double precision */
+    MITHRA_F32_SPLIT = 1 /* fields and push in float, positions as int32 cell
+                            + float offset, diagnostics in double */
+} mithra_precision;
+
+typedef enum {
+    MITHRA_BC_MUR1 = 0,    /* first-order Mur absorbing boundary */
+    MITHRA_BC_PERIODIC = 1 /* wrap-around (test configurations) */
+} mithra_bc;
+
+typedef enum {
+    MITHRA_AX = 0, MITHRA_AY = 1, MITHRA_AZ = 2, MITHRA_PHI = 3, /* newest level */
+    MITHRA_JX = 4, MITHRA_JY = 5, MITHRA_JZ = 6,                 /* J^s */
+    MITHRA_RHO = 7,                                              /* rho^{s+1/2} */
+    MITHRA_EX = 8, MITHRA_EY = 9, MITHRA_EZ = 10,                /* self field used by */
+    MITHRA_BX = 11, MITHRA_BY = 12, MITHRA_BZ = 13,              /* the last push */
+    MITHRA_AX_PREV = 14, MITHRA_AY_PREV = 15, MITHRA_AZ_PREV = 16,
+    MITHRA_PHI_PREV = 17,                                        /* level s-1 */
+    MITHRA_RHO_PREV = 18                                         /* rho^{s-1/2} */
+} mithra_field;
+
+/* MESH: the computational box in the rest frame (job-file section MESH). */
+typedef struct {
+    int32_t n[3];       /* grid points per axis, each >= 8 */
+    double d[3];        /* dx, dy, dz [m], > 0 */
+    double origin[3];   /* position of grid point (0,0,0) [m]; the undulator
+                           axis is x = y = 0 */
+    double courant;     /* nu = c dt / dz, in (0, 1] (dt = dz / c is nu = 1) */
+    double nsfd_A;      /* NSFD weight A of eq. (NSFDtrick); < 0 selects
+                           eq. (NSFDCoefficient) */
+    int32_t substeps;   /* N = dt / dt_b >= 1 particle sub-steps per field step */
+    int32_t space_charge; /* 0: phi == 0; 1: phi from eq. (HelmholtzF) */
+    int32_t bc[3];      /* mithra_bc per axis (both faces of the axis) */
+} mithra_mesh;
+
+/* UNDULATOR: static planar undulator, eq. (undulatorField), and the beam
+   energy that fixes the frame. */
+typedef struct {
+    double lambda_u;    /* lab period [m] > 0 */
+    double K;           /* undulator parameter >= 0; B0 = 2 pi m c K / (e lambda_u) */
+    double gamma_beam;  /* lab mean Lorentz factor; gamma0 = gamma / sqrt(1 + K^2/2) > 1 */
+    double z_entrance;  /* rest-frame z of the lab entrance z' = 0 at t = 0 [m];
+                           z' = gamma0 (z - z_entrance + beta0 c t) */
+} mithra_undulator;
+
+typedef struct {
+    int32_t probe[3];        /* vertex of the field probe */
+    int32_t power_plane_k;   /* z index of the plane of the power diagnostic */
+    int32_t mesh_diag_every; /* mesh-wide terms every M steps (M >= 1), 0 = never */
+    int32_t capacity;        /* rows kept in the device ring (>= 1) */
+} mithra_diag_cfg;
+
+/* One row per completed step s (fields at t = (s+1/2) dt). */
+typedef struct {
+    int64_t step;
+    double t;
+    double total_charge;        /* sum rho^{s+3/2} dV [C]                   (mesh term) */
+    double continuity_residual; /* max|rho^{s+3/2} - rho^{s+1/2} + dt div J^{s+1}|
+                                   / max|rho^{s+3/2}|                      (mesh term) */
+    double power;               /* sum (Ex By - Ey Bx) / mu0 dx dy over plane k [W] */
+    double field_energy;        /* sum (eps0 E^2/2 + B^2/(2 mu0)) dV [J]     (mesh term) */
+    double kinetic_energy;      /* sum (gamma - 1) m c^2 over live particles (mesh term) */
+    double probe_E[3], probe_B[3];
+    int64_t lost;               /* particles lost so far */
+    int32_t nonfinite;          /* a non-finite value was produced */
+    int32_t has_mesh_terms;     /* 1 if the mesh terms were computed this step */
+} mithra_diag_row;
+
+/* Derived constants and bookkeeping of a simulation. */
+typedef struct {
+    double dt, dtb;           /* field and particle time step [s] */
+    double nsfd_A;            /* NSFD weight in use */
+    double gamma0, beta0;     /* frame of the undulator-averaged bunch */
+    double B0, ku;            /* undulator peak field [T] and wave number [1/m] */
+    int64_t step;             /* completed steps */
+    int64_t np;               /* particles loaded (live + lost) */
+    int64_t device_bytes;     /* device memory held */
+    int32_t stencil_tile[3];  /* x, y columns per block and z planes per block */
+    int32_t precision;        /* mithra_precision */
+} mithra_info;
+
+/* ---- single simulation -------------------------------------------------- */
+
+/* Create a simulation.  Validates the mesh (the stability condition of the
+   NSFD scheme, section "Numerical Dispersion in FDTD": the largest value of
+   the right-hand side of eq. (NSFDDispersionCD) over the Brillouin zone must
+   not exceed 1) instead of adapting it; EINVAL names the violated condition.
+   stream: a hipStream_t; NULL makes the simulation create and own a
+   non-blocking stream (graph capture needs a stream other than the legacy
+   default stream).  EDEVICE if the current device is not gfx950. */
+mithra_status mithra_create(const mithra_mesh *mesh, const mithra_undulator *und,
+                            mithra_precision prec, void *stream, mithra_sim **out);
+
+/* Route device allocations through alloc(bytes, ctx) / release(ptr, ctx)
+   (e.g. a PyTorch caching allocator) for simulations created afterwards.
+   NULL functions restore hipMalloc/hipFree. */
+mithra_status mithra_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                                   void (*release)(void *ptr, void *ctx), void *ctx);
+
+/* Load np macro-particles (section "Electron Bunch Generation" produces them;
+   the caller supplies the result).  pos: [np][3] rest-frame positions [m] at
+   t = (s+1/2) dt; u: [np][3] gamma*beta at t = s dt; q_macro, m_macro: charge
+   [C] (signed) and mass [kg] of one macro-particle.  Particles whose cell is
+   outside [2, n-3] on an axis are counted as lost at once.  Deposits
+   rho^{s+1/2}; sets J^s = 0.  EINVAL for np < 0, non-finite input or m <= 0. */
+mithra_status mithra_set_particles(mithra_sim *sim, int64_t np, const double *pos,
+                                   const double *u, double q_macro, double m_macro);
+
+mithra_status mithra_config_diag(mithra_sim *sim, const mithra_diag_cfg *cfg);
+
+/* Enqueue nsteps steps on the simulation's stream (asynchronous).  ESTATE if
+   no particles were loaded (np = 0 is a valid load). */
+mithra_status mithra_run(mithra_sim *sim, int64_t nsteps);
+
+/* Wait for the stream; ENUMERIC if a non-finite momentum or diagnostic was
+   produced since the last sync (the particle is then counted as lost). */
+mithra_status mithra_sync(mithra_sim *sim);
+
+/* Copy a mesh quantity to host (n[0]*n[1]*n[2] doubles, layout above). */
+mithra_status mithra_get_field(mithra_sim *sim, mithra_field which, double *host);
+
+/* Overwrite a stored mesh quantity (potentials at the newest or previous
+   level, J, rho, rho_prev) from host doubles; E/B are derived and EINVAL. */
+mithra_status mithra_set_field(mithra_sim *sim, mithra_field which, const double *host);
+
+/* Copy the particles back in input order: pos [np][3], u [np][3] (SI), alive
+   [np] (1 live, 0 lost; may be NULL); np_alive may be NULL. */
+mithra_status mithra_get_particles(mithra_sim *sim, double *pos, double *u, uint8_t *alive,
+                                   int64_t *np_alive);
+
+/* Copy the unread diagnostic rows (oldest first, at most cap) and mark them
+   read; at most the last `capacity` rows are kept. */
+mithra_status mithra_get_diag(mithra_sim *sim, mithra_diag_row *rows, int64_t cap,
+                              int64_t *nrows);
+
+mithra_status mithra_get_info(mithra_sim *sim, mithra_info *info);
+
+/* Checkpoint: all potentials (3 levels), J, rho (2), particles, step and
+   lost count.  blob NULL: *bytes receives the size.  EINVAL if *bytes is too
+   small or the blob belongs to another mesh or precision. */
+mithra_status mithra_get_state(mithra_sim *sim, void *blob, size_t *bytes);
+mithra_status mithra_set_state(mithra_sim *sim, const void *blob, size_t bytes);
+
+/* Per-kernel timing with HIP events on the simulation's stream.  While on,
+   runs launch kernel by kernel (no graph replay).  ms[k], calls[k] for
+   k = 0 stencil, 1 boundary, 2 gather+push, 3 deposit, 4 scan, 5 scatter,
+   6 diagnostics; totals since the last reset (reset = 1 clears them). */
+mithra_status mithra_set_timing(mithra_sim *sim, int32_t on);
+mithra_status mithra_get_timing(mithra_sim *sim, double *ms, int64_t *calls, int32_t nkinds,
+                                int32_t reset);
+
+/* Autotuner: times trial_steps launches of the potential-update kernel for
+   each candidate tile shape (x and y columns per block, z planes per block)
+   and keeps the fastest.  The simulation state is unchanged. */
+mithra_status mithra_tune(mithra_sim *sim, int32_t trial_steps);
+
+const char *mithra_last_error(void);
+void mithra_destroy(mithra_sim *sim);
+
+/* ---- batch of independent simulations (parameter scans) ------------------
+   nsim simulations of different meshes, bunches and undulators advance in
+   lockstep: each step is one launch per kernel kind covering every
+   simulation, replayed from a captured hipGraph.  Indices are 0..nsim-1. */
+mithra_status mithra_batch_create(int32_t nsim, const mithra_mesh *meshes,
+                                  const mithra_undulator *unds, mithra_precision prec,
+                                  void *stream, mithra_batch **out);
+mithra_status mithra_batch_set_particles(mithra_batch *b, int32_t sim, int64_t np,
+                                         const double *pos, const double *u, double q_macro,
+                                         double m_macro);
+mithra_status mithra_batch_config_diag(mithra_batch *b, int32_t sim, const mithra_diag_cfg *cfg);
+/* Autotuner of the batch (see mithra_tune): one tile shape for all
+   simulations, chosen by timing the whole batched launch. */
+mithra_status mithra_batch_tune(mithra_batch *b, int32_t trial_steps);
+mithra_status mithra_batch_run(mithra_batch *b, int64_t nsteps);
+mithra_status mithra_batch_sync(mithra_batch *b);
+mithra_status mithra_batch_get_diag(mithra_batch *b, int32_t sim, mithra_diag_row *rows,
+                                    int64_t cap, int64_t *nrows);
+mithra_status mithra_batch_get_field(mithra_batch *b, int32_t sim, mithra_field which,
+                                     double *host);
+mithra_status mithra_batch_get_particles(mithra_batch *b, int32_t sim, double *pos, double *u,
+                                         uint8_t *alive, int64_t *np_alive);
+mithra_status mithra_batch_get_info(mithra_batch *b, int32_t sim, mithra_info *info);
+mithra_status mithra_batch_set_timing(mithra_batch *b, int32_t on);
+mithra_status mithra_batch_get_timing(mithra_batch *b, double *ms, int64_t *calls, int32_t nkinds,
+                                      int32_t reset);
+void mithra_batch_destroy(mithra_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MITHRA_H */

@@ -1,0 +1,1298 @@
+// gfx950 kernels of the boosted-frame FDTD/PIC step (arXiv:1612.03310,
+// chapter "Methodology").  Every kernel serves a whole batch of independent
+// simulations: a work table maps blocks to (simulation, tile).  The step
+// counter lives in device memory, so one captured step replays unchanged.
+//
+// Nothing here is a dense contraction: every kernel is bound by HBM or LDS
+// traffic, and none uses the matrix cores.
+#include <hip/hip_runtime.h>
+
+#include "mithra_internal.hpp"
+
+namespace mithra {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// Blocks are dispatched round-robin over the 8 XCDs of the chip, each with its
+// own L2.  Remap so that every XCD gets a contiguous range of logical blocks:
+// neighbouring tiles then share halo lines in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// index along an axis, wrapped on a periodic axis, clamped otherwise (clamped
+// values are only ever read by points that do not use them)
+__device__ __forceinline__ int axis_index(int v, int n, int periodic)
+{
+    if (v < 0) return periodic ? v + n : 0;
+    if (v >= n) return periodic ? v - n : n - 1;
+    return v;
+}
+
+__device__ __forceinline__ void sin_cos(float x, float *s, float *c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sin_cos(double x, double *s, double *c) { sincos(x, s, c); }
+
+__device__ __forceinline__ int comp_extent(const SimDev &S, int c, int a)
+{
+    return (c == a && !S.bc[a]) ? S.n[a] - 1 : S.n[a];
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive scan over a 256-thread block; returns the prefix, total in *tot
+__device__ __forceinline__ int block_excl_scan(int v, int *sh /*[4]*/, int *tot)
+{
+    const int incl = wave_incl_scan(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) sh[w] = incl;
+    __syncthreads();
+    int base = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) {
+        const int s = sh[i];
+        if (i < w) base += s;
+        all += s;
+    }
+    __syncthreads();
+    *tot = all;
+    return base + incl - v;
+}
+
+// fixed-order tree reduction of one double per thread over a 256-thread block
+__device__ __forceinline__ double block_sum(double v, double *sh /*[256]*/)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// vertex fields (section "Field Evaluation"): E and B at vertex (i, j, k) at
+// t_{s+1/2} from A^s, A^{s+1} and phi^s; the vertex value of the edge-sampled
+// A_l is the mean of its two edges along l.  B is the mean of the central
+// curls at the two levels; the sum over levels is taken first.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct FieldPtrs {
+    const R *A0[3];
+    const R *A1[3];
+    const R *phi;
+};
+
+template <typename R>
+__device__ __forceinline__ FieldPtrs<R> field_ptrs(const SimDev &S, const Arena &ar,
+                                                   long long lev0, long long lev1, int phi_lev)
+{
+    FieldPtrs<R> f;
+    for (int c = 0; c < 3; ++c) {
+        f.A0[c] = (const R *)ar.pot[lev0][c] + S.cell0;
+        f.A1[c] = (const R *)ar.pot[lev1][c] + S.cell0;
+    }
+    f.phi = (const R *)ar.pot[phi_lev][3] + S.cell0;
+    return f;
+}
+
+template <typename R>
+__device__ __forceinline__ void vertex_EB(const SimDev &S, const FieldPtrs<R> &f, int i, int j,
+                                          int k, R E[3], R B[3])
+{
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const long long sy = nx, sz = (long long)nx * ny;
+    const int im = axis_index(i - 1, nx, S.bc[0]), ip = axis_index(i + 1, nx, S.bc[0]);
+    const int jm = axis_index(j - 1, ny, S.bc[1]), jp = axis_index(j + 1, ny, S.bc[1]);
+    const int km = axis_index(k - 1, nz, S.bc[2]), kp = axis_index(k + 1, nz, S.bc[2]);
+    auto at = [&](int a, int b, int c) { return (long long)c * sz + (long long)b * sy + a; };
+    const R h = (R)0.5, q = (R)0.25;
+    const R idt = (R)S.inv_dt, i2x = (R)S.inv_2d[0], i2y = (R)S.inv_2d[1], i2z = (R)S.inv_2d[2];
+    const R *ph = f.phi;
+    // E = -dA/dt - grad phi
+    {
+        const long long p = at(i, j, k), px = at(im, j, k), py = at(i, jm, k), pz = at(i, j, km);
+        const R dAx = h * ((f.A1[0][p] + f.A1[0][px]) - (f.A0[0][p] + f.A0[0][px]));
+        const R dAy = h * ((f.A1[1][p] + f.A1[1][py]) - (f.A0[1][p] + f.A0[1][py]));
+        const R dAz = h * ((f.A1[2][p] + f.A1[2][pz]) - (f.A0[2][p] + f.A0[2][pz]));
+        E[0] = -dAx * idt - (ph[at(ip, j, k)] - ph[at(im, j, k)]) * i2x;
+        E[1] = -dAy * idt - (ph[at(i, jp, k)] - ph[at(i, jm, k)]) * i2y;
+        E[2] = -dAz * idt - (ph[at(i, j, kp)] - ph[at(i, j, km)]) * i2z;
+    }
+    // level sums of A at an edge sample
+    auto S0 = [&](int c, long long p) { return f.A0[c][p] + f.A1[c][p]; };
+    // Bx = dAz/dy - dAy/dz
+    {
+        const R dz_dy = (S0(2, at(i, jp, k)) + S0(2, at(i, jp, km))) -
+                        (S0(2, at(i, jm, k)) + S0(2, at(i, jm, km)));
+        const R dy_dz = (S0(1, at(i, j, kp)) + S0(1, at(i, jm, kp))) -
+                        (S0(1, at(i, j, km)) + S0(1, at(i, jm, km)));
+        B[0] = q * (dz_dy * i2y - dy_dz * i2z);
+    }
+    // By = dAx/dz - dAz/dx
+    {
+        const R dx_dz = (S0(0, at(i, j, kp)) + S0(0, at(im, j, kp))) -
+                        (S0(0, at(i, j, km)) + S0(0, at(im, j, km)));
+        const R dz_dx = (S0(2, at(ip, j, k)) + S0(2, at(ip, j, km))) -
+                        (S0(2, at(im, j, k)) + S0(2, at(im, j, km)));
+        B[1] = q * (dx_dz * i2z - dz_dx * i2x);
+    }
+    // Bz = dAy/dx - dAx/dy
+    {
+        const R dy_dx = (S0(1, at(ip, j, k)) + S0(1, at(ip, jm, k))) -
+                        (S0(1, at(im, j, k)) + S0(1, at(im, jm, k)));
+        const R dx_dy = (S0(0, at(i, jp, k)) + S0(0, at(im, jp, k))) -
+                        (S0(0, at(i, jm, k)) + S0(0, at(im, jm, k)));
+        B[2] = q * (dy_dx * i2x - dx_dy * i2y);
+    }
+}
+
+// vertices where the E, B formulas are evaluated: [1, n-2] on a Mur axis
+__device__ __forceinline__ bool vertex_valid(const SimDev &S, int i, int j, int k)
+{
+    const int v[3] = {i, j, k};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (v[a] < 0 || v[a] >= S.n[a]) return false;
+        if (!S.bc[a] && (v[a] < 1 || v[a] > S.n[a] - 2)) return false;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// 1. potential update, eq. (updateEquation), all four components.
+//    Each thread owns an (x, y) column and marches z through a block's chunk
+//    of planes.  Plane k+1 of psi^s is staged with a one-cell halo in a
+//    three-slot LDS ring (one barrier per plane: each iteration reads only the
+//    plane it staged, older planes stay in registers); loads run one plane
+//    ahead through registers so that a block keeps two planes in flight.  With
+//      T_k = ax (P_{i+1} + P_{i-1}) + ay (P_{j+1} + P_{j-1}) at plane k,
+//    the update is
+//      psi^{s+1} = -psi^{s-1} + a1 P + A (T_{k-1} + T_{k+1}) + (1 - 2A) T_k
+//                  + az (P_{k+1} + P_{k-1}) + src S,
+//    an exact regrouping of the z-averaged transverse neighbours.
+// ---------------------------------------------------------------------------
+
+template <typename R, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ sims,
+                                                     const int4 *__restrict__ items, Arena ar,
+                                                     int KZ)
+{
+    const int4 it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const SimDev &S = sims[it.x];
+    const int comp = blockIdx.y;
+    if (comp == 3 && !S.sc) return;
+    const long long step = *ar.d_step;
+    const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+    const long long sxy = (long long)nx * ny;
+    const R *__restrict__ P = (const R *)ar.pot[step % 3][comp] + S.cell0;
+    const R *__restrict__ Q = (const R *)ar.pot[(step + 2) % 3][comp] + S.cell0;
+    R *__restrict__ Rn = (R *)ar.pot[(step + 1) % 3][comp] + S.cell0;
+    const R *__restrict__ Src =
+        (comp < 3 ? (const R *)ar.J[comp] : (const R *)ar.rho[step & 1]) + S.cell0;
+
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = S.bc[a] ? 0 : 1;
+        hi[a] = S.bc[a] ? S.n[a] - 1 : comp_extent(S, comp, a) - 2;
+    }
+    const int k0 = max(it.w * KZ, lo[2]);
+    const int k1 = min(it.w * KZ + KZ - 1, hi[2]);
+    if (k0 > k1) return;  // uniform over the block
+
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int i = it.y * TX + tx, j = it.z * TY + ty;
+    const bool act = i >= lo[0] && i <= hi[0] && j >= lo[1] && j <= hi[1];
+
+    const R a1 = (R)S.a1, ax = (R)S.ax, ay = (R)S.ay, az = (R)S.az, A = (R)S.A;
+    const R oma = (R)(1.0 - 2.0 * S.A);
+    const R src = (R)(comp < 3 ? S.srcA : S.srcPhi);
+
+    __shared__ R sP[3][TY + 2][TX + 2];
+    // each thread stages at most NE elements of a haloed plane; their plane
+    // offsets do not depend on k
+    constexpr int NT = TX * TY, NPL = (TX + 2) * (TY + 2), NE = (NPL + NT - 1) / NT;
+    int eoff[NE], elds[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        const int e = threadIdx.x + m * NT;
+        const int lx = e % (TX + 2), ly = e / (TX + 2);
+        const int gi = axis_index(it.y * TX - 1 + lx, nx, S.bc[0]);
+        const int gj = axis_index(it.z * TY - 1 + ly, ny, S.bc[1]);
+        eoff[m] = gj * nx + gi;
+        elds[m] = e < NPL ? e : -1;
+    }
+    R pv[NE];
+    auto fetch = [&](int kk) {  // global -> registers
+        const R *base = P + (long long)axis_index(kk, nz, S.bc[2]) * sxy;
+#pragma unroll
+        for (int m = 0; m < NE; ++m)
+            if (elds[m] >= 0) pv[m] = base[eoff[m]];
+    };
+    auto commit = [&](int slot) {  // registers -> LDS
+#pragma unroll
+        for (int m = 0; m < NE; ++m)
+            if (elds[m] >= 0) (&sP[slot][0][0])[elds[m]] = pv[m];
+    };
+    auto trans = [&](int slot) {
+        return ax * (sP[slot][ty + 1][tx + 2] + sP[slot][ty + 1][tx]) +
+               ay * (sP[slot][ty + 2][tx + 1] + sP[slot][ty][tx + 1]);
+    };
+
+    // software pipeline: while plane k is computed, plane k+2 of psi^s and
+    // psi^{s-1}, S at plane k+1 are already in flight
+    const long long col = (long long)j * nx + i;
+    fetch(k0 - 1);
+    commit(0);
+    fetch(k0);
+    commit(1);
+    fetch(k0 + 1);
+    R qn = 0, sn = 0;
+    if (act) {
+        qn = __builtin_nontemporal_load(&Q[(long long)k0 * sxy + col]);
+        sn = __builtin_nontemporal_load(&Src[(long long)k0 * sxy + col]);
+    }
+    __syncthreads();
+    R Tm = trans(0), Tc = trans(1);
+    R Pm = sP[0][ty + 1][tx + 1], Pc = sP[1][ty + 1][tx + 1];
+    int slot = 2;
+    for (int k = k0; k <= k1; ++k) {
+        // the slot refilled here was last read two iterations ago, before the
+        // previous barrier
+        commit(slot);
+        const R q = qn, s = sn;
+        if (k < k1) {
+            fetch(k + 2);
+            if (act) {
+                qn = __builtin_nontemporal_load(&Q[(long long)(k + 1) * sxy + col]);
+                sn = __builtin_nontemporal_load(&Src[(long long)(k + 1) * sxy + col]);
+            }
+        }
+        __syncthreads();
+        const R Pp = sP[slot][ty + 1][tx + 1];
+        const R Tp = trans(slot);
+        if (act)
+            __builtin_nontemporal_store(
+                -q + a1 * Pc + A * (Tm + Tp) + oma * Tc + az * (Pp + Pm) + src * s,
+                &Rn[(long long)k * sxy + col]);
+        Pm = Pc;
+        Pc = Pp;
+        Tm = Tc;
+        Tc = Tp;
+        slot = slot == 2 ? 0 : slot + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. first-order Mur on the outer layer of every component grid (section
+//    "Boundary Truncation").  A point on several faces uses the rule of its
+//    highest-priority axis (z > y > x); its inward neighbour along that axis
+//    lies on one face fewer.  Each thread evaluates that chain down to an
+//    interior point, so faces, edges and corners need no ordering between
+//    threads: only interior psi^{s+1} values are read.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_boundary(const SimDev *__restrict__ sims,
+                                                     const BSeg *__restrict__ segs, int nseg,
+                                                     long long total, Arena ar)
+{
+    const long long step = *ar.d_step;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < total;
+         t += (long long)gridDim.x * BLOCK) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segs[mid].start <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BSeg g = segs[lo];
+        const SimDev &S = sims[g.sim];
+        const int c = g.comp;
+        const long long r = t - g.start;
+        int ext[3], ilo[3], ihi[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ext[a] = comp_extent(S, c, a);
+            ilo[a] = S.bc[a] ? 0 : 1;
+            ihi[a] = S.bc[a] ? ext[a] - 1 : ext[a] - 2;
+        }
+        int v[3];
+        if (g.group == 2) {
+            const long long fa = (long long)ext[0] * ext[1];
+            const int face = (int)(r / fa), rem = (int)(r % fa);
+            v[0] = rem % ext[0];
+            v[1] = rem / ext[0];
+            v[2] = face ? ext[2] - 1 : 0;
+        } else if (g.group == 1) {
+            const int nzi = ihi[2] - ilo[2] + 1;
+            const long long fa = (long long)ext[0] * nzi;
+            const int face = (int)(r / fa), rem = (int)(r % fa);
+            v[0] = rem % ext[0];
+            v[2] = ilo[2] + rem / ext[0];
+            v[1] = face ? ext[1] - 1 : 0;
+        } else {
+            const int nyi = ihi[1] - ilo[1] + 1, nzi = ihi[2] - ilo[2] + 1;
+            const long long fa = (long long)nyi * nzi;
+            const int face = (int)(r / fa), rem = (int)(r % fa);
+            v[1] = ilo[1] + rem % nyi;
+            v[2] = ilo[2] + rem / nyi;
+            v[0] = face ? ext[0] - 1 : 0;
+        }
+        const R *P = (const R *)ar.pot[step % 3][c] + S.cell0;
+        const R *Q = (const R *)ar.pot[(step + 2) % 3][c] + S.cell0;
+        R *Rn = (R *)ar.pot[(step + 1) % 3][c] + S.cell0;
+        const long long sy = S.n[0], sz = (long long)S.n[0] * S.n[1];
+        long long pts[4];
+        int axs[3];
+        int len = 0;
+        int cur[3] = {v[0], v[1], v[2]};
+        for (;;) {
+            int top = -1;
+            for (int a = 2; a >= 0; --a)
+                if (!S.bc[a] && (cur[a] == 0 || cur[a] == ext[a] - 1)) {
+                    top = a;
+                    break;
+                }
+            if (top < 0) break;
+            pts[len] = cur[2] * sz + cur[1] * sy + cur[0];
+            axs[len] = top;
+            ++len;
+            cur[top] += cur[top] == 0 ? 1 : -1;
+        }
+        pts[len] = cur[2] * sz + cur[1] * sy + cur[0];
+        R val = Rn[pts[len]];
+        for (int m = len - 1; m >= 0; --m) {
+            const R b0 = (R)S.murb0[axs[m]], b1 = (R)S.murb1[axs[m]];
+            const long long p = pts[m], q = pts[m + 1];
+            val = b0 * Q[p] + b1 * P[p] - Q[q] + b1 * P[q] + b0 * val;
+        }
+        Rn[pts[0]] = val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. gather + undulator + Boris push, one block per 8^3-cell tile.
+//    The tile's particles are contiguous (sorted by cell at the end of the
+//    previous step).  E and B at the tile's 9^3 vertices are computed once
+//    into LDS (pre-scaled to Boris kicks), then every particle interpolates
+//    linearly (eq. (fieldInterpolation)), adds the rest-frame undulator field
+//    at each sub-step, and is pushed (eq. (BorisScheme)).  Positions are kept
+//    as an int32 cell (the bin key) plus an offset in [0, 1) per axis.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int tile_key(const SimDev &S, int ci, int cj, int ck)
+{
+    const int t = ((ck >> 3) * S.nt[1] + (cj >> 3)) * S.nt[0] + (ci >> 3);
+    return t * TILE_CELLS + (((ck & 7) * TILE + (cj & 7)) * TILE + (ci & 7));
+}
+
+// rest-frame undulator field (eqs. (undulatorField), (undulatorFieldRest) with
+// E_x = -g0 b0 c B'_y, and the fringe field for z' < 0), scaled to kicks.
+// ph_cell: k_u z' at the particle's cell corner, in double (it reaches
+// hundreds of radians); the in-cell part is added in working precision.
+template <typename R>
+__device__ __forceinline__ void undulator_kick(const SimDev &S, double ph_cell, R fz, double y,
+                                               R &Ex, R &By, R &Bz)
+{
+    const double kzc = S.kz_cell;
+    const double full = ph_cell + kzc * (double)fz;
+    const R kuy = (R)(S.ku * y);
+    const R ch = cosh(kuy), sh = sinh(kuy);
+    if (full >= 0.0) {
+        const double twopi = 6.283185307179586476925286766559;
+        const double red = ph_cell - twopi * floor(ph_cell / twopi);
+        const R ph = (R)red + (R)kzc * fz;
+        R sn, cs;
+        sin_cos(ph, &sn, &cs);
+        Ex = (R)S.EuK * ch * sn;
+        By = (R)S.BuyK * ch * sn;
+        Bz = (R)S.BuzK * sh * cs;
+    } else {
+        const R s = (R)full;
+        const R g = exp(-s * s * (R)0.5);
+        Ex = (R)S.EuK * ch * s * g;
+        By = (R)S.BuyK * ch * s * g;
+        Bz = (R)S.BuzK * sh * g;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
+                                                 const int2 *__restrict__ items, Arena ar)
+{
+    const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const SimDev &S = sims[it.x];
+    const long long step = *ar.d_step;
+    const int par = (int)(step & 1);
+    const int *__restrict__ offs = ar.offs[par];
+    if (it.y == 0 && threadIdx.x == 0) {
+        // particles lost in earlier steps stay in the lost bucket
+        const long long g = S.key0 + S.nkeys;
+        const int n_lost = offs[g + 1] - offs[g];
+        if (n_lost) atomicAdd(&ar.counts[g], n_lost);
+    }
+    const long long g0 = S.key0 + (long long)it.y * TILE_CELLS;
+    const int p_lo = offs[g0], p_hi = offs[g0 + TILE_CELLS];
+    if (p_lo == p_hi) return;
+
+    const int t = it.y;
+    const int L0 = (t % S.nt[0]) * TILE, L1 = ((t / S.nt[0]) % S.nt[1]) * TILE,
+              L2 = (t / (S.nt[0] * S.nt[1])) * TILE;
+
+    // E and B at the tile's 9^3 vertices.  The potentials of the box
+    // [L-1, L+9]^3 are staged in LDS one component at a time (both levels as
+    // their difference, for E = -dA/dt, and their sum, for the mean curl),
+    // then phi; each thread accumulates its vertices' E and B in registers.
+    constexpr int NV = TILE_VERT * TILE_VERT * TILE_VERT;  // 729
+    constexpr int SG = TILE_VERT + 2;                      // 11
+    constexpr int NS = SG * SG * SG;                       // 1331
+    constexpr int VPT = (NV + BLOCK - 1) / BLOCK;          // 3
+    // the staging buffers (2 x NS) and the field table (6 x NV) share LDS
+    constexpr int NSM = 6 * NV > 2 * NS ? 6 * NV : 2 * NS;
+    __shared__ R smem[NSM];
+    R *sD = smem, *sS = smem + NS;
+    R (*sF)[NV] = reinterpret_cast<R (*)[NV]>(smem);
+    {
+        const R kE = (R)S.kE, kB = (R)S.kB;
+        const R hidt = (R)(0.5 * S.inv_dt);
+        const R q2x = (R)(0.25 * S.inv_2d[0]), q2y = (R)(0.25 * S.inv_2d[1]),
+                q2z = (R)(0.25 * S.inv_2d[2]);
+        const R i2x = (R)S.inv_2d[0], i2y = (R)S.inv_2d[1], i2z = (R)S.inv_2d[2];
+        const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+        constexpr int OX = 1, OY = SG, OZ = SG * SG;
+        R E[VPT][3], B[VPT][3];
+        int sp[VPT];
+        bool val[VPT];
+#pragma unroll
+        for (int m = 0; m < VPT; ++m) {
+            const int v = threadIdx.x + m * BLOCK;
+            const int vi = v % TILE_VERT, vj = (v / TILE_VERT) % TILE_VERT,
+                      vk = v / (TILE_VERT * TILE_VERT);
+            val[m] = v < NV && vertex_valid(S, L0 + vi, L1 + vj, L2 + vk);
+            sp[m] = ((vk + 1) * SG + (vj + 1)) * SG + (vi + 1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) E[m][a] = B[m][a] = (R)0;
+        }
+        auto stage_index = [&](int e) {
+            const int r0 = e % SG, r1 = (e / SG) % SG, r2 = e / (SG * SG);
+            const int gi = axis_index(L0 - 1 + r0, nx, S.bc[0]);
+            const int gj = axis_index(L1 - 1 + r1, ny, S.bc[1]);
+            const int gk = axis_index(L2 - 1 + r2, nz, S.bc[2]);
+            return ((long long)gk * ny + gj) * nx + gi;
+        };
+        const long long l0 = step % 3, l1 = (step + 1) % 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R *A0 = (const R *)ar.pot[l0][c] + S.cell0;
+            const R *A1 = (const R *)ar.pot[l1][c] + S.cell0;
+            for (int e = threadIdx.x; e < NS; e += BLOCK) {
+                const long long g = stage_index(e);
+                const R a0 = A0[g], a1 = A1[g];
+                sD[e] = a1 - a0;
+                sS[e] = a0 + a1;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < VPT; ++m) {
+                if (!val[m]) continue;
+                const int p = sp[m];
+                if (c == 0) {
+                    E[m][0] -= hidt * (sD[p] + sD[p - OX]);
+                    B[m][1] += q2z * ((sS[p + OZ] + sS[p + OZ - OX]) - (sS[p - OZ] + sS[p - OZ - OX]));
+                    B[m][2] -= q2y * ((sS[p + OY] + sS[p + OY - OX]) - (sS[p - OY] + sS[p - OY - OX]));
+                } else if (c == 1) {
+                    E[m][1] -= hidt * (sD[p] + sD[p - OY]);
+                    B[m][2] += q2x * ((sS[p + OX] + sS[p + OX - OY]) - (sS[p - OX] + sS[p - OX - OY]));
+                    B[m][0] -= q2z * ((sS[p + OZ] + sS[p + OZ - OY]) - (sS[p - OZ] + sS[p - OZ - OY]));
+                } else {
+                    E[m][2] -= hidt * (sD[p] + sD[p - OZ]);
+                    B[m][0] += q2y * ((sS[p + OY] + sS[p + OY - OZ]) - (sS[p - OY] + sS[p - OY - OZ]));
+                    B[m][1] -= q2x * ((sS[p + OX] + sS[p + OX - OZ]) - (sS[p - OX] + sS[p - OX - OZ]));
+                }
+            }
+            __syncthreads();
+        }
+        {
+            const R *ph = (const R *)ar.pot[l0][3] + S.cell0;
+            for (int e = threadIdx.x; e < NS; e += BLOCK) sS[e] = ph[stage_index(e)];
+            __syncthreads();
+        }
+#pragma unroll
+        for (int m = 0; m < VPT; ++m) {
+            const int p = sp[m];
+            if (val[m]) {
+                E[m][0] -= (sS[p + OX] - sS[p - OX]) * i2x;
+                E[m][1] -= (sS[p + OY] - sS[p - OY]) * i2y;
+                E[m][2] -= (sS[p + OZ] - sS[p - OZ]) * i2z;
+            }
+        }
+        __syncthreads();  // the field table overwrites the staging buffers
+#pragma unroll
+        for (int m = 0; m < VPT; ++m) {
+            const int v = threadIdx.x + m * BLOCK;
+            if (v >= NV) continue;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                sF[a][v] = kE * E[m][a];
+                sF[3 + a][v] = kB * B[m][a];
+            }
+        }
+    }
+    __syncthreads();
+
+    int *__restrict__ key = ar.key[par];
+    R *__restrict__ o0 = (R *)ar.off[par][0];
+    R *__restrict__ o1 = (R *)ar.off[par][1];
+    R *__restrict__ o2 = (R *)ar.off[par][2];
+    R *__restrict__ u0 = (R *)ar.u[par][0];
+    R *__restrict__ u1 = (R *)ar.u[par][1];
+    R *__restrict__ u2 = (R *)ar.u[par][2];
+    R *__restrict__ q0 = (R *)ar.ooff[0];
+    R *__restrict__ q1 = (R *)ar.ooff[1];
+    R *__restrict__ q2 = (R *)ar.ooff[2];
+    const bool want_ke = S.mesh_every > 0 && ((step + 1) % S.mesh_every) == 0;
+    const double t0 = ((double)step + 0.5) * S.dt;
+
+    for (int p = p_lo + threadIdx.x; p < p_hi; p += BLOCK) {
+        const int gk = key[p];
+        const int lkey = (gk - (int)S.key0) & (TILE_CELLS - 1);
+        const int li = lkey & 7, lj = (lkey >> 3) & 7, lk = lkey >> 6;
+        int c[3] = {L0 + li, L1 + lj, L2 + lk};
+        R f[3] = {o0[p], o1[p], o2[p]};
+        R u[3] = {u0[p], u1[p], u2[p]};
+        q0[p] = f[0];
+        q1[p] = f[1];
+        q2[p] = f[2];
+        // linear interpolation of the 6 kick-scaled components from LDS
+        R F[6];
+        {
+            const int b = (lk * TILE_VERT + lj) * TILE_VERT + li;
+            const R wx1 = f[0], wx0 = (R)1 - f[0], wy1 = f[1], wy0 = (R)1 - f[1];
+            const R wz1 = f[2], wz0 = (R)1 - f[2];
+            constexpr int DY = TILE_VERT, DZ = TILE_VERT * TILE_VERT;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                const R *g = sF[a];
+                const R x00 = wx0 * g[b] + wx1 * g[b + 1];
+                const R x10 = wx0 * g[b + DY] + wx1 * g[b + DY + 1];
+                const R x01 = wx0 * g[b + DZ] + wx1 * g[b + DZ + 1];
+                const R x11 = wx0 * g[b + DZ + DY] + wx1 * g[b + DZ + DY + 1];
+                F[a] = wz0 * (wy0 * x00 + wy1 * x10) + wz1 * (wy0 * x01 + wy1 * x11);
+            }
+        }
+        const double ph_cell0 = S.kz_cell * (double)c[2] + S.phase_off;
+        for (int sub = 0; sub < S.nsub; ++sub) {
+            const double ts = t0 + sub * S.dtb;
+            const double y = S.origin[1] + ((double)c[1] + (double)f[1]) * S.d[1];
+            R Eu, Buy, Buz;
+            undulator_kick<R>(S, ph_cell0 + S.phase_rate * ts, f[2], y, Eu, Buy, Buz);
+            const R e0 = F[0] + Eu, e1 = F[1], e2 = F[2];
+            const R b0 = F[3], b1 = F[4] + Buy, b2 = F[5] + Buz;
+            // Boris: half kick, rotation, half kick
+            const R t1x = u[0] + e0, t1y = u[1] + e1, t1z = u[2] + e2;
+            const R ig = (R)1 / sqrt((R)1 + t1x * t1x + t1y * t1y + t1z * t1z);
+            const R bx = b0 * ig, by = b1 * ig, bz = b2 * ig;
+            const R t2x = t1x + (t1y * bz - t1z * by);
+            const R t2y = t1y + (t1z * bx - t1x * bz);
+            const R t2z = t1z + (t1x * by - t1y * bx);
+            const R fac = (R)2 / ((R)1 + bx * bx + by * by + bz * bz);
+            const R wx = fac * bx, wy = fac * by, wz = fac * bz;
+            u[0] = t1x + (t2y * wz - t2z * wy) + e0;
+            u[1] = t1y + (t2z * wx - t2x * wz) + e1;
+            u[2] = t1z + (t2x * wy - t2y * wx) + e2;
+            const R ginv = (R)1 / sqrt((R)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            f[0] += (R)S.cdtb_d[0] * u[0] * ginv;
+            f[1] += (R)S.cdtb_d[1] * u[1] * ginv;
+            f[2] += (R)S.cdtb_d[2] * u[2] * ginv;
+        }
+        bool ok = isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(f[0]) &&
+                  isfinite(f[1]) && isfinite(f[2]);
+        int nk = (int)S.nkeys;
+        // record of the start cell for the deposit: x inside the tile and the
+        // cell move per axis (-1, 0, 1; a move is below one cell per step)
+        int move = li;
+        if (ok) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R fl = floor(f[a]);
+                c[a] += (int)fl;
+                f[a] -= fl;
+                move |= ((int)fl + 1) << (3 + 2 * a);
+                if (c[a] < 2 || c[a] > S.n[a] - 3) ok = false;  // lost
+            }
+            if (ok) nk = tile_key(S, c[0], c[1], c[2]);
+        } else {
+            atomicOr(&ar.flags[it.x], 1);
+        }
+        ar.okey[p] = move;
+        const int ngk = (int)S.key0 + nk;
+        key[p] = ngk;
+        o0[p] = f[0];
+        o1[p] = f[1];
+        o2[p] = f[2];
+        u0[p] = u[0];
+        u1[p] = u[1];
+        u2[p] = u[2];
+        atomicAdd(&ar.counts[ngk], 1);
+        if (!ok || want_ke) {
+            const int pid = ar.id[par][p];
+            double ke = 0.0;
+            if (ok)
+                ke = sqrt(1.0 + (double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]) -
+                     1.0;
+            ar.ke[S.part0 + pid] = ke;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. charge and current deposition (section "Current Deposition",
+//    eq. (currentIntegral)) with Esirkepov's decomposition of the change of
+//    the linear-weight density, which makes the discrete continuity equation
+//    exact.  One block owns the 8^3 vertices of a tile and visits every
+//    particle whose start cell lies in [L-2, L+8] per axis (those are all the
+//    particles that can reach the tile), adding only what lands on its own
+//    vertices.  Sums are fixed point in LDS: each term t (|t| <= 1) is scaled
+//    by 2^S, split into its nearest integer hi and the remainder scaled by
+//    2^LO_BITS, and both parts go to 64-bit integer accumulators.  Integer
+//    addition is associative, so the result does not depend on the order of
+//    the atomics; the resolution is 2^-(S + LO_BITS) of one particle's weight.
+//    The flush converts once and writes every vertex, zeros included.
+// ---------------------------------------------------------------------------
+
+// |lo| <= 2^31 per term and at most 2^31 terms per vertex: no overflow
+constexpr int LO_BITS = 32;
+
+// add t * 2^S as a (hi, lo) fixed-point pair; the float path keeps hi only
+// (its terms carry 24 bits, far below the 2^-S resolution of hi)
+template <typename R>
+__device__ __forceinline__ void fx_add(unsigned long long *hi, unsigned long long *lo, double t,
+                                       double scale)
+{
+    const double v = t * scale;
+    const double h = rint(v);
+    const long long lh = (long long)h;
+    if (lh) atomicAdd(hi, (unsigned long long)lh);
+    if (sizeof(R) == 8) {
+        const long long ll = __double2ll_rn((v - h) * 0x1p32);
+        if (ll) atomicAdd(lo, (unsigned long long)ll);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ double fx_value(unsigned long long hi, unsigned long long lo)
+{
+    if (sizeof(R) != 8) return (double)(long long)hi;
+    return (double)(long long)hi + (double)(long long)lo * 0x1p-32;
+}
+
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ sims,
+                                                    const int2 *__restrict__ items, Arena ar,
+                                                    int init)
+{
+    const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const SimDev &S = sims[it.x];
+    const long long step = *ar.d_step;
+    const int par = (int)(step & 1);
+    const int *__restrict__ offs = ar.offs[par];
+    const int t = it.y;
+    const int tX = t % S.nt[0], tY = (t / S.nt[0]) % S.nt[1], tZ = t / (S.nt[0] * S.nt[1]);
+    const int L[3] = {tX * TILE, tY * TILE, tZ * TILE};
+
+    constexpr int NLO = sizeof(R) == 8 ? TILE_CELLS : 1;  // low words: double path only
+    __shared__ unsigned long long acc[4][TILE_CELLS], acl[4][NLO];
+    __shared__ int rstart[384], rlen[384], rpre[384];
+    __shared__ int wsum[BLOCK / 64];
+    __shared__ int any;
+    for (int e = threadIdx.x; e < 4 * TILE_CELLS; e += BLOCK) (&acc[0][0])[e] = 0ull;
+    for (int e = threadIdx.x; e < 4 * NLO; e += BLOCK) (&acl[0][0])[e] = 0ull;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+
+    // skip the particle pass when the 27 surrounding tiles hold no particle
+    if (threadIdx.x < 27) {
+        const int dx = threadIdx.x % 3 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x / 9 - 1;
+        const int a = tX + dx, b = tY + dy, cc = tZ + dz;
+        if (a >= 0 && a < S.nt[0] && b >= 0 && b < S.nt[1] && cc >= 0 && cc < S.nt[2]) {
+            const long long g = S.key0 + (long long)((cc * S.nt[1] + b) * S.nt[0] + a) * TILE_CELLS;
+            if (offs[g + TILE_CELLS] != offs[g]) atomicOr(&any, 1);
+        }
+    }
+    __syncthreads();
+
+    if (any) {
+        // particle ranges: rows of start cells (y, z) in [L-2, L+8], x-range
+        // [L-2, L+8] split at tile boundaries (at most 3 contiguous key ranges)
+        int mylen[2] = {0, 0};
+        for (int h = 0; h < 2; ++h) {
+            const int e = threadIdx.x * 2 + h;  // 121 rows x 3 pieces = 363 entries
+            int st = 0, ln = 0;
+            if (e < 363) {
+                const int row = e / 3, piece = e % 3;
+                const int cy = L[1] - 2 + row % 11, cz = L[2] - 2 + row / 11;
+                const int xa = max(L[0] - 2, 0), xb = min(L[0] + 8, S.n[0] - 1);
+                const int tx = tX - 1 + piece;
+                const int pa = max(xa, tx * TILE), pb = min(xb, tx * TILE + TILE - 1);
+                if (cy >= 0 && cy < S.n[1] && cz >= 0 && cz < S.n[2] && tx >= 0 &&
+                    tx < S.nt[0] && pa <= pb) {
+                    const long long ka = S.key0 + tile_key(S, pa, cy, cz);
+                    const long long kb = S.key0 + tile_key(S, pb, cy, cz);
+                    st = offs[ka];
+                    ln = offs[kb + 1] - st;
+                }
+                rstart[e] = st;
+                rlen[e] = ln;
+            }
+            mylen[h] = ln;
+        }
+        int total;
+        const int pre = block_excl_scan(mylen[0] + mylen[1], wsum, &total);
+        if (threadIdx.x * 2 < 363) rpre[threadIdx.x * 2] = pre;
+        if (threadIdx.x * 2 + 1 < 363) rpre[threadIdx.x * 2 + 1] = pre + mylen[0];
+        __syncthreads();
+
+        const int *__restrict__ key = ar.key[par];
+        const R *__restrict__ n0 = (const R *)ar.off[par][0];
+        const R *__restrict__ n1 = (const R *)ar.off[par][1];
+        const R *__restrict__ n2 = (const R *)ar.off[par][2];
+        const int *__restrict__ okey = ar.okey;
+        const R *__restrict__ q0 = init ? n0 : (const R *)ar.ooff[0];
+        const R *__restrict__ q1 = init ? n1 : (const R *)ar.ooff[1];
+        const R *__restrict__ q2 = init ? n2 : (const R *)ar.ooff[2];
+        const double scale = S.fx_scale;
+
+        for (int w = threadIdx.x; w < total; w += BLOCK) {
+            int lo = 0, hi = 362;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rpre[mid] <= w) lo = mid;
+                else hi = mid - 1;
+            }
+            const int p = rstart[lo] + (w - rpre[lo]);
+            const int nk = key[p] - (int)S.key0;
+            if (nk >= S.nkeys) continue;  // lost this step: deposits nothing
+            // start cell from the range (row y, z and x tile) and the x bits;
+            // end cell = start cell + recorded move
+            const int row = lo / 3;
+            const int rec = init ? (nk & 7) : okey[p];
+            int c0[3], c1[3];
+            c0[0] = (tX - 1 + lo % 3) * TILE + (rec & 7);
+            c0[1] = L[1] - 2 + row % 11;
+            c0[2] = L[2] - 2 + row / 11;
+            bool reach = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                c1[a] = c0[a] + (init ? 0 : ((rec >> (3 + 2 * a)) & 3) - 1);
+                const int b = min(c0[a], c1[a]);
+                reach = reach && b + 2 >= L[a] && b <= L[a] + TILE - 1;
+            }
+            if (!reach) continue;  // the 3^3 box of this move misses the tile
+            const R f0[3] = {q0[p], q1[p], q2[p]};
+            const R f1[3] = {n0[p], n1[p], n2[p]};
+            int base[3];
+            R S0[3][3], DS[3][3], S1[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                base[a] = min(c0[a], c1[a]);
+                // the start (end) cell is base or base + 1
+                const bool s0 = c0[a] == base[a], s1 = c1[a] == base[a];
+                S0[a][0] = s0 ? (R)1 - f0[a] : (R)0;
+                S0[a][1] = s0 ? f0[a] : (R)1 - f0[a];
+                S0[a][2] = s0 ? (R)0 : f0[a];
+                S1[a][0] = s1 ? (R)1 - f1[a] : (R)0;
+                S1[a][1] = s1 ? f1[a] : (R)1 - f1[a];
+                S1[a][2] = s1 ? (R)0 : f1[a];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) DS[a][m] = S1[a][m] - S0[a][m];
+            }
+            // the 3x3x3 box [base, base+2] in tile-local vertex coordinates
+            const int b0 = base[0] - L[0], b1 = base[1] - L[1], b2 = base[2] - L[2];
+            auto own = [](int v) { return v >= 0 && v < TILE; };
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const int pa = (l + 1) % 3, ra = (l + 2) % 3;
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                    for (int ee = 0; ee < 3; ++ee) {
+                        const R Y = S0[pa][bb] * S0[ra][ee] + (R)0.5 * DS[pa][bb] * S0[ra][ee] +
+                                    (R)0.5 * S0[pa][bb] * DS[ra][ee] +
+                                    DS[pa][bb] * DS[ra][ee] * (R)(1.0 / 3.0);
+                        R run = 0;
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) {
+                            run += DS[l][a] * Y;
+                            int v[3];
+                            v[l] = a;
+                            v[pa] = bb;
+                            v[ra] = ee;
+                            const int vx = b0 + v[0], vy = b1 + v[1], vz = b2 + v[2];
+                            if (own(vx) && own(vy) && own(vz)) {
+                                const int e = (vz * TILE + vy) * TILE + vx;
+                                fx_add<R>(&acc[l][e], &acl[l][e], (double)run, scale);
+                            }
+                        }
+                    }
+            }
+            // rho^{s+3/2} at the 8 vertices of the end cell
+            const int e0 = c1[0] - L[0], e1 = c1[1] - L[1], e2 = c1[2] - L[2];
+#pragma unroll
+            for (int K = 0; K < 2; ++K)
+#pragma unroll
+                for (int J = 0; J < 2; ++J)
+#pragma unroll
+                    for (int I = 0; I < 2; ++I) {
+                        const int vx = e0 + I, vy = e1 + J, vz = e2 + K;
+                        if (own(vx) && own(vy) && own(vz)) {
+                            const R w8 = (I ? f1[0] : (R)1 - f1[0]) * (J ? f1[1] : (R)1 - f1[1]) *
+                                         (K ? f1[2] : (R)1 - f1[2]);
+                            const int e = (vz * TILE + vy) * TILE + vx;
+                            fx_add<R>(&acc[3][e], &acl[3][e], (double)w8, scale);
+                        }
+                    }
+        }
+        __syncthreads();
+    }
+
+    // flush: every owned vertex, zeros included
+    R *J0 = (R *)ar.J[0] + S.cell0, *J1 = (R *)ar.J[1] + S.cell0, *J2 = (R *)ar.J[2] + S.cell0;
+    R *rho = (R *)ar.rho[init ? par : par ^ 1] + S.cell0;
+    const long long sy = S.n[0], sz = (long long)S.n[0] * S.n[1];
+    for (int e = threadIdx.x; e < TILE_CELLS; e += BLOCK) {
+        const int vx = L[0] + (e & 7), vy = L[1] + ((e >> 3) & 7), vz = L[2] + (e >> 6);
+        if (vx >= S.n[0] || vy >= S.n[1] || vz >= S.n[2]) continue;
+        const long long g = vz * sz + vy * sy + vx;
+        const int el = NLO == 1 ? 0 : e;
+        J0[g] = (R)(fx_value<R>(acc[0][e], acl[0][el]) * S.J_unit[0]);
+        J1[g] = (R)(fx_value<R>(acc[1][e], acl[1][el]) * S.J_unit[1]);
+        J2[g] = (R)(fx_value<R>(acc[2][e], acl[2][el]) * S.J_unit[2]);
+        rho[g] = (R)(fx_value<R>(acc[3][e], acl[3][el]) * S.rho_unit);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 5. exclusive scan of the bucket counts -> bucket starts (offs[(s+1) & 1]).
+//    Reduce per chunk, scan the chunk sums in one block, then scan each chunk
+//    with its base.  Wavefront scans use cross-lane shuffles.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int *__restrict__ counts,
+                                                        long long n, int *__restrict__ bsum)
+{
+    const long long base = (long long)blockIdx.x * SCAN_CHUNK;
+    int s = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_PER_THREAD; ++r) {
+        const long long i = base + (long long)r * BLOCK + threadIdx.x;
+        if (i < n) s += counts[i];
+    }
+    __shared__ int sh[BLOCK / 64];
+    int tot;
+    block_excl_scan(s, sh, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_top(int *__restrict__ bsum, int nb)
+{
+    __shared__ int sh[BLOCK / 64];
+    int carry = 0;
+    for (int base = 0; base < nb; base += BLOCK) {
+        const int i = base + threadIdx.x;
+        const int v = i < nb ? bsum[i] : 0;
+        int tot;
+        const int ex = block_excl_scan(v, sh, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_down(const int *__restrict__ counts, long long n,
+                                                      const int *__restrict__ bsum, Arena ar)
+{
+    const long long step = *ar.d_step;
+    int *__restrict__ out = ar.offs[(step + 1) & 1];
+    const long long base = (long long)blockIdx.x * SCAN_CHUNK;
+    // each thread scans SCAN_PER_THREAD consecutive entries
+    const long long i0 = base + (long long)threadIdx.x * SCAN_PER_THREAD;
+    int v[SCAN_PER_THREAD];
+    int s = 0;
+#pragma unroll
+    for (int r = 0; r < SCAN_PER_THREAD; ++r) {
+        v[r] = (i0 + r < n) ? counts[i0 + r] : 0;
+        s += v[r];
+    }
+    __shared__ int sh[BLOCK / 64];
+    int tot;
+    int run = bsum[blockIdx.x] + block_excl_scan(s, sh, &tot);
+#pragma unroll
+    for (int r = 0; r < SCAN_PER_THREAD; ++r) {
+        if (i0 + r < n) out[i0 + r] = run;
+        run += v[r];
+    }
+    if (i0 < n && i0 + SCAN_PER_THREAD >= n) out[n] = run;  // total
+}
+
+// ---------------------------------------------------------------------------
+// 6. scatter to the new sorted order (buffer (s+1) & 1).  The slot inside a
+//    bucket comes from an atomic decrement, which also returns the counts to
+//    zero for the next step.  The order inside a cell is arbitrary; nothing
+//    downstream depends on it (deposits are integer sums, the kinetic energy
+//    is summed by particle id).
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_scatter(Arena ar, long long np)
+{
+    const long long p = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= np) return;
+    const long long step = *ar.d_step;
+    const int s = (int)(step & 1), d = s ^ 1;
+    const int g = ar.key[s][p];
+    const int dst = ar.offs[d][g] + atomicSub(&ar.counts[g], 1) - 1;
+    ar.key[d][dst] = g;
+    ar.id[d][dst] = ar.id[s][p];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ((R *)ar.off[d][a])[dst] = ((const R *)ar.off[s][a])[p];
+        ((R *)ar.u[d][a])[dst] = ((const R *)ar.u[s][a])[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 7. double-precision diagnostics.  Per-block partial sums in fixed order,
+//    then one block per simulation sums its partials in fixed order and
+//    writes the row: deterministic run to run.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_diag_plane(const SimDev *__restrict__ sims,
+                                                       const int2 *__restrict__ items, Arena ar)
+{
+    const int2 it = items[blockIdx.x];
+    const SimDev &S = sims[it.x];
+    const long long step = *ar.d_step;
+    const FieldPtrs<R> f = field_ptrs<R>(S, ar, step % 3, (step + 1) % 3, (int)(step % 3));
+    const int e = it.y * BLOCK + threadIdx.x;
+    double pw = 0.0;
+    if (e < S.n[0] * S.n[1]) {
+        const int i = e % S.n[0], j = e / S.n[0];
+        if (vertex_valid(S, i, j, S.kp)) {
+            R E[3], B[3];
+            vertex_EB<R>(S, f, i, j, S.kp, E, B);
+            pw = (double)E[0] * (double)B[1] - (double)E[1] * (double)B[0];
+        }
+    }
+    __shared__ double sh[BLOCK];
+    const double tot = block_sum(pw, sh);
+    if (threadIdx.x == 0) ar.partial[S.part_plane0 + it.y] = tot;
+}
+
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_diag_mesh(const SimDev *__restrict__ sims,
+                                                      const int2 *__restrict__ items, Arena ar)
+{
+    const int2 it = items[blockIdx.x];
+    const SimDev &S = sims[it.x];
+    const long long step = *ar.d_step;
+    if (S.mesh_every <= 0 || ((step + 1) % S.mesh_every) != 0) return;
+    const FieldPtrs<R> f = field_ptrs<R>(S, ar, step % 3, (step + 1) % 3, (int)(step % 3));
+    const R *rn = (const R *)ar.rho[(step + 1) & 1] + S.cell0;
+    const R *ro = (const R *)ar.rho[step & 1] + S.cell0;
+    const R *J0 = (const R *)ar.J[0] + S.cell0, *J1 = (const R *)ar.J[1] + S.cell0,
+            *J2 = (const R *)ar.J[2] + S.cell0;
+    const long long ncell = (long long)S.n[0] * S.n[1] * S.n[2];
+    const long long sy = S.n[0], sz = (long long)S.n[0] * S.n[1];
+    double q = 0.0, wf = 0.0, rmax = 0.0, res = 0.0;
+    const long long base = (long long)it.y * BLOCK * MESH_DIAG_PER_THREAD;
+    for (int r = 0; r < MESH_DIAG_PER_THREAD; ++r) {
+        const long long g = base + (long long)r * BLOCK + threadIdx.x;
+        if (g >= ncell) break;
+        const int i = (int)(g % S.n[0]), j = (int)((g / S.n[0]) % S.n[1]), k = (int)(g / sz);
+        const double rv = (double)rn[g];
+        q += rv;
+        rmax = fmax(rmax, fabs(rv));
+        if (i >= 1 && j >= 1 && k >= 1) {
+            const double div = ((double)J0[g] - (double)J0[g - 1]) / S.d[0] +
+                               ((double)J1[g] - (double)J1[g - sy]) / S.d[1] +
+                               ((double)J2[g] - (double)J2[g - sz]) / S.d[2];
+            res = fmax(res, fabs(rv - (double)ro[g] + S.dt * div));
+        }
+        if (vertex_valid(S, i, j, k)) {
+            R E[3], B[3];
+            vertex_EB<R>(S, f, i, j, k, E, B);
+            const double e2 = (double)E[0] * E[0] + (double)E[1] * E[1] + (double)E[2] * E[2];
+            const double b2 = (double)B[0] * B[0] + (double)B[1] * B[1] + (double)B[2] * B[2];
+            wf += S.eps0_half * e2 + S.inv_2mu0 * b2;
+        }
+    }
+    __shared__ double sh[BLOCK];
+    const double tq = block_sum(q, sh);
+    const double tw = block_sum(wf, sh);
+    const double tr = block_max(rmax, sh);
+    const double ts = block_max(res, sh);
+    if (threadIdx.x == 0) {
+        double *o = ar.partial + S.part_mesh0 + 4 * (long long)it.y;
+        o[0] = tq;
+        o[1] = tw;
+        o[2] = tr;
+        o[3] = ts;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_diag_kin(const SimDev *__restrict__ sims,
+                                                     const int2 *__restrict__ items, Arena ar)
+{
+    const int2 it = items[blockIdx.x];
+    const SimDev &S = sims[it.x];
+    const long long step = *ar.d_step;
+    if (S.mesh_every <= 0 || ((step + 1) % S.mesh_every) != 0) return;
+    double s = 0.0;
+    const long long base = (long long)it.y * BLOCK * KIN_PER_THREAD;
+    for (int r = 0; r < KIN_PER_THREAD; ++r) {
+        const long long i = base + (long long)r * BLOCK + threadIdx.x;
+        if (i < S.np) s += ar.ke[S.part0 + i];
+    }
+    __shared__ double sh[BLOCK];
+    const double tot = block_sum(s, sh);
+    if (threadIdx.x == 0) ar.partial[S.part_kin0 + it.y] = tot;
+}
+
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__ sims, Arena ar)
+{
+    const SimDev &S = sims[blockIdx.x];
+    const long long step = *ar.d_step;
+    const bool mesh = S.mesh_every > 0 && ((step + 1) % S.mesh_every) == 0;
+    __shared__ double sh[BLOCK];
+    double pw = 0.0;
+    for (int b = threadIdx.x; b < S.nb_plane; b += BLOCK) pw += ar.partial[S.part_plane0 + b];
+    pw = block_sum(pw, sh);
+    double q = 0.0, wf = 0.0, rmax = 0.0, res = 0.0, kin = 0.0;
+    if (mesh) {
+        for (int b = threadIdx.x; b < S.nb_mesh; b += BLOCK) {
+            const double *o = ar.partial + S.part_mesh0 + 4 * (long long)b;
+            q += o[0];
+            wf += o[1];
+            rmax = fmax(rmax, o[2]);
+            res = fmax(res, o[3]);
+        }
+        for (int b = threadIdx.x; b < S.nb_kin; b += BLOCK) kin += ar.partial[S.part_kin0 + b];
+        q = block_sum(q, sh);
+        wf = block_sum(wf, sh);
+        rmax = block_max(rmax, sh);
+        res = block_max(res, sh);
+        kin = block_sum(kin, sh);
+    }
+    if (threadIdx.x == 0) {
+        double *row = ar.ring + (S.ring0 + step % S.ring_cap) * NDIAG;
+        R E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+        if (vertex_valid(S, S.probe[0], S.probe[1], S.probe[2])) {
+            const FieldPtrs<R> f = field_ptrs<R>(S, ar, step % 3, (step + 1) % 3, (int)(step % 3));
+            vertex_EB<R>(S, f, S.probe[0], S.probe[1], S.probe[2], E, B);
+        }
+        const int *offn = ar.offs[(step + 1) & 1];
+        const long long g = S.key0 + S.nkeys;
+        row[0] = (double)step;
+        row[1] = ((double)step + 0.5) * S.dt;
+        row[2] = mesh ? q * S.dV : 0.0;
+        row[3] = mesh ? (rmax > 0.0 ? res / rmax : 0.0) : 0.0;
+        row[4] = pw * S.dxdy_mu0;
+        row[5] = mesh ? wf * S.dV : 0.0;
+        row[6] = mesh ? kin * S.mc2 : 0.0;
+        for (int a = 0; a < 3; ++a) {
+            row[7 + a] = (double)E[a];
+            row[10 + a] = (double)B[a];
+        }
+        row[13] = (double)(offn[g + 1] - offn[g]);
+        int nf = ar.flags[blockIdx.x] ? 1 : 0;
+        for (int a = 2; a < 13; ++a)
+            if (!isfinite(row[a])) nf = 1;
+        if (nf) atomicOr(&ar.flags[blockIdx.x], 2);
+        row[14] = (double)nf;
+        row[15] = mesh ? 1.0 : 0.0;
+    }
+}
+
+__global__ void k_advance(long long *d_step)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d_step += 1;
+}
+
+// E and B at every vertex of one simulation for the last completed push
+// (levels s-1 and s after s steps), in double, component-major.
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_vertex_fields(const SimDev *__restrict__ sims, int sim,
+                                                          long long ncell, Arena ar,
+                                                          double *__restrict__ out)
+{
+    const SimDev &S = sims[sim];
+    const long long step = *ar.d_step;
+    const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (g >= ncell) return;
+    const int i = (int)(g % S.n[0]), j = (int)((g / S.n[0]) % S.n[1]),
+              k = (int)(g / ((long long)S.n[0] * S.n[1]));
+    R E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+    if (step > 0 && vertex_valid(S, i, j, k)) {
+        const FieldPtrs<R> f = field_ptrs<R>(S, ar, (step + 2) % 3, step % 3, (int)((step + 2) % 3));
+        vertex_EB<R>(S, f, i, j, k, E, B);
+    }
+    for (int a = 0; a < 3; ++a) {
+        out[a * ncell + g] = (double)E[a];
+        out[(3 + a) * ncell + g] = (double)B[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+#define MITHRA_STENCIL_SHAPES(X) X(64, 4) X(32, 8) X(128, 2) X(64, 2) X(32, 4) X(16, 16)
+
+bool stencil_shape_supported(int tx, int ty)
+{
+#define CHECK(a, b) if (tx == a && ty == b) return true;
+    MITHRA_STENCIL_SHAPES(CHECK)
+#undef CHECK
+    return false;
+}
+
+template <typename R>
+void launch_stencil(hipStream_t st, const SimDev *sims, const int4 *items, int nitems,
+                    const Arena &ar, int tx, int ty, int kz)
+{
+    if (nitems <= 0) return;
+    dim3 grid(nitems, 4);
+#define LAUNCH(a, b)                                                                        \
+    if (tx == a && ty == b) {                                                               \
+        hipLaunchKernelGGL((k_stencil<R, a, b>), grid, dim3(a * b), 0, st, sims, items, ar, \
+                           kz);                                                             \
+        return;                                                                             \
+    }
+    MITHRA_STENCIL_SHAPES(LAUNCH)
+#undef LAUNCH
+}
+
+template <typename R>
+void launch_boundary(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg,
+                     long long total, const Arena &ar)
+{
+    if (total <= 0) return;
+    long long nb = (total + BLOCK - 1) / BLOCK;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL((k_boundary<R>), dim3((unsigned)nb), dim3(BLOCK), 0, st, sims, segs, nseg,
+                       total, ar);
+}
+
+template <typename R>
+void launch_push(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
+                 const Arena &ar)
+{
+    if (nitems <= 0) return;
+    hipLaunchKernelGGL((k_push<R>), dim3(nitems), dim3(BLOCK), 0, st, sims, items, ar);
+}
+
+template <typename R>
+void launch_deposit(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
+                    const Arena &ar, int init)
+{
+    if (nitems <= 0) return;
+    hipLaunchKernelGGL((k_deposit<R>), dim3(nitems), dim3(BLOCK), 0, st, sims, items, ar, init);
+}
+
+void launch_scan(hipStream_t st, const Arena &ar, long long nkeys_total, int *block_sums,
+                 int nblocks, const long long *)
+{
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(BLOCK), 0, st, ar.counts, nkeys_total,
+                       block_sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, st, block_sums, nblocks);
+    hipLaunchKernelGGL(k_scan_down, dim3(nblocks), dim3(BLOCK), 0, st, ar.counts, nkeys_total,
+                       block_sums, ar);
+}
+
+template <typename R>
+void launch_scatter(hipStream_t st, const Arena &ar, long long np)
+{
+    if (np <= 0) return;
+    hipLaunchKernelGGL((k_scatter<R>), dim3((unsigned)((np + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       st, ar, np);
+}
+
+template <typename R>
+void launch_diag(hipStream_t st, const SimDev *sims, int nsim, const int2 *plane_items,
+                 int nplane, const int2 *mesh_items, int nmesh, const int2 *kin_items, int nkin,
+                 const Arena &ar)
+{
+    if (nplane > 0)
+        hipLaunchKernelGGL((k_diag_plane<R>), dim3(nplane), dim3(BLOCK), 0, st, sims, plane_items,
+                           ar);
+    if (nmesh > 0)
+        hipLaunchKernelGGL((k_diag_mesh<R>), dim3(nmesh), dim3(BLOCK), 0, st, sims, mesh_items,
+                           ar);
+    if (nkin > 0)
+        hipLaunchKernelGGL(k_diag_kin, dim3(nkin), dim3(BLOCK), 0, st, sims, kin_items, ar);
+    hipLaunchKernelGGL((k_diag_final<R>), dim3(nsim), dim3(BLOCK), 0, st, sims, ar);
+}
+
+void launch_advance(hipStream_t st, long long *d_step)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, d_step);
+}
+
+template <typename R>
+void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long ncell,
+                          const Arena &ar, double *out6)
+{
+    hipLaunchKernelGGL((k_vertex_fields<R>), dim3((unsigned)((ncell + BLOCK - 1) / BLOCK)),
+                       dim3(BLOCK), 0, st, sims, sim, ncell, ar, out6);
+}
+
+#define MITHRA_INSTANTIATE(R)                                                                   \
+    template void launch_stencil<R>(hipStream_t, const SimDev *, const int4 *, int,             \
+                                    const Arena &, int, int, int);                              \
+    template void launch_boundary<R>(hipStream_t, const SimDev *, const BSeg *, int, long long, \
+                                     const Arena &);                                            \
+    template void launch_push<R>(hipStream_t, const SimDev *, const int2 *, int, const Arena &); \
+    template void launch_deposit<R>(hipStream_t, const SimDev *, const int2 *, int,             \
+                                    const Arena &, int);                                        \
+    template void launch_scatter<R>(hipStream_t, const Arena &, long long);                     \
+    template void launch_diag<R>(hipStream_t, const SimDev *, int, const int2 *, int,           \
+                                 const int2 *, int, const int2 *, int, const Arena &);          \
+    template void launch_vertex_fields<R>(hipStream_t, const SimDev *, int, long long,          \
+                                          const Arena &, double *);
+
+MITHRA_INSTANTIATE(float)
+MITHRA_INSTANTIATE(double)
+
+}  // namespace mithra

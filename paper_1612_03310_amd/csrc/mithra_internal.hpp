@@ -1,0 +1,122 @@
+// Internal types shared by the kernels and the runtime of the MI355X path.
+// Not part of the public ABI (see include/mithra.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mithra {
+
+// Particles are binned by cell in tiles of 8x8x8 cells; a cell's bin key is
+// tile * 512 + (lz * 8 + ly) * 8 + lx (tile-major, x fastest inside the tile),
+// so one tile's particles and one row of cells inside a tile are contiguous.
+constexpr int TILE = 8;
+constexpr int TILE_CELLS = TILE * TILE * TILE;
+constexpr int TILE_VERT = TILE + 1;  // vertices per axis a tile's cells touch
+constexpr int NKINDS = 7;            // kernel kinds for timing
+constexpr int NDIAG = 16;            // doubles per diagnostic row
+constexpr int BLOCK = 256;
+constexpr int SCAN_PER_THREAD = 16;
+constexpr int SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
+constexpr int MESH_DIAG_PER_THREAD = 8;
+constexpr int KIN_PER_THREAD = 8;
+
+enum Kind { K_STENCIL = 0, K_BOUNDARY, K_PUSH, K_DEPOSIT, K_SCAN, K_SCATTER, K_DIAG };
+
+// Per-simulation constants, read by every kernel (device copy in an array).
+struct SimDev {
+    int n[3];
+    int bc[3];          // 0 Mur-1, 1 periodic
+    int sc;             // space charge on
+    int nsub;           // particle sub-steps per field step
+    int nt[3];          // tiles per axis
+    int nkeys;          // nt0*nt1*nt2*512; key nkeys is the "lost" bucket
+    int np;             // particles of this simulation (live + lost)
+    long long cell0;    // offset of this simulation in the mesh arenas
+    long long key0;     // offset in the key arenas (nkeys + 1 entries)
+    long long part0;    // offset in the particle arenas
+    // diagnostics
+    int probe[3];
+    int kp;
+    int mesh_every;     // 0: never
+    int ring_cap;
+    long long ring0;    // first row of this simulation in the ring arena
+    int part_plane0, nb_plane;  // partial-sum slots
+    int part_mesh0, nb_mesh;
+    int part_kin0, nb_kin;
+    // potential update, eq. (updateEquation) in the regrouped form
+    double a1, ax, ay, az, A, srcA, srcPhi;
+    double murb0[3], murb1[3];  // first-order Mur beta_0 (= beta_4), beta_1 (= beta_3)
+    // vertex fields
+    double inv_dt, inv_2d[3];
+    // particles
+    double d[3], origin[3];
+    double kE;          // q dtb / (2 m c): E [V/m] -> half kick of u
+    double kB;          // q dtb / (2 m):   B [T] * kB / gamma = Boris rotation vector
+    double cdtb_d[3];   // c dtb / d_a
+    double dt, dtb;
+    // undulator in the rest frame
+    double ku, kz_cell, phase_off, phase_rate;
+    double EuK, BuyK, BuzK;  // kick-scaled amplitudes of E_x, B_y, B_z
+    // deposition (fixed point with 2^S units)
+    double fx_scale;
+    double rho_unit, J_unit[3];
+    // diagnostics (SI)
+    double dV, mc2, dxdy_mu0, eps0_half, inv_2mu0;
+};
+
+// Device buffers of a batch (one arena per quantity, simulations concatenated).
+struct Arena {
+    void *pot[3][4];    // potential levels (rotating mod 3) x {Ax, Ay, Az, phi}
+    void *J[3];
+    void *rho[2];       // rho^{s+1/2} in rho[s & 1]
+    int *counts;        // per key (all simulations), zero between steps
+    int *offs[2];       // bucket starts; offs[s & 1] describes particle buffer s & 1
+    int *key[2];
+    void *off[2][3];    // position inside the cell, [0, 1)
+    void *u[2][3];
+    int *id[2];
+    int *okey;          // start of the step, for the deposit: x inside the tile (3 bits)
+                        // and the cell move per axis (2 bits each, move + 1)
+    void *ooff[3];
+    double *ke;         // (gamma - 1) by particle id, for the kinetic-energy sum
+    double *partial;    // diagnostic partial sums
+    double *ring;       // diagnostic rows
+    int *flags;         // per simulation: a non-finite value was produced
+    long long *d_step;  // completed steps (all simulations advance together)
+};
+
+struct BSeg {
+    int sim, comp, group, pad;  // group: axis of the faces
+    long long start, count;
+};
+
+// Host-side launchers (kernels.hip).
+template <typename R>
+void launch_stencil(hipStream_t st, const SimDev *sims, const int4 *items, int nitems,
+                    const Arena &ar, int tx, int ty, int kz);
+template <typename R>
+void launch_boundary(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg,
+                     long long total, const Arena &ar);
+template <typename R>
+void launch_push(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
+                 const Arena &ar);
+template <typename R>
+void launch_deposit(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
+                    const Arena &ar, int init);
+void launch_scan(hipStream_t st, const Arena &ar, long long nkeys_total, int *block_sums,
+                 int nblocks, const long long *d_step);
+template <typename R>
+void launch_scatter(hipStream_t st, const Arena &ar, long long nparticles);
+template <typename R>
+void launch_diag(hipStream_t st, const SimDev *sims, int nsim, const int2 *plane_items,
+                 int nplane, const int2 *mesh_items, int nmesh, const int2 *kin_items, int nkin,
+                 const Arena &ar);
+void launch_advance(hipStream_t st, long long *d_step);
+template <typename R>
+void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long ncell,
+                          const Arena &ar, double *out6);
+bool stencil_shape_supported(int tx, int ty);
+
+}  // namespace mithra

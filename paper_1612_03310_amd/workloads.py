@@ -15,11 +15,15 @@ examples and the published configuration list):
   radiation wavelength); the transverse cells are ``aspect`` times larger,
   which keeps (dz/dx)^2 + (dz/dy)^2 < 1 as the NSFD scheme requires;
 * the mesh is centred on the undulator axis: x = y = z = 0 at its centre;
-* positions: independent Gaussian per axis with sigma = n_d / 8 cells,
-  truncated at 3 sigma by re-drawing (numpy PCG64, seeded);
+* guiding centres: independent Gaussian per axis with sigma = n_d / 8
+  cells, truncated at 3 sigma by re-drawing (numpy PCG64, seeded);
 * lab energy gamma' = gamma * (1 + sigma_delta * N(0, 1)); momenta matched to
   the undulator at the particle's lab phase, u'_x = -K cos(k_u z'),
   u'_y = 0, u'_z from gamma', then boosted to the rest frame;
+* each particle sits at its guiding centre plus its wiggle offset,
+  x = x_c - K / (gamma0 k_u sqrt(1 + K^2/2)) sin(k_u z'), so that its
+  transverse oscillation is centred on x_c (a particle started at its
+  centre would swing up to twice the amplitude to one side);
 * the undulator entrance z_e lies one cell behind the mesh, so every
   particle starts inside the periodic field.
 """
@@ -103,6 +107,7 @@ def make_workload(name: str, n, n_particles: int, gamma: float, K: float, lambda
     gp = gamma * (1.0 + sigma_delta * rng.standard_normal(n_particles))
     zlab = gamma0 * (x[:, 2] - z_e)  # lab undulator coordinate at t = 0
     uxp = -K * np.cos(ku * zlab)
+    x[:, 0] -= K / (gamma0 * ku * math.sqrt(1.0 + K * K / 2.0)) * np.sin(ku * zlab)
     uzp = np.sqrt(gp * gp - 1.0 - uxp * uxp)
     u = np.zeros((n_particles, 3))
     u[:, 0] = uxp

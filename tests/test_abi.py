@@ -1,0 +1,51 @@
+"""Host-side checks of the C-ABI library (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1612_03310_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mithra.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mithra_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_functions():
+    assert _declared_functions() == sorted(native.ABI_FUNCTIONS)
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    if not os.path.exists(native.LIB_PATH):
+        pytest.fail("libmithra.so is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(native.LIB_PATH)
+    missing = [f for f in _declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_the_header():
+    # sizes implied by the C declarations (natural alignment on x86-64)
+    assert ctypes.sizeof(native.Mesh) == 3 * 4 + 4 + 3 * 8 + 3 * 8 + 8 + 8 + 4 + 4 + 3 * 4 + 4
+    assert ctypes.sizeof(native.Undulator) == 32
+    assert ctypes.sizeof(native.DiagCfg) == 24
+    assert ctypes.sizeof(native.DiagRow) == 8 * 14 + 4 + 4
+    assert ctypes.sizeof(native.Info) == 7 * 8 + 3 * 8 + 3 * 4 + 4
+
+
+def test_last_error_is_empty_string_before_any_failure():
+    lib = native.load_library()
+    assert isinstance(lib.mithra_last_error(), bytes)
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    lib = native.load_library()
+    assert lib.mithra_create(None, None, 0, None, None) == native.EINVAL
+    assert lib.mithra_run(None, 1) == native.EINVAL
+    assert b"NULL" in lib.mithra_last_error()
+    assert lib.mithra_set_allocator(ctypes.c_void_p(1), None, None) == native.EINVAL

@@ -1,0 +1,461 @@
+"""GPU path (through the C ABI) against the FP64 CPU oracle, element by element.
+
+Bar: relative L2 <= 1e-10 for the double-precision path; for the float path
+with split positions, relative L2 <= 1e-3 of the on-axis probe field series
+and of the radiated-power series.  Every input comes from the seeded
+generator; no expected value comes from the GPU path.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1612_03310_amd import native
+from paper_1612_03310_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+C = 299792458.0
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+
+TOL64 = 1e-10
+POT = ("Ax", "Ay", "Az", "phi")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return float(np.linalg.norm(a))
+    return float(np.linalg.norm(a - b) / nb)
+
+
+VECTORS = {"A": ("Ax", "Ay", "Az"), "A_prev": ("Ax_prev", "Ay_prev", "Az_prev"),
+           "J": ("Jx", "Jy", "Jz"), "E": ("Ex", "Ey", "Ez"), "B": ("Bx", "By", "Bz")}
+# Per-component guard.  A component that is tiny next to its vector (J_y,
+# A_y: the bunch barely moves in y) is ill-conditioned: its edge currents are
+# differences of nearly equal linear weights, so a one-ulp difference in how a
+# position is held (SI metres in the oracle, cell + offset on the GPU) is
+# amplified by the ratio of the weight to the y-displacement.  The bar is the
+# relative L2 of each vector field; a component must still agree to 1e-8,
+# which any real error in one component (a sign, an index) fails by far.
+COMPONENT_GUARD = 1e-8
+
+
+def _oracle_field(orc, name):
+    table = {"Ax": lambda: orc.pot(0, "cur"), "Ay": lambda: orc.pot(1, "cur"),
+             "Az": lambda: orc.pot(2, "cur"), "phi": lambda: orc.pot(3, "cur"),
+             "Ax_prev": lambda: orc.pot(0, "prev"), "Ay_prev": lambda: orc.pot(1, "prev"),
+             "Az_prev": lambda: orc.pot(2, "prev"), "phi_prev": lambda: orc.pot(3, "prev"),
+             "Jx": lambda: orc.J(0), "Jy": lambda: orc.J(1), "Jz": lambda: orc.J(2),
+             "rho": lambda: orc.rho, "rho_prev": lambda: orc.rho_prev,
+             "Ex": lambda: orc.E(0), "Ey": lambda: orc.E(1), "Ez": lambda: orc.E(2),
+             "Bx": lambda: orc.B(0), "By": lambda: orc.B(1), "Bz": lambda: orc.B(2)}
+    return table[name]()
+
+
+def compare_state(sim, orc, tol, what=""):
+    """Every stored mesh quantity, the derived E/B and the particles."""
+    errs, comp = {}, {}
+    for vec, names in VECTORS.items():
+        g = np.stack([sim.get_field(n) for n in names])
+        o = np.stack([_oracle_field(orc, n) for n in names])
+        errs[vec] = rel_l2(g, o)
+        for n, gi, oi in zip(names, g, o):
+            comp[n] = rel_l2(gi, oi)
+    for n in ("phi", "phi_prev", "rho", "rho_prev"):
+        errs[n] = rel_l2(sim.get_field(n), _oracle_field(orc, n))
+    if orc.np > 0:
+        pos, u, alive = sim.get_particles()
+        assert np.array_equal(alive, orc.alive), what
+        errs["pos"] = rel_l2(pos[alive], orc.x[alive])
+        errs["u"] = rel_l2(u, orc.u)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    bad.update({k: v for k, v in comp.items() if not v <= COMPONENT_GUARD})
+    say(what, "worst", max(errs, key=errs.get), max(errs.values()),
+        "worst component", max(comp, key=comp.get), max(comp.values()))
+    assert not bad, (what, bad)
+    return errs
+
+
+def compare_diag(gd, od, tol, what=""):
+    assert len(gd) == len(od), (len(gd), len(od))
+    assert np.array_equal(gd["step"], od[:, 0].astype(np.int64))
+    assert np.array_equal(gd["lost"], od[:, 13].astype(np.int64))
+    assert not gd["nonfinite"].any()
+    cols = {"total_charge": 2, "power": 4, "field_energy": 5, "kinetic_energy": 6}
+    errs = {k: rel_l2(gd[k], od[:, c]) for k, c in cols.items()}
+    errs["probe_E"] = rel_l2(gd["probe_E"], od[:, 7:10])
+    errs["probe_B"] = rel_l2(gd["probe_B"], od[:, 10:13])
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    say(what, "diag", errs)
+    assert not bad, (what, bad)
+    # continuity holds to round-off of the fixed-point deposit on both sides
+    assert np.max(gd["continuity_residual"]) < 1e-11
+
+
+def run_pair(w, steps, precision="f64", every=1):
+    say("case", w.name, w.n, w.np, "steps", steps, precision)
+    orc = oracle.from_workload(w)
+    sim = native.sim_from_workload(w, precision=precision, every=every)
+    sim.run(steps)
+    sim.sync()
+    orc.step(steps)
+    return sim, orc
+
+
+# ---------------------------------------------------------------------------
+# potential update and boundary alone
+# ---------------------------------------------------------------------------
+
+def _random_fields(n, bc, rng):
+    """Random potentials; the unused last layer of an edge grid along its own
+    Mur axis is zero."""
+    nx, ny, nz = n
+    out = {}
+    for c, name in enumerate(POT):
+        a = rng.standard_normal((nz, ny, nx))
+        if c < 3 and not bc[c]:
+            idx = [slice(None)] * 3
+            idx[2 - c] = -1
+            a[tuple(idx)] = 0.0
+        out[name] = a
+    return out
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 0), (1, 1, 1), (0, 1, 0)])
+def test_potential_update_and_mur_match_oracle(bc):
+    """One step of eq. (updateEquation) plus first-order Mur on faces, edges
+    and corners, with random potentials and sources, on a mesh whose sizes are
+    not multiples of the 8-cell tiles."""
+    n = (40, 36, 50)
+    dz = 2e-6
+    d = (4 * dz, 3 * dz, dz)
+    origin = tuple(-(n[a] - 1) / 2 * d[a] for a in range(3))
+    say("case stencil", n, bc)
+    rng = np.random.default_rng(11)
+    cur = _random_fields(n, bc, rng)
+    prev = _random_fields(n, bc, rng)
+    J = [rng.standard_normal((n[2], n[1], n[0])) * 1e4 for _ in range(3)]
+    rho = rng.standard_normal((n[2], n[1], n[0])) * 1e-2
+    orc = oracle.OracleSim(n, d, origin, courant=0.9, bc=bc, space_charge=1, K=0.0,
+                           gamma_beam=50.0)
+    orc.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+    sim = native.Sim(n, d, origin, courant=0.9, bc=bc, space_charge=1, K=0.0, gamma_beam=50.0)
+    sim.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+    for c, name in enumerate(POT):
+        orc.pot(c, "cur")[:] = cur[name]
+        orc.pot(c, "prev")[:] = prev[name]
+        sim.set_field(name, cur[name])
+        sim.set_field(name + "_prev", prev[name])
+    for c, name in enumerate(("Jx", "Jy", "Jz")):
+        orc.J(c)[:] = J[c]
+        sim.set_field(name, J[c])
+    orc.rho[:] = rho
+    sim.set_field("rho", rho)
+    orc.field_update()
+    sim.run(1)
+    sim.sync()
+    for c, name in enumerate(POT):
+        e = rel_l2(sim.get_field(name), orc.pot(c, "next"))
+        assert e < TOL64, (name, e)
+        # the boundary layer alone (faces, edges, corners)
+        g = sim.get_field(name)
+        o = orc.pot(c, "next")
+        mask = np.zeros_like(g, dtype=bool)
+        mask[0], mask[-1], mask[:, 0], mask[:, -1], mask[:, :, 0], mask[:, :, -1] = (True,) * 6
+        if np.any(o[mask] != 0):
+            assert rel_l2(g[mask], o[mask]) < TOL64, name
+
+
+def test_plane_wave_dispersion_on_gpu():
+    """Property at any size: a plane wave with the frequency of eq.
+    (NSFDDispersionCD) stays an exact discrete solution on the GPU too."""
+    n = (32, 32, 64)
+    dz = 1e-6
+    d = (4 * dz, 4 * dz, dz)
+    origin = (0.0, 0.0, 0.0)
+    sim = native.Sim(n, d, origin, courant=0.9, bc=(1, 1, 1), space_charge=1, K=0.0,
+                     gamma_beam=50.0)
+    sim.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+    info = sim.info()
+    dt, A = info["dt"], info["nsfd_A"]
+    k = (2 * math.pi / (n[0] * d[0]), 2 * math.pi * 3 / (n[1] * d[1]),
+         2 * math.pi * 5 / (n[2] * d[2]))
+    sx = math.sin(k[0] * d[0] / 2) ** 2 / d[0] ** 2
+    sy = math.sin(k[1] * d[1] / 2) ** 2 / d[1] ** 2
+    szr = math.sin(k[2] * d[2] / 2) ** 2
+    w = 2.0 / dt * math.asin(C * dt * math.sqrt((1 - 4 * A * szr) * (sx + sy) + szr / d[2] ** 2))
+    kk, jj, ii = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    ph = k[0] * ii * d[0] + k[1] * jj * d[1] + k[2] * kk * d[2]
+    for name in POT:
+        sim.set_field(name, np.cos(ph))
+        sim.set_field(name + "_prev", np.cos(ph + w * dt))
+    say("case plane wave")
+    sim.run(150)
+    sim.sync()
+    for name in POT:
+        assert np.max(np.abs(sim.get_field(name) - np.cos(ph - 150 * w * dt))) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# the whole step
+# ---------------------------------------------------------------------------
+
+def test_tiny_config_full_loop_f64():
+    """32x32x64, 4096 particles, 200 steps: every array and every diagnostic."""
+    w = W.config(0)
+    sim, orc = run_pair(w, 200)
+    compare_state(sim, orc, TOL64, "tiny")
+    compare_diag(sim.get_diag(), orc.diag(), TOL64, "tiny")
+    assert orc.lost == 0
+
+
+@pytest.mark.parametrize("variant", ["ragged_substeps", "no_space_charge", "courant_one",
+                                     "standard_scheme"])
+def test_variants_full_loop_f64(variant):
+    kw = dict()
+    n = (40, 44, 72)
+    if variant == "ragged_substeps":
+        kw = dict(substeps=2)
+    elif variant == "no_space_charge":
+        kw = dict(space_charge=0)
+    elif variant == "courant_one":
+        kw = dict(courant=1.0)
+    w = W.make_workload(variant, n, 3000, 120.0, 1.3, 0.015, 1e-4, 77, 60, **kw)
+    if variant == "standard_scheme":
+        w.nsfd_A = 0.0
+        w.courant = 0.5
+    sim, orc = run_pair(w, 60)
+    compare_state(sim, orc, TOL64, variant)
+    compare_diag(sim.get_diag(), orc.diag(), TOL64, variant)
+
+
+def test_mid_subcase_full_loop_f64():
+    """64x64x128 with 65536 particles (the oracle-checkable slice of the mid
+    configuration), 100 steps."""
+    w = W.mid_subcase(steps=100)
+    sim, orc = run_pair(w, 100)
+    compare_state(sim, orc, TOL64, "mid-subcase")
+    compare_diag(sim.get_diag(), orc.diag(), TOL64, "mid-subcase")
+
+
+def test_mid_config_full_size_f64():
+    """128x128x512, 1M particles, in the launch configuration the benchmark
+    times: a few steps against the oracle at full size."""
+    w = W.config(1)
+    sim, orc = run_pair(w, 3, every=1)
+    compare_state(sim, orc, TOL64, "mid-full")
+    compare_diag(sim.get_diag(), orc.diag(), TOL64, "mid-full")
+
+
+# ---------------------------------------------------------------------------
+# float path with split positions
+# ---------------------------------------------------------------------------
+
+def test_precision_config_f32_split():
+    """Float fields and push, int32 cell + float offset positions, double
+    diagnostics: probe field and radiated power within 1e-3 of the FP64 oracle."""
+    w = W.config(2)
+    sim, orc = run_pair(w, 200, precision="f32")
+    gd, od = sim.get_diag(), orc.diag()
+    errs = {
+        "probe_Ex": rel_l2(gd["probe_E"][:, 0], od[:, 7]),
+        "power": rel_l2(gd["power"], od[:, 4]),
+    }
+    other = {
+        "probe_E": rel_l2(gd["probe_E"], od[:, 7:10]),
+        "probe_B": rel_l2(gd["probe_B"], od[:, 10:13]),
+        "field_energy": rel_l2(gd["field_energy"], od[:, 5]),
+        "kinetic_energy": rel_l2(gd["kinetic_energy"], od[:, 6]),
+        "charge": rel_l2(gd["total_charge"], od[:, 2]),
+        "Ax": rel_l2(sim.get_field("Ax"), orc.pot(0, "cur")),
+        "phi": rel_l2(sim.get_field("phi"), orc.pot(3, "cur")),
+    }
+    # a particle lost at the mesh edge takes its charge along, which the
+    # continuity residual of that step reports; judge the other steps
+    steady = np.concatenate([[gd["lost"][0] == 0], np.diff(gd["lost"]) == 0])
+    cont = np.max(gd["continuity_residual"][steady])
+    say("f32 split", errs, other, "continuity", cont, "lost", gd["lost"][-1], orc.lost)
+    assert errs["probe_Ex"] <= 1e-3 and errs["power"] <= 1e-3, errs
+    assert other["charge"] < 1e-6
+    assert cont < 1e-5
+    assert not gd["nonfinite"].any()
+    assert gd["lost"][-1] == orc.lost
+
+
+# ---------------------------------------------------------------------------
+# determinism, batch, checkpoint
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_run_twice_is_bitwise_identical(precision):
+    w = W.config(0, steps=50)
+    outs = []
+    for _ in range(2):
+        sim = native.sim_from_workload(w, precision=precision)
+        sim.run(50)
+        sim.sync()
+        outs.append(([sim.get_field(f) for f in ("Ax", "Az", "phi", "Jx", "rho", "Ex")],
+                     sim.get_particles(), sim.get_diag()))
+        sim.close()
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b, equal_nan=True)
+    assert outs[0][2].tobytes() == outs[1][2].tobytes()
+
+
+def test_batch_equals_separate_runs_bitwise():
+    ws = [W.make_workload("b%d" % i, n, npart, g, K, 0.015, 1e-4, 100 + i, 40)
+          for i, (n, npart, g, K) in enumerate([((32, 32, 128), 3000, 90.0, 0.9),
+                                                  ((48, 48, 192), 8000, 150.0, 1.6),
+                                                  ((40, 40, 160), 5000, 220.0, 1.2)])]
+    say("case batch", [w.n for w in ws])
+    b = native.batch_from_workloads(ws, precision="f32")
+    b.run(40)
+    b.sync()
+    for s, w in enumerate(ws):
+        sim = native.sim_from_workload(w, precision="f32")
+        sim.run(40)
+        sim.sync()
+        for f in ("Ax", "Ay", "Az", "phi", "Jz", "rho", "Ex", "By"):
+            assert np.array_equal(b.get_field(s, f), sim.get_field(f)), (s, f)
+        pb, ub, ab = b.get_particles(s)
+        ps, us, as_ = sim.get_particles()
+        assert np.array_equal(ab, as_)
+        assert np.array_equal(pb[ab], ps[as_]) and np.array_equal(ub, us)
+        assert b.get_diag(s).tobytes() == sim.get_diag().tobytes()
+        sim.close()
+
+
+def test_batch_tuned_matches_oracle_f64():
+    ws = [W.make_workload("t%d" % i, n, npart, g, K, 0.015, 1e-4, 300 + i, 30)
+          for i, (n, npart, g, K) in enumerate([((32, 32, 64), 2000, 100.0, 1.0),
+                                                  ((40, 32, 96), 3000, 140.0, 1.5)])]
+    b = native.batch_from_workloads(ws, precision="f64")
+    b.tune(2)
+    b.run(30)
+    b.sync()
+    for s, w in enumerate(ws):
+        orc = oracle.from_workload(w)
+        orc.step(30)
+        for c, name in enumerate(POT):
+            assert rel_l2(b.get_field(s, name), orc.pot(c, "cur")) < TOL64
+        pos, u, alive = b.get_particles(s)
+        assert rel_l2(u, orc.u) < TOL64
+        compare_diag(b.get_diag(s), orc.diag(), TOL64, "batch-f64-%d" % s)
+
+
+def test_checkpoint_resume_is_bitwise():
+    w = W.config(0, steps=30)
+    sim = native.sim_from_workload(w)
+    sim.run(10)
+    blob = sim.get_state()
+    sim.run(20)
+    sim.sync()
+    ref = [sim.get_field(f) for f in ("Ax", "phi", "Jy", "rho", "Bz")] + list(sim.get_particles())
+    sim2 = native.sim_from_workload(w)
+    sim2.set_state(blob)
+    sim2.run(20)
+    sim2.sync()
+    got = [sim2.get_field(f) for f in ("Ax", "phi", "Jy", "rho", "Bz")] + list(sim2.get_particles())
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b, equal_nan=True)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+def test_empty_bunch_and_minimal_mesh():
+    n = (8, 8, 8)
+    d = (4e-6, 4e-6, 1e-6)
+    origin = (-14e-6, -14e-6, -3.5e-6)
+    sim = native.Sim(n, d, origin)
+    sim.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+    sim.run(10)
+    sim.sync()
+    assert np.all(sim.get_field("Ax") == 0.0)
+    dg = sim.get_diag()
+    assert len(dg) == 10 and not dg["nonfinite"].any()
+
+
+def test_particles_outside_the_safe_interior_are_counted_lost():
+    w = W.config(0, n_particles=64, steps=1)
+    x = w.x.copy()
+    x[3] = [w.origin[0] + 0.5 * w.d[0], 0.0, 0.0]           # cell 0 in x
+    x[7] = [0.0, 0.0, w.origin[2] + (w.n[2] - 2.5) * w.d[2]]  # cell n-3 is the last allowed
+    x[9] = [0.0, 0.0, w.origin[2] + (w.n[2] - 1.5) * w.d[2]]  # cell n-2: lost
+    w.x = x
+    sim, orc = run_pair(w, 1)
+    pos, u, alive = sim.get_particles()
+    assert not alive[3] and alive[7] and not alive[9]
+    assert np.array_equal(alive, orc.alive)
+    assert sim.get_diag()["lost"][-1] == orc.lost == 2
+    compare_state(sim, orc, TOL64, "lost")
+
+
+def test_invalid_meshes_are_rejected():
+    n = (16, 16, 16)
+    d = (1e-6, 1e-6, 1e-6)  # cubic cells: unstable for the NSFD scheme at courant 0.9
+    with pytest.raises(native.MithraError) as e:
+        native.Sim(n, d, (0, 0, 0), courant=0.9)
+    assert e.value.status == native.EINVAL and "unstable" in str(e.value)
+    with pytest.raises(native.MithraError) as e:
+        native.Sim(n, (4e-6, 4e-6, 1e-6), (0, 0, 0), courant=1.2)
+    assert e.value.status == native.EINVAL
+    with pytest.raises(native.MithraError) as e:
+        native.Sim((4, 16, 16), (4e-6, 4e-6, 1e-6), (0, 0, 0))
+    assert e.value.status == native.EINVAL
+
+
+def test_run_before_particles_is_a_state_error():
+    sim = native.Sim((16, 16, 16), (4e-6, 4e-6, 1e-6), (0, 0, 0))
+    with pytest.raises(native.MithraError) as e:
+        sim.run(1)
+    assert e.value.status == native.ESTATE
+
+
+def test_overflowing_field_is_reported_as_numeric_error():
+    """A potential that overflows the float range makes the momenta non-finite;
+    the particle is counted lost and sync reports ENUMERIC."""
+    w = W.config(0, n_particles=256, steps=2)
+    sim = native.sim_from_workload(w, precision="f32")
+    big = np.full((w.n[2], w.n[1], w.n[0]), 3e38)
+    big[::2] = -3e38
+    sim.set_field("Ax", big)
+    sim.run(1)
+    with pytest.raises(native.MithraError) as e:
+        sim.sync()
+    assert e.value.status == native.ENUMERIC
+    sim.sync()  # the flag is cleared once reported
+
+
+# ---------------------------------------------------------------------------
+# the large float configuration at full size (properties that hold at any size)
+# ---------------------------------------------------------------------------
+
+def test_large_config_f32_properties():
+    """256x256x2048 with 16.8M particles: charge conserved, continuity at
+    round-off of the float deposit, nothing lost, everything finite."""
+    w = W.config(3)
+    say("case large", w.n, w.np)
+    sim = native.sim_from_workload(w, precision="f32", every=5)
+    sim.run(10)
+    sim.sync()
+    dg = sim.get_diag()
+    mesh = dg[dg["has_mesh_terms"] == 1]
+    total = w.q * w.np
+    assert len(mesh) == 2
+    assert np.max(np.abs(mesh["total_charge"] / total - 1.0)) < 1e-5
+    assert np.max(mesh["continuity_residual"]) < 1e-5
+    assert dg["lost"][-1] == 0 and not dg["nonfinite"].any()
+    assert np.all(np.isfinite(dg["power"]))
