@@ -173,6 +173,9 @@ def main():
                     help="first copy 1 GiB device-to-device 5 times (a kernel of known "
                          "traffic, to scale hardware byte counters)")
     ap.add_argument("--skip-large", action="store_true")
+    ap.add_argument("--workload", choices=("mid", "large"), default="mid",
+                    help="headline workload: mid (128x128x512, 1M particles, f64, the "
+                         "default) or large (256x256x2048, 16.8M particles, f32 split)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -197,16 +200,18 @@ def main():
         del src, dst
 
     # ---- headline: the mid configuration in double precision ----------------
-    w = W.config(1)
-    wname = "mid-128x128x512-1M-particles"
-    log("mid configuration %s, %d particles, f64, %d steps" % (w.n, w.np, K))
-    dt, dt_ev, per, dg, info = measure(w, "f64", K, Wm, torch, native)
+    if args.workload == "mid":
+        w, wname, prec, rs = W.config(1), "mid-128x128x512-1M-particles", "f64", 8
+    else:
+        w, wname, prec, rs = W.config(3), "large-256x256x2048-16.8M-particles", "f32", 4
+        args.skip_large = True
+    log("%s configuration %s, %d particles, %s, %d steps" % (args.workload, w.n, w.np, prec, K))
+    dt, dt_ev, per, dg, info = measure(w, prec, K, Wm, torch, native)
     ms_step = dt * 1e3 / K
     value = w.ncell * K / dt
     pushes = w.np * K * w.substeps / dt
     log("  %.4f ms/step, %.3e cell-updates/s, %.3e pushes/s" % (ms_step, value, pushes))
 
-    rs = 8
     nbp = boundary_points(w)
     kernels = {}
     for kind, t in per.items():
@@ -218,7 +223,7 @@ def main():
     dom = max((k for k in per if kernel_bytes(k, w, rs, nbp)), key=lambda k: per[k])
     dom_bytes = kernel_bytes(dom, w, rs, nbp)
     achieved = dom_bytes / (per[dom] * 1e-3) / 1e9
-    traffic = traffic_from_profile(dom, "mid")
+    traffic = traffic_from_profile(dom, args.workload)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes_per_launch": dom_bytes,
@@ -259,7 +264,7 @@ def main():
                               "cell_updates_per_s": cells * nb / dtb}
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "mid":  # a large step takes minutes on one core
         log("cpu baseline: oracle, %d steps of the mid configuration" % args.cpu_steps)
         cpu = cpu_baseline(w, args.cpu_steps)
         log("  %.3e cell-updates/s" % cpu["value"])
@@ -267,9 +272,9 @@ def main():
     line = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": round(ms_step, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
         "config": {"workload": wname, "mesh": list(w.n), "particles": w.np,
-                   "precision": "f64", "courant": w.courant, "nsfd_A": info["nsfd_A"],
+                   "precision": prec, "courant": w.courant, "nsfd_A": info["nsfd_A"],
                    "substeps": w.substeps, "space_charge": w.space_charge,
                    "gamma": w.gamma_beam, "K": w.K, "lambda_u": w.lambda_u,
                    "mesh_diag_every": 100, "stencil_tile": info["stencil_tile"]},
