@@ -7,6 +7,8 @@
 // traffic, and none uses the matrix cores.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "mithra_internal.hpp"
 
 namespace mithra {
@@ -447,6 +449,26 @@ __device__ __forceinline__ void undulator_kick(const SimDev &S, double ph_cell, 
     }
 }
 
+// One atomic add per run of equal keys in consecutive active lanes of a
+// wavefront (particles arrive sorted by cell, so runs are common).  Every lane
+// of the wavefront must call this.
+__device__ __forceinline__ void count_runs(int *counts, int key, bool active)
+{
+    const int lane = threadIdx.x & 63;
+    const int k = active ? key : -1;
+    const int prev = __shfl_up(k, 1, 64);
+    const bool head = active && (lane == 0 || prev != k);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long act = __ballot(active);
+    if (head) {
+        const unsigned long long later = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+        const int next = later ? __ffsll((long long)later) - 1 : 64;
+        const unsigned long long span =
+            (next == 64 ? ~0ull : ((1ull << next) - 1)) & (~0ull << lane);
+        atomicAdd(&counts[k], __popcll(act & span));
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
                                                  const int2 *__restrict__ items, Arena ar)
@@ -464,97 +486,114 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
     }
     const long long g0 = S.key0 + (long long)it.y * TILE_CELLS;
     const int p_lo = offs[g0], p_hi = offs[g0 + TILE_CELLS];
+    if (threadIdx.x == 0) ar.tocc[S.tile0 + it.y] = p_hi - p_lo;  // for the deposit
     if (p_lo == p_hi) return;
 
     const int t = it.y;
     const int L0 = (t % S.nt[0]) * TILE, L1 = ((t / S.nt[0]) % S.nt[1]) * TILE,
               L2 = (t / (S.nt[0] * S.nt[1])) * TILE;
 
+    int *__restrict__ key = ar.key[par];
+    R *__restrict__ o0 = (R *)ar.off[par][0];
+    R *__restrict__ o1 = (R *)ar.off[par][1];
+    R *__restrict__ o2 = (R *)ar.off[par][2];
+    R *__restrict__ u0 = (R *)ar.u[par][0];
+    R *__restrict__ u1 = (R *)ar.u[par][1];
+    R *__restrict__ u2 = (R *)ar.u[par][2];
+
+    // The thread's first particle is loaded together with the fields, so a
+    // block waits for memory once before the E, B table is built.
+    int gk = 0;
+    R f[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+    if (p_lo + (int)threadIdx.x < p_hi) {
+        const int p = p_lo + threadIdx.x;
+        gk = key[p];
+        f[0] = o0[p];
+        f[1] = o1[p];
+        f[2] = o2[p];
+        u[0] = u0[p];
+        u[1] = u1[p];
+        u[2] = u2[p];
+    }
+
     // E and B at the tile's 9^3 vertices.  The potentials of the box
-    // [L-1, L+9]^3 are staged in LDS one component at a time (both levels as
-    // their difference, for E = -dA/dt, and their sum, for the mean curl),
-    // then phi; each thread accumulates its vertices' E and B in registers.
+    // [L-1, L+9]^3 are staged in LDS in one pass: for each A component the
+    // level difference (for E = -dA/dt) and the level sum (for the mean
+    // curl), and phi.  The kick-scaled E, B table then overwrites the staging.
     constexpr int NV = TILE_VERT * TILE_VERT * TILE_VERT;  // 729
     constexpr int SG = TILE_VERT + 2;                      // 11
     constexpr int NS = SG * SG * SG;                       // 1331
-    constexpr int VPT = (NV + BLOCK - 1) / BLOCK;          // 3
-    // the staging buffers (2 x NS) and the field table (6 x NV) share LDS
-    constexpr int NSM = 6 * NV > 2 * NS ? 6 * NV : 2 * NS;
-    __shared__ R smem[NSM];
-    R *sD = smem, *sS = smem + NS;
-    R (*sF)[NV] = reinterpret_cast<R (*)[NV]>(smem);
+    constexpr int NSE = (NS + BLOCK - 1) / BLOCK;          // staged points per thread
+    constexpr int VPT = (NV + BLOCK - 1) / BLOCK;          // vertices per thread
+    constexpr int OX = 1, OY = SG, OZ = SG * SG;
+    static_assert(6 * NV <= 7 * NS, "the field table must fit in the staging area");
+    __shared__ R smem[7 * NS];
+    R(*stg)[NS] = reinterpret_cast<R(*)[NS]>(smem);  // D_x D_y D_z S_x S_y S_z phi
+    R(*sF)[NV] = reinterpret_cast<R(*)[NV]>(smem);
+    {
+        const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+        const long long l0 = step % 3, l1 = (step + 1) % 3;
+        R a0[3][NSE], a1[3][NSE], ph[NSE];
+#pragma unroll
+        for (int m = 0; m < NSE; ++m) {
+            const int e = threadIdx.x + m * BLOCK;
+            if (e < NS) {
+                const int r0 = e % SG, r1 = (e / SG) % SG, r2 = e / (SG * SG);
+                const int gi = axis_index(L0 - 1 + r0, nx, S.bc[0]);
+                const int gj = axis_index(L1 - 1 + r1, ny, S.bc[1]);
+                const int gkk = axis_index(L2 - 1 + r2, nz, S.bc[2]);
+                const long long g = ((long long)gkk * ny + gj) * nx + gi;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    a0[c][m] = ((const R *)ar.pot[l0][c] + S.cell0)[g];
+                    a1[c][m] = ((const R *)ar.pot[l1][c] + S.cell0)[g];
+                }
+                ph[m] = ((const R *)ar.pot[l0][3] + S.cell0)[g];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NSE; ++m) {
+            const int e = threadIdx.x + m * BLOCK;
+            if (e < NS) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    stg[c][e] = a1[c][m] - a0[c][m];
+                    stg[3 + c][e] = a0[c][m] + a1[c][m];
+                }
+                stg[6][e] = ph[m];
+            }
+        }
+    }
+    __syncthreads();
     {
         const R kE = (R)S.kE, kB = (R)S.kB;
         const R hidt = (R)(0.5 * S.inv_dt);
         const R q2x = (R)(0.25 * S.inv_2d[0]), q2y = (R)(0.25 * S.inv_2d[1]),
                 q2z = (R)(0.25 * S.inv_2d[2]);
         const R i2x = (R)S.inv_2d[0], i2y = (R)S.inv_2d[1], i2z = (R)S.inv_2d[2];
-        const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
-        constexpr int OX = 1, OY = SG, OZ = SG * SG;
-        R E[VPT][3], B[VPT][3];
-        int sp[VPT];
-        bool val[VPT];
+        R EB[VPT][6];
 #pragma unroll
         for (int m = 0; m < VPT; ++m) {
             const int v = threadIdx.x + m * BLOCK;
             const int vi = v % TILE_VERT, vj = (v / TILE_VERT) % TILE_VERT,
                       vk = v / (TILE_VERT * TILE_VERT);
-            val[m] = v < NV && vertex_valid(S, L0 + vi, L1 + vj, L2 + vk);
-            sp[m] = ((vk + 1) * SG + (vj + 1)) * SG + (vi + 1);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) E[m][a] = B[m][a] = (R)0;
-        }
-        auto stage_index = [&](int e) {
-            const int r0 = e % SG, r1 = (e / SG) % SG, r2 = e / (SG * SG);
-            const int gi = axis_index(L0 - 1 + r0, nx, S.bc[0]);
-            const int gj = axis_index(L1 - 1 + r1, ny, S.bc[1]);
-            const int gk = axis_index(L2 - 1 + r2, nz, S.bc[2]);
-            return ((long long)gk * ny + gj) * nx + gi;
-        };
-        const long long l0 = step % 3, l1 = (step + 1) % 3;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const R *A0 = (const R *)ar.pot[l0][c] + S.cell0;
-            const R *A1 = (const R *)ar.pot[l1][c] + S.cell0;
-            for (int e = threadIdx.x; e < NS; e += BLOCK) {
-                const long long g = stage_index(e);
-                const R a0 = A0[g], a1 = A1[g];
-                sD[e] = a1 - a0;
-                sS[e] = a0 + a1;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < VPT; ++m) {
-                if (!val[m]) continue;
-                const int p = sp[m];
-                if (c == 0) {
-                    E[m][0] -= hidt * (sD[p] + sD[p - OX]);
-                    B[m][1] += q2z * ((sS[p + OZ] + sS[p + OZ - OX]) - (sS[p - OZ] + sS[p - OZ - OX]));
-                    B[m][2] -= q2y * ((sS[p + OY] + sS[p + OY - OX]) - (sS[p - OY] + sS[p - OY - OX]));
-                } else if (c == 1) {
-                    E[m][1] -= hidt * (sD[p] + sD[p - OY]);
-                    B[m][2] += q2x * ((sS[p + OX] + sS[p + OX - OY]) - (sS[p - OX] + sS[p - OX - OY]));
-                    B[m][0] -= q2z * ((sS[p + OZ] + sS[p + OZ - OY]) - (sS[p - OZ] + sS[p - OZ - OY]));
-                } else {
-                    E[m][2] -= hidt * (sD[p] + sD[p - OZ]);
-                    B[m][0] += q2y * ((sS[p + OY] + sS[p + OY - OZ]) - (sS[p - OY] + sS[p - OY - OZ]));
-                    B[m][1] -= q2x * ((sS[p + OX] + sS[p + OX - OZ]) - (sS[p - OX] + sS[p - OX - OZ]));
-                }
-            }
-            __syncthreads();
-        }
-        {
-            const R *ph = (const R *)ar.pot[l0][3] + S.cell0;
-            for (int e = threadIdx.x; e < NS; e += BLOCK) sS[e] = ph[stage_index(e)];
-            __syncthreads();
-        }
-#pragma unroll
-        for (int m = 0; m < VPT; ++m) {
-            const int p = sp[m];
-            if (val[m]) {
-                E[m][0] -= (sS[p + OX] - sS[p - OX]) * i2x;
-                E[m][1] -= (sS[p + OY] - sS[p - OY]) * i2y;
-                E[m][2] -= (sS[p + OZ] - sS[p - OZ]) * i2z;
+            for (int a = 0; a < 6; ++a) EB[m][a] = (R)0;
+            if (v < NV && vertex_valid(S, L0 + vi, L1 + vj, L2 + vk)) {
+                const int p = ((vk + 1) * SG + (vj + 1)) * SG + (vi + 1);
+                const R *Dx = stg[0], *Dy = stg[1], *Dz = stg[2];
+                const R *Sx = stg[3], *Sy = stg[4], *Sz = stg[5], *P = stg[6];
+                // E = -dA/dt - grad phi
+                EB[m][0] = -hidt * (Dx[p] + Dx[p - OX]) - (P[p + OX] - P[p - OX]) * i2x;
+                EB[m][1] = -hidt * (Dy[p] + Dy[p - OY]) - (P[p + OY] - P[p - OY]) * i2y;
+                EB[m][2] = -hidt * (Dz[p] + Dz[p - OZ]) - (P[p + OZ] - P[p - OZ]) * i2z;
+                // B = mean over the two levels of curl A
+                EB[m][3] = q2y * ((Sz[p + OY] + Sz[p + OY - OZ]) - (Sz[p - OY] + Sz[p - OY - OZ])) -
+                           q2z * ((Sy[p + OZ] + Sy[p + OZ - OY]) - (Sy[p - OZ] + Sy[p - OZ - OY]));
+                EB[m][4] = q2z * ((Sx[p + OZ] + Sx[p + OZ - OX]) - (Sx[p - OZ] + Sx[p - OZ - OX])) -
+                           q2x * ((Sz[p + OX] + Sz[p + OX - OZ]) - (Sz[p - OX] + Sz[p - OX - OZ]));
+                EB[m][5] = q2x * ((Sy[p + OX] + Sy[p + OX - OY]) - (Sy[p - OX] + Sy[p - OX - OY])) -
+                           q2y * ((Sx[p + OY] + Sx[p + OY - OX]) - (Sx[p - OY] + Sx[p - OY - OX]));
             }
         }
         __syncthreads();  // the field table overwrites the staging buffers
@@ -564,115 +603,121 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
             if (v >= NV) continue;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                sF[a][v] = kE * E[m][a];
-                sF[3 + a][v] = kB * B[m][a];
+                sF[a][v] = kE * EB[m][a];
+                sF[3 + a][v] = kB * EB[m][3 + a];
             }
         }
     }
     __syncthreads();
 
-    int *__restrict__ key = ar.key[par];
-    R *__restrict__ o0 = (R *)ar.off[par][0];
-    R *__restrict__ o1 = (R *)ar.off[par][1];
-    R *__restrict__ o2 = (R *)ar.off[par][2];
-    R *__restrict__ u0 = (R *)ar.u[par][0];
-    R *__restrict__ u1 = (R *)ar.u[par][1];
-    R *__restrict__ u2 = (R *)ar.u[par][2];
     R *__restrict__ q0 = (R *)ar.ooff[0];
     R *__restrict__ q1 = (R *)ar.ooff[1];
     R *__restrict__ q2 = (R *)ar.ooff[2];
     const bool want_ke = S.mesh_every > 0 && ((step + 1) % S.mesh_every) == 0;
     const double t0 = ((double)step + 0.5) * S.dt;
 
-    for (int p = p_lo + threadIdx.x; p < p_hi; p += BLOCK) {
-        const int gk = key[p];
-        const int lkey = (gk - (int)S.key0) & (TILE_CELLS - 1);
-        const int li = lkey & 7, lj = (lkey >> 3) & 7, lk = lkey >> 6;
-        int c[3] = {L0 + li, L1 + lj, L2 + lk};
-        R f[3] = {o0[p], o1[p], o2[p]};
-        R u[3] = {u0[p], u1[p], u2[p]};
-        q0[p] = f[0];
-        q1[p] = f[1];
-        q2[p] = f[2];
-        // linear interpolation of the 6 kick-scaled components from LDS
-        R F[6];
-        {
-            const int b = (lk * TILE_VERT + lj) * TILE_VERT + li;
-            const R wx1 = f[0], wx0 = (R)1 - f[0], wy1 = f[1], wy0 = (R)1 - f[1];
-            const R wz1 = f[2], wz0 = (R)1 - f[2];
-            constexpr int DY = TILE_VERT, DZ = TILE_VERT * TILE_VERT;
+    // uniform trip count over the block: count_runs needs whole wavefronts
+    for (int base = p_lo; base < p_hi; base += BLOCK) {
+        const int p = base + threadIdx.x;
+        const bool active = p < p_hi;
+        int ngk = 0;
+        if (active) {
+            if (base != p_lo) {
+                gk = key[p];
+                f[0] = o0[p];
+                f[1] = o1[p];
+                f[2] = o2[p];
+                u[0] = u0[p];
+                u[1] = u1[p];
+                u[2] = u2[p];
+            }
+            const int lkey = (gk - (int)S.key0) & (TILE_CELLS - 1);
+            const int li = lkey & 7, lj = (lkey >> 3) & 7, lk = lkey >> 6;
+            int c[3] = {L0 + li, L1 + lj, L2 + lk};
+            q0[p] = f[0];
+            q1[p] = f[1];
+            q2[p] = f[2];
+            // linear interpolation of the 6 kick-scaled components from LDS
+            R F[6];
+            {
+                const int b = (lk * TILE_VERT + lj) * TILE_VERT + li;
+                const R wx1 = f[0], wx0 = (R)1 - f[0], wy1 = f[1], wy0 = (R)1 - f[1];
+                const R wz1 = f[2], wz0 = (R)1 - f[2];
+                constexpr int DY = TILE_VERT, DZ = TILE_VERT * TILE_VERT;
 #pragma unroll
-            for (int a = 0; a < 6; ++a) {
-                const R *g = sF[a];
-                const R x00 = wx0 * g[b] + wx1 * g[b + 1];
-                const R x10 = wx0 * g[b + DY] + wx1 * g[b + DY + 1];
-                const R x01 = wx0 * g[b + DZ] + wx1 * g[b + DZ + 1];
-                const R x11 = wx0 * g[b + DZ + DY] + wx1 * g[b + DZ + DY + 1];
-                F[a] = wz0 * (wy0 * x00 + wy1 * x10) + wz1 * (wy0 * x01 + wy1 * x11);
+                for (int a = 0; a < 6; ++a) {
+                    const R *g = sF[a];
+                    const R x00 = wx0 * g[b] + wx1 * g[b + 1];
+                    const R x10 = wx0 * g[b + DY] + wx1 * g[b + DY + 1];
+                    const R x01 = wx0 * g[b + DZ] + wx1 * g[b + DZ + 1];
+                    const R x11 = wx0 * g[b + DZ + DY] + wx1 * g[b + DZ + DY + 1];
+                    F[a] = wz0 * (wy0 * x00 + wy1 * x10) + wz1 * (wy0 * x01 + wy1 * x11);
+                }
+            }
+            const double ph_cell0 = S.kz_cell * (double)c[2] + S.phase_off;
+            for (int sub = 0; sub < S.nsub; ++sub) {
+                const double ts = t0 + sub * S.dtb;
+                const double y = S.origin[1] + ((double)c[1] + (double)f[1]) * S.d[1];
+                R Eu, Buy, Buz;
+                undulator_kick<R>(S, ph_cell0 + S.phase_rate * ts, f[2], y, Eu, Buy, Buz);
+                const R e0 = F[0] + Eu, e1 = F[1], e2 = F[2];
+                const R b0 = F[3], b1 = F[4] + Buy, b2 = F[5] + Buz;
+                // Boris: half kick, rotation, half kick
+                const R t1x = u[0] + e0, t1y = u[1] + e1, t1z = u[2] + e2;
+                const R ig = (R)1 / sqrt((R)1 + t1x * t1x + t1y * t1y + t1z * t1z);
+                const R bx = b0 * ig, by = b1 * ig, bz = b2 * ig;
+                const R t2x = t1x + (t1y * bz - t1z * by);
+                const R t2y = t1y + (t1z * bx - t1x * bz);
+                const R t2z = t1z + (t1x * by - t1y * bx);
+                const R fac = (R)2 / ((R)1 + bx * bx + by * by + bz * bz);
+                const R wx = fac * bx, wy = fac * by, wz = fac * bz;
+                u[0] = t1x + (t2y * wz - t2z * wy) + e0;
+                u[1] = t1y + (t2z * wx - t2x * wz) + e1;
+                u[2] = t1z + (t2x * wy - t2y * wx) + e2;
+                const R ginv = (R)1 / sqrt((R)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                f[0] += (R)S.cdtb_d[0] * u[0] * ginv;
+                f[1] += (R)S.cdtb_d[1] * u[1] * ginv;
+                f[2] += (R)S.cdtb_d[2] * u[2] * ginv;
+            }
+            bool ok = isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(f[0]) &&
+                      isfinite(f[1]) && isfinite(f[2]);
+            int nk = (int)S.nkeys;
+            // record of the start cell for the deposit: x inside the tile and
+            // the cell move per axis (-1, 0, 1; a move is below one cell)
+            int move = li;
+            if (ok) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const R fl = floor(f[a]);
+                    c[a] += (int)fl;
+                    f[a] -= fl;
+                    move |= ((int)fl + 1) << (3 + 2 * a);
+                    if (c[a] < 2 || c[a] > S.n[a] - 3) ok = false;  // lost
+                }
+                if (ok) nk = tile_key(S, c[0], c[1], c[2]);
+            } else {
+                atomicOr(&ar.flags[it.x], 1);
+            }
+            ar.okey[p] = ok ? move : OKEY_LOST;
+            ngk = (int)S.key0 + nk;
+            key[p] = ngk;
+            o0[p] = f[0];
+            o1[p] = f[1];
+            o2[p] = f[2];
+            u0[p] = u[0];
+            u1[p] = u[1];
+            u2[p] = u[2];
+            if (!ok || want_ke) {
+                const int pid = ar.id[par][p];
+                double ke = 0.0;
+                if (ok)
+                    ke = sqrt(1.0 + (double)u[0] * u[0] + (double)u[1] * u[1] +
+                              (double)u[2] * u[2]) -
+                         1.0;
+                ar.ke[S.part0 + pid] = ke;
             }
         }
-        const double ph_cell0 = S.kz_cell * (double)c[2] + S.phase_off;
-        for (int sub = 0; sub < S.nsub; ++sub) {
-            const double ts = t0 + sub * S.dtb;
-            const double y = S.origin[1] + ((double)c[1] + (double)f[1]) * S.d[1];
-            R Eu, Buy, Buz;
-            undulator_kick<R>(S, ph_cell0 + S.phase_rate * ts, f[2], y, Eu, Buy, Buz);
-            const R e0 = F[0] + Eu, e1 = F[1], e2 = F[2];
-            const R b0 = F[3], b1 = F[4] + Buy, b2 = F[5] + Buz;
-            // Boris: half kick, rotation, half kick
-            const R t1x = u[0] + e0, t1y = u[1] + e1, t1z = u[2] + e2;
-            const R ig = (R)1 / sqrt((R)1 + t1x * t1x + t1y * t1y + t1z * t1z);
-            const R bx = b0 * ig, by = b1 * ig, bz = b2 * ig;
-            const R t2x = t1x + (t1y * bz - t1z * by);
-            const R t2y = t1y + (t1z * bx - t1x * bz);
-            const R t2z = t1z + (t1x * by - t1y * bx);
-            const R fac = (R)2 / ((R)1 + bx * bx + by * by + bz * bz);
-            const R wx = fac * bx, wy = fac * by, wz = fac * bz;
-            u[0] = t1x + (t2y * wz - t2z * wy) + e0;
-            u[1] = t1y + (t2z * wx - t2x * wz) + e1;
-            u[2] = t1z + (t2x * wy - t2y * wx) + e2;
-            const R ginv = (R)1 / sqrt((R)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            f[0] += (R)S.cdtb_d[0] * u[0] * ginv;
-            f[1] += (R)S.cdtb_d[1] * u[1] * ginv;
-            f[2] += (R)S.cdtb_d[2] * u[2] * ginv;
-        }
-        bool ok = isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(f[0]) &&
-                  isfinite(f[1]) && isfinite(f[2]);
-        int nk = (int)S.nkeys;
-        // record of the start cell for the deposit: x inside the tile and the
-        // cell move per axis (-1, 0, 1; a move is below one cell per step)
-        int move = li;
-        if (ok) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const R fl = floor(f[a]);
-                c[a] += (int)fl;
-                f[a] -= fl;
-                move |= ((int)fl + 1) << (3 + 2 * a);
-                if (c[a] < 2 || c[a] > S.n[a] - 3) ok = false;  // lost
-            }
-            if (ok) nk = tile_key(S, c[0], c[1], c[2]);
-        } else {
-            atomicOr(&ar.flags[it.x], 1);
-        }
-        ar.okey[p] = move;
-        const int ngk = (int)S.key0 + nk;
-        key[p] = ngk;
-        o0[p] = f[0];
-        o1[p] = f[1];
-        o2[p] = f[2];
-        u0[p] = u[0];
-        u1[p] = u[1];
-        u2[p] = u[2];
-        atomicAdd(&ar.counts[ngk], 1);
-        if (!ok || want_ke) {
-            const int pid = ar.id[par][p];
-            double ke = 0.0;
-            if (ok)
-                ke = sqrt(1.0 + (double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]) -
-                     1.0;
-            ar.ke[S.part0 + pid] = ke;
-        }
+        count_runs(ar.counts, ngk, active);
     }
 }
 
@@ -683,38 +728,28 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
 //    exact.  One block owns the 8^3 vertices of a tile and visits every
 //    particle whose start cell lies in [L-2, L+8] per axis (those are all the
 //    particles that can reach the tile), adding only what lands on its own
-//    vertices.  Sums are fixed point in LDS: each term t (|t| <= 1) is scaled
-//    by 2^S, split into its nearest integer hi and the remainder scaled by
-//    2^LO_BITS, and both parts go to 64-bit integer accumulators.  Integer
+//    vertices.  A tile with no particle in its 27-tile neighbourhood has zero
+//    sources; it writes them only when per-tile flags say they are not zero
+//    already, so only the bunch's neighbourhood costs memory traffic.
+//    Sums are fixed point in LDS: each term t (|t| <= 1) is scaled by 2^S,
+//    rounded to an integer and added to a 64-bit accumulator.  Integer
 //    addition is associative, so the result does not depend on the order of
-//    the atomics; the resolution is 2^-(S + LO_BITS) of one particle's weight.
+//    the atomics.  S is chosen per tile from the number of particles the tile
+//    visits, S = min(50, 62 - ceil(log2(visits + 1))): no accumulator can
+//    overflow, and the resolution is 2^-S of one particle's weight (2^-50 for
+//    tiles below 4096 visits, finer than the rounding of the FP64 terms).
 //    The flush converts once and writes every vertex, zeros included.
 // ---------------------------------------------------------------------------
 
-// |lo| <= 2^31 per term and at most 2^31 terms per vertex: no overflow
-constexpr int LO_BITS = 32;
+constexpr double FX_SHIFT = 0x1.8p52;                      // 1.5 * 2^52
+constexpr long long FX_SHIFT_BITS = 0x4338000000000000LL;  // its bit pattern
+constexpr int FX_MAX_BITS = 50;                            // 2^S < 2^51
 
-// add t * 2^S as a (hi, lo) fixed-point pair; the float path keeps hi only
-// (its terms carry 24 bits, far below the 2^-S resolution of hi)
-template <typename R>
-__device__ __forceinline__ void fx_add(unsigned long long *hi, unsigned long long *lo, double t,
-                                       double scale)
+// v rounded to the nearest integer (ties to even) for |v| < 2^51: adding
+// 1.5 * 2^52 leaves the integer in the low mantissa bits
+__device__ __forceinline__ long long fx_round(double v)
 {
-    const double v = t * scale;
-    const double h = rint(v);
-    const long long lh = (long long)h;
-    if (lh) atomicAdd(hi, (unsigned long long)lh);
-    if (sizeof(R) == 8) {
-        const long long ll = __double2ll_rn((v - h) * 0x1p32);
-        if (ll) atomicAdd(lo, (unsigned long long)ll);
-    }
-}
-
-template <typename R>
-__device__ __forceinline__ double fx_value(unsigned long long hi, unsigned long long lo)
-{
-    if (sizeof(R) != 8) return (double)(long long)hi;
-    return (double)(long long)hi + (double)(long long)lo * 0x1p-32;
+    return __double_as_longlong(__dadd_rn(v, FX_SHIFT)) - FX_SHIFT_BITS;
 }
 
 template <typename R>
@@ -731,174 +766,288 @@ __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ si
     const int tX = t % S.nt[0], tY = (t / S.nt[0]) % S.nt[1], tZ = t / (S.nt[0] * S.nt[1]);
     const int L[3] = {tX * TILE, tY * TILE, tZ * TILE};
 
-    constexpr int NLO = sizeof(R) == 8 ? TILE_CELLS : 1;  // low words: double path only
-    __shared__ unsigned long long acc[4][TILE_CELLS], acl[4][NLO];
-    __shared__ int rstart[384], rlen[384], rpre[384];
+    constexpr int NENT = 363;  // 11 x 11 rows of start cells, up to 3 key ranges each
+    __shared__ unsigned long long acc[4][TILE_CELLS];
+    __shared__ int rstart[384], rpre[384];
+    // queues (0: particles that stay in their cell, 1: the others): particle
+    // index, packed start cell and move
+    __shared__ int qp[2][2 * BLOCK], qi[2][2 * BLOCK];
     __shared__ int wsum[BLOCK / 64];
-    __shared__ int any;
-    for (int e = threadIdx.x; e < 4 * TILE_CELLS; e += BLOCK) (&acc[0][0])[e] = 0ull;
-    for (int e = threadIdx.x; e < 4 * NLO; e += BLOCK) (&acl[0][0])[e] = 0ull;
-    if (threadIdx.x == 0) any = 0;
-    __syncthreads();
+    __shared__ int any, qn[2];
 
-    // skip the particle pass when the 27 surrounding tiles hold no particle
-    if (threadIdx.x < 27) {
-        const int dx = threadIdx.x % 3 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x / 9 - 1;
-        const int a = tX + dx, b = tY + dy, cc = tZ + dz;
-        if (a >= 0 && a < S.nt[0] && b >= 0 && b < S.nt[1] && cc >= 0 && cc < S.nt[2]) {
-            const long long g = S.key0 + (long long)((cc * S.nt[1] + b) * S.nt[0] + a) * TILE_CELLS;
-            if (offs[g + TILE_CELLS] != offs[g]) atomicOr(&any, 1);
-        }
+    R *J0 = (R *)ar.J[0] + S.cell0, *J1 = (R *)ar.J[1] + S.cell0, *J2 = (R *)ar.J[2] + S.cell0;
+    const int dst = init ? par : par ^ 1;
+    R *rho = (R *)ar.rho[dst] + S.cell0;
+    const long long sy = S.n[0], sz = (long long)S.n[0] * S.n[1];
+    const int tg = S.tile0 + t;
+
+    // No particle in the 27 surrounding tiles: the tile's sources are zero.
+    // They are written only if they still hold values from an earlier step.
+    // (The first deposit after loading particles has no push before it and
+    // takes every tile.)
+    if (threadIdx.x == 0) any = init;
+    __syncthreads();
+    if (!init && threadIdx.x < 27) {
+        const int a = tX + (int)threadIdx.x % 3 - 1, b = tY + ((int)threadIdx.x / 3) % 3 - 1,
+                  cc = tZ + (int)threadIdx.x / 9 - 1;
+        if (a >= 0 && a < S.nt[0] && b >= 0 && b < S.nt[1] && cc >= 0 && cc < S.nt[2] &&
+            ar.tocc[S.tile0 + (cc * S.nt[1] + b) * S.nt[0] + a] != 0)
+            atomicOr(&any, 1);
     }
     __syncthreads();
-
-    if (any) {
-        // particle ranges: rows of start cells (y, z) in [L-2, L+8], x-range
-        // [L-2, L+8] split at tile boundaries (at most 3 contiguous key ranges)
-        int mylen[2] = {0, 0};
-        for (int h = 0; h < 2; ++h) {
-            const int e = threadIdx.x * 2 + h;  // 121 rows x 3 pieces = 363 entries
-            int st = 0, ln = 0;
-            if (e < 363) {
-                const int row = e / 3, piece = e % 3;
-                const int cy = L[1] - 2 + row % 11, cz = L[2] - 2 + row / 11;
-                const int xa = max(L[0] - 2, 0), xb = min(L[0] + 8, S.n[0] - 1);
-                const int tx = tX - 1 + piece;
-                const int pa = max(xa, tx * TILE), pb = min(xb, tx * TILE + TILE - 1);
-                if (cy >= 0 && cy < S.n[1] && cz >= 0 && cz < S.n[2] && tx >= 0 &&
-                    tx < S.nt[0] && pa <= pb) {
-                    const long long ka = S.key0 + tile_key(S, pa, cy, cz);
-                    const long long kb = S.key0 + tile_key(S, pb, cy, cz);
-                    st = offs[ka];
-                    ln = offs[kb + 1] - st;
-                }
-                rstart[e] = st;
-                rlen[e] = ln;
+    if (!any) {
+        const bool zj = ar.jdirty[tg] != 0, zr = ar.rdirty[dst][tg] != 0;
+        if (zj || zr) {
+            for (int e = threadIdx.x; e < TILE_CELLS; e += BLOCK) {
+                const int vx = L[0] + (e & 7), vy = L[1] + ((e >> 3) & 7), vz = L[2] + (e >> 6);
+                if (vx >= S.n[0] || vy >= S.n[1] || vz >= S.n[2]) continue;
+                const long long g = vz * sz + vy * sy + vx;
+                if (zj) J0[g] = J1[g] = J2[g] = (R)0;
+                if (zr) rho[g] = (R)0;
             }
-            mylen[h] = ln;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                ar.jdirty[tg] = 0;
+                ar.rdirty[dst][tg] = 0;
+            }
         }
-        int total;
-        const int pre = block_excl_scan(mylen[0] + mylen[1], wsum, &total);
-        if (threadIdx.x * 2 < 363) rpre[threadIdx.x * 2] = pre;
-        if (threadIdx.x * 2 + 1 < 363) rpre[threadIdx.x * 2 + 1] = pre + mylen[0];
-        __syncthreads();
+        return;
+    }
 
-        const int *__restrict__ key = ar.key[par];
-        const R *__restrict__ n0 = (const R *)ar.off[par][0];
-        const R *__restrict__ n1 = (const R *)ar.off[par][1];
-        const R *__restrict__ n2 = (const R *)ar.off[par][2];
-        const int *__restrict__ okey = ar.okey;
-        const R *__restrict__ q0 = init ? n0 : (const R *)ar.ooff[0];
-        const R *__restrict__ q1 = init ? n1 : (const R *)ar.ooff[1];
-        const R *__restrict__ q2 = init ? n2 : (const R *)ar.ooff[2];
-        const double scale = S.fx_scale;
+    // particle ranges: rows of start cells (y, z) in [L-2, L+8], x-range
+    // [L-2, L+8] split at tile boundaries (at most 3 contiguous key ranges)
+    int mylen[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = threadIdx.x * 2 + h;
+        int st = 0, ln = 0;
+        if (e < NENT) {
+            const int row = e / 3, piece = e % 3;
+            const int cy = L[1] - 2 + row % 11, cz = L[2] - 2 + row / 11;
+            const int xa = max(L[0] - 2, 0), xb = min(L[0] + 8, S.n[0] - 1);
+            const int tx = tX - 1 + piece;
+            const int pa = max(xa, tx * TILE), pb = min(xb, tx * TILE + TILE - 1);
+            if (cy >= 0 && cy < S.n[1] && cz >= 0 && cz < S.n[2] && tx >= 0 && tx < S.nt[0] &&
+                pa <= pb) {
+                const long long ka = S.key0 + tile_key(S, pa, cy, cz);
+                const long long kb = S.key0 + tile_key(S, pb, cy, cz);
+                st = offs[ka];
+                ln = offs[kb + 1] - st;
+            }
+            rstart[e] = st;
+        }
+        mylen[h] = ln;
+    }
+    for (int e = threadIdx.x; e < 4 * TILE_CELLS; e += BLOCK) (&acc[0][0])[e] = 0ull;
+    if (threadIdx.x < 2) qn[threadIdx.x] = 0;
+    int total;
+    const int pre = block_excl_scan(mylen[0] + mylen[1], wsum, &total);
+    if (threadIdx.x * 2 < NENT) rpre[threadIdx.x * 2] = pre;
+    if (threadIdx.x * 2 + 1 < NENT) rpre[threadIdx.x * 2 + 1] = pre + mylen[0];
+    __syncthreads();
 
-        for (int w = threadIdx.x; w < total; w += BLOCK) {
-            int lo = 0, hi = 362;
+    const int lane = threadIdx.x & 63;
+    // fixed-point scale of this tile: at most `total` terms meet at a vertex
+    const int fx_bits = min(FX_MAX_BITS, 62 - (32 - __clz(total)));
+    const double scale = ldexp(1.0, fx_bits);
+    const R *__restrict__ n0 = (const R *)ar.off[par][0];
+    const R *__restrict__ n1 = (const R *)ar.off[par][1];
+    const R *__restrict__ n2 = (const R *)ar.off[par][2];
+    const R *__restrict__ q0 = init ? n0 : (const R *)ar.ooff[0];
+    const R *__restrict__ q1 = init ? n1 : (const R *)ar.ooff[1];
+    const R *__restrict__ q2 = init ? n2 : (const R *)ar.ooff[2];
+
+    // terms off the tile and zero terms are skipped
+    auto add = [&](int q, bool own, int e, double t) __attribute__((always_inline)) {
+        if (!own) return;
+        const long long v = fx_round(__dmul_rn(t, scale));  // scaling is exact
+        if (v) atomicAdd(&acc[q][e], (unsigned long long)v);
+    };
+
+    // One queued particle: its start cell and move (packed by the filter) and
+    // its start and end positions inside the cells.  For a particle that
+    // stays in its cell (nm true) the weights on the far vertex of each axis
+    // are zero and the loops over them are left out; the terms kept are the
+    // same expressions as in the general case.
+    auto deposit_one = [&](auto nm, int p, int info) __attribute__((always_inline)) {
+        constexpr bool NM = decltype(nm)::value;
+        constexpr int NB = NM ? 2 : 3;
+        const R f0[3] = {q0[p], q1[p], q2[p]};
+        const R f1[3] = {n0[p], n1[p], n2[p]};
+        int base[3];
+        R S0[3][3], DS[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int c0 = ((info >> (4 * a)) & 15) - 2;        // start cell - L
+            const int mv = NM ? 0 : ((info >> (12 + 2 * a)) & 3) - 1;  // cell move
+            base[a] = min(c0, c0 + mv);
+            // the start (end) cell is base or base + 1
+            const bool s0 = mv >= 0, s1 = mv <= 0;
+            R S1[3];
+            S0[a][0] = s0 ? (R)1 - f0[a] : (R)0;
+            S0[a][1] = s0 ? f0[a] : (R)1 - f0[a];
+            S0[a][2] = s0 ? (R)0 : f0[a];
+            S1[0] = s1 ? (R)1 - f1[a] : (R)0;
+            S1[1] = s1 ? f1[a] : (R)1 - f1[a];
+            S1[2] = s1 ? (R)0 : f1[a];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) DS[a][m] = S1[m] - S0[a][m];
+        }
+        // the 3x3x3 box [base, base+2] in tile-local vertex coordinates;
+        // J_l sits on the edges from vertex a to a + 1 along l (a = 0, 1)
+        auto own = [](int v) { return v >= 0 && v < TILE; };
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int pa = (l + 1) % 3, ra = (l + 2) % 3;
+#pragma unroll
+            for (int bb = 0; bb < NB; ++bb)
+#pragma unroll
+                for (int ee = 0; ee < NB; ++ee) {
+                    const R Y = S0[pa][bb] * S0[ra][ee] + (R)0.5 * DS[pa][bb] * S0[ra][ee] +
+                                (R)0.5 * S0[pa][bb] * DS[ra][ee] +
+                                DS[pa][bb] * DS[ra][ee] * (R)(1.0 / 3.0);
+                    R run = 0;
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        run += DS[l][a] * Y;
+                        int v[3];
+                        v[l] = base[l] + a;
+                        v[pa] = base[pa] + bb;
+                        v[ra] = base[ra] + ee;
+                        add(l, own(v[0]) && own(v[1]) && own(v[2]),
+                            (v[2] * TILE + v[1]) * TILE + v[0], (double)run);
+                    }
+                }
+        }
+        // rho^{s+3/2} at the 8 vertices of the end cell
+        int e1[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            e1[a] = ((info >> (4 * a)) & 15) - 2 + (NM ? 0 : ((info >> (12 + 2 * a)) & 3) - 1);
+#pragma unroll
+        for (int K = 0; K < 2; ++K)
+#pragma unroll
+            for (int J = 0; J < 2; ++J)
+#pragma unroll
+                for (int I = 0; I < 2; ++I) {
+                    const int vx = e1[0] + I, vy = e1[1] + J, vz = e1[2] + K;
+                    const R w8 = (I ? f1[0] : (R)1 - f1[0]) * (J ? f1[1] : (R)1 - f1[1]) *
+                                 (K ? f1[2] : (R)1 - f1[2]);
+                    add(3, own(vx) && own(vy) && own(vz), (vz * TILE + vy) * TILE + vx,
+                        (double)w8);
+                }
+    };
+
+    // Candidates in chunks of one per thread.  The filter reads only the
+    // 4-byte move record, keeps the particles whose vertex support
+    // [min(c0, c1), max(c0, c1) + 1] meets the tile on every axis, and
+    // appends them to an LDS queue; a full block's worth is deposited at a
+    // time.  The queue order varies between runs, the integer sums do not.
+    const int *__restrict__ okey = ar.okey;
+    const int *__restrict__ key = ar.key[par];
+    for (int g = 0; g < total; g += BLOCK) {
+        const int w = g + threadIdx.x;
+        bool take = false;
+        int p = 0, info = 0;
+        if (w < total) {
+            int lo = 0, hi = NENT - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (rpre[mid] <= w) lo = mid;
                 else hi = mid - 1;
             }
-            const int p = rstart[lo] + (w - rpre[lo]);
-            const int nk = key[p] - (int)S.key0;
-            if (nk >= S.nkeys) continue;  // lost this step: deposits nothing
-            // start cell from the range (row y, z and x tile) and the x bits;
-            // end cell = start cell + recorded move
-            const int row = lo / 3;
-            const int rec = init ? (nk & 7) : okey[p];
-            int c0[3], c1[3];
-            c0[0] = (tX - 1 + lo % 3) * TILE + (rec & 7);
-            c0[1] = L[1] - 2 + row % 11;
-            c0[2] = L[2] - 2 + row / 11;
-            bool reach = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                c1[a] = c0[a] + (init ? 0 : ((rec >> (3 + 2 * a)) & 3) - 1);
-                const int b = min(c0[a], c1[a]);
-                reach = reach && b + 2 >= L[a] && b <= L[a] + TILE - 1;
+            p = rstart[lo] + (w - rpre[lo]);
+            int rec;
+            if (init) {
+                const int nk = key[p] - (int)S.key0;
+                rec = nk >= S.nkeys ? OKEY_LOST : (nk & 7) | (0x15 << 3);  // no move
+            } else {
+                rec = okey[p];
             }
-            if (!reach) continue;  // the 3^3 box of this move misses the tile
-            const R f0[3] = {q0[p], q1[p], q2[p]};
-            const R f1[3] = {n0[p], n1[p], n2[p]};
-            int base[3];
-            R S0[3][3], DS[3][3], S1[3][3];
+            if (!(rec & OKEY_LOST)) {
+                const int row = lo / 3;
+                const int c0[3] = {(tX - 1 + lo % 3) * TILE + (rec & 7) - L[0],
+                                   row % 11 - 2, row / 11 - 2};
+                take = true;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                base[a] = min(c0[a], c1[a]);
-                // the start (end) cell is base or base + 1
-                const bool s0 = c0[a] == base[a], s1 = c1[a] == base[a];
-                S0[a][0] = s0 ? (R)1 - f0[a] : (R)0;
-                S0[a][1] = s0 ? f0[a] : (R)1 - f0[a];
-                S0[a][2] = s0 ? (R)0 : f0[a];
-                S1[a][0] = s1 ? (R)1 - f1[a] : (R)0;
-                S1[a][1] = s1 ? f1[a] : (R)1 - f1[a];
-                S1[a][2] = s1 ? (R)0 : f1[a];
-#pragma unroll
-                for (int m = 0; m < 3; ++m) DS[a][m] = S1[a][m] - S0[a][m];
+                for (int a = 0; a < 3; ++a) {
+                    const int mv = ((rec >> (3 + 2 * a)) & 3) - 1;
+                    const int mn = min(c0[a], c0[a] + mv), mx = max(c0[a], c0[a] + mv);
+                    take = take && mx + 1 >= 0 && mn <= TILE - 1;
+                    info |= (c0[a] + 2) << (4 * a);
+                    info |= (mv + 1) << (12 + 2 * a);
+                }
             }
-            // the 3x3x3 box [base, base+2] in tile-local vertex coordinates
-            const int b0 = base[0] - L[0], b1 = base[1] - L[1], b2 = base[2] - L[2];
-            auto own = [](int v) { return v >= 0 && v < TILE; };
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                const int pa = (l + 1) % 3, ra = (l + 2) % 3;
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-                    for (int ee = 0; ee < 3; ++ee) {
-                        const R Y = S0[pa][bb] * S0[ra][ee] + (R)0.5 * DS[pa][bb] * S0[ra][ee] +
-                                    (R)0.5 * S0[pa][bb] * DS[ra][ee] +
-                                    DS[pa][bb] * DS[ra][ee] * (R)(1.0 / 3.0);
-                        R run = 0;
-#pragma unroll
-                        for (int a = 0; a < 2; ++a) {
-                            run += DS[l][a] * Y;
-                            int v[3];
-                            v[l] = a;
-                            v[pa] = bb;
-                            v[ra] = ee;
-                            const int vx = b0 + v[0], vy = b1 + v[1], vz = b2 + v[2];
-                            if (own(vx) && own(vy) && own(vz)) {
-                                const int e = (vz * TILE + vy) * TILE + vx;
-                                fx_add<R>(&acc[l][e], &acl[l][e], (double)run, scale);
-                            }
-                        }
-                    }
-            }
-            // rho^{s+3/2} at the 8 vertices of the end cell
-            const int e0 = c1[0] - L[0], e1 = c1[1] - L[1], e2 = c1[2] - L[2];
-#pragma unroll
-            for (int K = 0; K < 2; ++K)
-#pragma unroll
-                for (int J = 0; J < 2; ++J)
-#pragma unroll
-                    for (int I = 0; I < 2; ++I) {
-                        const int vx = e0 + I, vy = e1 + J, vz = e2 + K;
-                        if (own(vx) && own(vy) && own(vz)) {
-                            const R w8 = (I ? f1[0] : (R)1 - f1[0]) * (J ? f1[1] : (R)1 - f1[1]) *
-                                         (K ? f1[2] : (R)1 - f1[2]);
-                            const int e = (vz * TILE + vy) * TILE + vx;
-                            fx_add<R>(&acc[3][e], &acl[3][e], (double)w8, scale);
-                        }
-                    }
         }
+        const bool still = info == (0x15 << 12) + (info & 0xfff);  // no move on any axis
+#pragma unroll
+        for (int Q = 0; Q < 2; ++Q) {
+            const bool mine = take && (still == (Q == 0));
+            const unsigned long long m = __ballot(mine);
+            int wbase = 0;
+            if (lane == 0 && m) wbase = atomicAdd(&qn[Q], __popcll(m));
+            wbase = __shfl(wbase, 0);
+            if (mine) {
+                const int pos = wbase + __popcll(m & ((1ull << lane) - 1ull));
+                qp[Q][pos] = p;
+                qi[Q][pos] = info;
+            }
+        }
+        __syncthreads();
+        // a full block's worth of one queue at a time; at the end, the rest
+        const bool last = g + BLOCK >= total;
+        auto drain = [&](auto nm) __attribute__((always_inline)) {
+            constexpr int Q = decltype(nm)::value ? 0 : 1;
+            const int n = qn[Q];
+            const int cnt = last ? n : (n >= BLOCK ? BLOCK : 0);
+            if (cnt == 0) return;  // uniform
+            // up to two entries per thread, read before the rest moves down
+            const int e0 = threadIdx.x, e1 = threadIdx.x + BLOCK;
+            int p0 = 0, i0 = 0, p1 = 0, i1 = 0;
+            if (e0 < cnt) {
+                p0 = qp[Q][e0];
+                i0 = qi[Q][e0];
+            }
+            if (e1 < cnt) {
+                p1 = qp[Q][e1];
+                i1 = qi[Q][e1];
+            }
+            if (!last) {
+                __syncthreads();
+                if ((int)threadIdx.x < n - BLOCK) {
+                    qp[Q][threadIdx.x] = qp[Q][BLOCK + threadIdx.x];
+                    qi[Q][threadIdx.x] = qi[Q][BLOCK + threadIdx.x];
+                }
+                if (threadIdx.x == 0) qn[Q] = n - BLOCK;
+            }
+            const int mine = (e0 < cnt) + (e1 < cnt);
+            for (int j = 0; j < mine; ++j) {
+                deposit_one(nm, p0, i0);
+                p0 = p1;
+                i0 = i1;
+            }
+        };
+        drain(std::integral_constant<bool, true>());
+        drain(std::integral_constant<bool, false>());
         __syncthreads();
     }
 
     // flush: every owned vertex, zeros included
-    R *J0 = (R *)ar.J[0] + S.cell0, *J1 = (R *)ar.J[1] + S.cell0, *J2 = (R *)ar.J[2] + S.cell0;
-    R *rho = (R *)ar.rho[init ? par : par ^ 1] + S.cell0;
-    const long long sy = S.n[0], sz = (long long)S.n[0] * S.n[1];
+    const double inv = ldexp(1.0, -fx_bits);
+    const double ju0 = S.J_unit[0] * inv, ju1 = S.J_unit[1] * inv, ju2 = S.J_unit[2] * inv,
+                 ru = S.rho_unit * inv;
+    if (threadIdx.x == 0) {
+        ar.jdirty[tg] = 1;
+        ar.rdirty[dst][tg] = 1;
+    }
     for (int e = threadIdx.x; e < TILE_CELLS; e += BLOCK) {
         const int vx = L[0] + (e & 7), vy = L[1] + ((e >> 3) & 7), vz = L[2] + (e >> 6);
         if (vx >= S.n[0] || vy >= S.n[1] || vz >= S.n[2]) continue;
         const long long g = vz * sz + vy * sy + vx;
-        const int el = NLO == 1 ? 0 : e;
-        J0[g] = (R)(fx_value<R>(acc[0][e], acl[0][el]) * S.J_unit[0]);
-        J1[g] = (R)(fx_value<R>(acc[1][e], acl[1][el]) * S.J_unit[1]);
-        J2[g] = (R)(fx_value<R>(acc[2][e], acl[2][el]) * S.J_unit[2]);
-        rho[g] = (R)(fx_value<R>(acc[3][e], acl[3][el]) * S.rho_unit);
+        J0[g] = (R)((double)(long long)acc[0][e] * ju0);
+        J1[g] = (R)((double)(long long)acc[1][e] * ju1);
+        J2[g] = (R)((double)(long long)acc[2][e] * ju2);
+        rho[g] = (R)((double)(long long)acc[3][e] * ru);
     }
 }
 
@@ -976,11 +1125,31 @@ template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_scatter(Arena ar, long long np)
 {
     const long long p = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= np) return;
+    const bool active = p < np;  // every lane stays: the run logic is per wavefront
     const long long step = *ar.d_step;
     const int s = (int)(step & 1), d = s ^ 1;
-    const int g = ar.key[s][p];
-    const int dst = ar.offs[d][g] + atomicSub(&ar.counts[g], 1) - 1;
+    const int lane = threadIdx.x & 63;
+    const int g = active ? ar.key[s][p] : -1;
+    const int prev = __shfl_up(g, 1, 64);
+    const bool head = active && (lane == 0 || prev != g);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long act = __ballot(active);
+    // one atomic per run of equal keys; the run takes the slots just below
+    // the old count, in lane order
+    int base = 0;
+    if (head) {
+        const unsigned long long later = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+        const int next = later ? __ffsll((long long)later) - 1 : 64;
+        const unsigned long long span =
+            (next == 64 ? ~0ull : ((1ull << next) - 1)) & (~0ull << lane);
+        const int len = __popcll(act & span);
+        base = atomicSub(&ar.counts[g], len) - len;
+    }
+    const unsigned long long upto = heads & ((2ull << lane) - 1);
+    const int hl = upto ? 63 - __clzll((long long)upto) : 0;
+    base = __shfl(base, hl, 64);
+    if (!active) return;
+    const int dst = ar.offs[d][g] + base + __popcll(act & ((2ull << lane) - 1) & ~((1ull << hl) - 1)) - 1;
     ar.key[d][dst] = g;
     ar.id[d][dst] = ar.id[s][p];
 #pragma unroll

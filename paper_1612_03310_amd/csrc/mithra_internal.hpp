@@ -21,6 +21,7 @@ constexpr int SCAN_PER_THREAD = 16;
 constexpr int SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
 constexpr int MESH_DIAG_PER_THREAD = 8;
 constexpr int KIN_PER_THREAD = 8;
+constexpr int OKEY_LOST = 1 << 9;
 
 enum Kind { K_STENCIL = 0, K_BOUNDARY, K_PUSH, K_DEPOSIT, K_SCAN, K_SCATTER, K_DIAG };
 
@@ -36,6 +37,7 @@ struct SimDev {
     long long cell0;    // offset of this simulation in the mesh arenas
     long long key0;     // offset in the key arenas (nkeys + 1 entries)
     long long part0;    // offset in the particle arenas
+    int tile0;          // offset in the per-tile arrays
     // diagnostics
     int probe[3];
     int kp;
@@ -59,8 +61,7 @@ struct SimDev {
     // undulator in the rest frame
     double ku, kz_cell, phase_off, phase_rate;
     double EuK, BuyK, BuzK;  // kick-scaled amplitudes of E_x, B_y, B_z
-    // deposition (fixed point with 2^S units)
-    double fx_scale;
+    // deposition: rho and J per unit of particle weight
     double rho_unit, J_unit[3];
     // diagnostics (SI)
     double dV, mc2, dxdy_mu0, eps0_half, inv_2mu0;
@@ -78,12 +79,16 @@ struct Arena {
     void *u[2][3];
     int *id[2];
     int *okey;          // start of the step, for the deposit: x inside the tile (3 bits)
-                        // and the cell move per axis (2 bits each, move + 1)
+                        // and the cell move per axis (2 bits each, move + 1), or
+                        // OKEY_LOST for a particle lost in the step
     void *ooff[3];
     double *ke;         // (gamma - 1) by particle id, for the kinetic-energy sum
     double *partial;    // diagnostic partial sums
     double *ring;       // diagnostic rows
     int *flags;         // per simulation: a non-finite value was produced
+    int *tocc;          // per tile: particles at the start of the step (written by the push)
+    int *jdirty;        // per tile: J holds non-zero values
+    int *rdirty[2];     // per tile: rho[b] holds non-zero values
     long long *d_step;  // completed steps (all simulations advance together)
 };
 

@@ -281,14 +281,10 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     S.BuyK = S.kB * h.gamma0 * h.B0;
     S.BuzK = S.kB * h.B0;
     const double dV = m.d[0] * m.d[1] * m.d[2];
-    const long long np = h.loaded ? (long long)h.alive.size() : 0;
-    int bits = 0;
-    while ((1LL << bits) < np + 1) ++bits;
-    const int Sbits = 62 - bits;
-    S.fx_scale = std::ldexp(1.0, Sbits);
-    const double inv = std::ldexp(1.0, -Sbits);
-    S.rho_unit = q / dV * inv;
-    for (int a = 0; a < 3; ++a) S.J_unit[a] = -q * m.d[a] / (dV * h.dt) * inv;
+    // deposit units per particle weight (the fixed-point scale is applied
+    // per tile by the deposit)
+    S.rho_unit = q / dV;
+    for (int a = 0; a < 3; ++a) S.J_unit[a] = -q * m.d[a] / (dV * h.dt);
     S.dV = dV;
     S.mc2 = mm * C_LIGHT * C_LIGHT;
     S.dxdy_mu0 = m.d[0] * m.d[1] / MU0;
@@ -334,6 +330,16 @@ static void stencil_items(const Batch &b, int tx, int ty, int kz, std::vector<in
             for (int y = 0; y < by; ++y)
                 for (int x = 0; x < bx; ++x) out.push_back(make_int4(s, x, y, z));
     }
+}
+
+// The deposit skips rewriting zeros into tiles whose sources are known to be
+// zero; after any write from the host every tile is taken as non-zero.
+static hipError_t mark_sources_dirty(Batch &b)
+{
+    const size_t tb = sizeof(int) * std::max(b.n_tiles, 1);
+    hipError_t e = hipMemsetAsync(b.ar.jdirty, 1, tb, b.stream);
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) e = hipMemsetAsync(b.ar.rdirty[r], 1, tb, b.stream);
+    return e;
 }
 
 static mithra_status build_tables(Batch &b)
@@ -385,6 +391,7 @@ static mithra_status build_tables(Batch &b)
     for (int s = 0; s < b.nsim; ++s) {
         SimDev &S = b.sd[s];
         const int nt = S.nt[0] * S.nt[1] * S.nt[2];
+        S.tile0 = (int)tiles.size();
         for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(s, t));
         const long long ncell = (long long)S.n[0] * S.n[1] * S.n[2];
         S.nb_plane = (S.n[0] * S.n[1] + BLOCK - 1) / BLOCK;
@@ -414,8 +421,16 @@ static mithra_status build_tables(Batch &b)
     b.ar.partial = (double *)dev_alloc(b, sizeof(double) * std::max(slot, 1), b.mem_tab);
     b.n_scan_blocks = (int)((b.total_keys + SCAN_CHUNK - 1) / SCAN_CHUNK);
     b.d_bsum = (int *)dev_alloc(b, sizeof(int) * std::max(b.n_scan_blocks, 1), b.mem_tab);
-    if (!b.ar.partial || !b.d_bsum) return fail(MITHRA_ENOMEM, "device allocation failed");
+    const size_t tb = sizeof(int) * std::max(b.n_tiles, 1);
+    b.ar.tocc = (int *)dev_alloc(b, tb, b.mem_tab);
+    b.ar.jdirty = (int *)dev_alloc(b, tb, b.mem_tab);
+    for (int r = 0; r < 2; ++r) b.ar.rdirty[r] = (int *)dev_alloc(b, tb, b.mem_tab);
+    if (!b.ar.partial || !b.d_bsum || !b.ar.tocc || !b.ar.jdirty || !b.ar.rdirty[0] ||
+        !b.ar.rdirty[1])
+        return fail(MITHRA_ENOMEM, "device allocation failed");
     HIP_TRY(hipMemsetAsync(b.ar.partial, 0, sizeof(double) * std::max(slot, 1), b.stream));
+    HIP_TRY(hipMemsetAsync(b.ar.tocc, 0, tb, b.stream));
+    HIP_TRY(mark_sources_dirty(b));
     HIP_TRY(hipMemcpyAsync(b.d_sims, b.sd.data(), sizeof(SimDev) * b.nsim, hipMemcpyHostToDevice,
                            b.stream));
     HIP_TRY(hipStreamSynchronize(b.stream));
@@ -927,6 +942,8 @@ static mithra_status set_field(Batch &b, int s, int which, const double *host)
         std::vector<float> tmp(host, host + ncell);
         HIP_TRY(hipMemcpy(dst, tmp.data(), sizeof(float) * ncell, hipMemcpyHostToDevice));
     }
+    HIP_TRY(mark_sources_dirty(b));
+    HIP_TRY(hipStreamSynchronize(b.stream));
     return MITHRA_OK;
 }
 
@@ -1310,6 +1327,8 @@ static mithra_status set_state_impl(Batch &b, const void *blob, size_t bytes)
     HIP_TRY(hipMemcpy((char *)b.ar.rho[s & 1] + off, w, mesh_bytes, hipMemcpyHostToDevice));
     w += mesh_bytes;
     HIP_TRY(hipMemcpy((char *)b.ar.rho[(s + 1) & 1] + off, w, mesh_bytes, hipMemcpyHostToDevice));
+    HIP_TRY(mark_sources_dirty(b));
+    HIP_TRY(hipStreamSynchronize(b.stream));
     h.read_step = s;
     return MITHRA_OK;
 }
