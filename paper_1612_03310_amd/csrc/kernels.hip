@@ -26,6 +26,18 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Particle work is concentrated where the bunch is.  The tiles are dealt to
+// the XCDs in chunks (a few tile layers along z): XCD x takes chunks x, x + 8,
+// x + 16, ..., so every XCD gets a share of the dense region while the tiles
+// of a chunk still share halo lines in one L2.  The grid is padded to whole
+// rounds of 8 chunks; blocks past the last tile get -1.
+__device__ __forceinline__ int tile_deal(int b, int nb, int chunk)
+{
+    const int x = b & 7, i = b >> 3;
+    const long long t = (long long)(x + 8 * (i / chunk)) * chunk + i % chunk;
+    return t < nb ? (int)t : -1;
+}
+
 // index along an axis, wrapped on a periodic axis, clamped otherwise (clamped
 // values are only ever read by points that do not use them)
 __device__ __forceinline__ int axis_index(int v, int n, int periodic)
@@ -471,9 +483,12 @@ __device__ __forceinline__ void count_runs(int *counts, int key, bool active)
 
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
-                                                 const int2 *__restrict__ items, Arena ar)
+                                                 const int2 *__restrict__ items, int nitems,
+                                                 int chunk, Arena ar)
 {
-    const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const int ti = tile_deal(blockIdx.x, nitems, chunk);
+    if (ti < 0) return;
+    const int2 it = items[ti];
     const SimDev &S = sims[it.x];
     const long long step = *ar.d_step;
     const int par = (int)(step & 1);
@@ -486,12 +501,19 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
     }
     const long long g0 = S.key0 + (long long)it.y * TILE_CELLS;
     const int p_lo = offs[g0], p_hi = offs[g0 + TILE_CELLS];
-    if (threadIdx.x == 0) ar.tocc[S.tile0 + it.y] = p_hi - p_lo;  // for the deposit
     if (p_lo == p_hi) return;
 
     const int t = it.y;
     const int L0 = (t % S.nt[0]) * TILE, L1 = ((t / S.nt[0]) % S.nt[1]) * TILE,
               L2 = (t / (S.nt[0] * S.nt[1])) * TILE;
+    if (threadIdx.x < 27) {
+        // the deposit of the tiles around this one has work
+        const int a = L0 / TILE + (int)threadIdx.x % 3 - 1,
+                  b = L1 / TILE + ((int)threadIdx.x / 3) % 3 - 1,
+                  cc = L2 / TILE + (int)threadIdx.x / 9 - 1;
+        if (a >= 0 && a < S.nt[0] && b >= 0 && b < S.nt[1] && cc >= 0 && cc < S.nt[2])
+            ar.tact[S.tile0 + (cc * S.nt[1] + b) * S.nt[0] + a] = 1;
+    }
 
     int *__restrict__ key = ar.key[par];
     R *__restrict__ o0 = (R *)ar.off[par][0];
@@ -754,65 +776,60 @@ __device__ __forceinline__ long long fx_round(double v)
 
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ sims,
-                                                    const int2 *__restrict__ items, Arena ar,
-                                                    int init)
+                                                    const int2 *__restrict__ items, int nitems,
+                                                    int chunk, Arena ar, int init)
 {
-    const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    const SimDev &S = sims[it.x];
+    // The tile table lists the tiles of all simulations in order, so the
+    // entry index is the global tile index.  A tile with no particle in its
+    // 27-tile neighbourhood (flag set by the push) has zero sources; it writes
+    // them only if they still hold values from an earlier step.  The flags,
+    // the table entry and the step counter are read in one round trip.  (The
+    // first deposit after loading particles has no push before it and takes
+    // every tile.)
+    const int tg = tile_deal(blockIdx.x, nitems, chunk);
+    if (tg < 0) return;
+    const int act = ar.tact[tg];
+    const int jd = ar.jdirty[tg], rd0 = ar.rdirty[0][tg], rd1 = ar.rdirty[1][tg];
+    const int2 it = items[tg];
     const long long step = *ar.d_step;
     const int par = (int)(step & 1);
+    const int dst = init ? par : par ^ 1;
+    const bool zj = jd != 0, zr = (dst ? rd1 : rd0) != 0;
+    if (!init && !act && !zj && !zr) return;
+
+    const SimDev &S = sims[it.x];
     const int *__restrict__ offs = ar.offs[par];
     const int t = it.y;
     const int tX = t % S.nt[0], tY = (t / S.nt[0]) % S.nt[1], tZ = t / (S.nt[0] * S.nt[1]);
     const int L[3] = {tX * TILE, tY * TILE, tZ * TILE};
+    R *J0 = (R *)ar.J[0] + S.cell0, *J1 = (R *)ar.J[1] + S.cell0, *J2 = (R *)ar.J[2] + S.cell0;
+    R *rho = (R *)ar.rho[dst] + S.cell0;
+    const long long sy = S.n[0], sz = (long long)S.n[0] * S.n[1];
+
+    if (!init && !act) {
+        for (int e = threadIdx.x; e < TILE_CELLS; e += BLOCK) {
+            const int vx = L[0] + (e & 7), vy = L[1] + ((e >> 3) & 7), vz = L[2] + (e >> 6);
+            if (vx >= S.n[0] || vy >= S.n[1] || vz >= S.n[2]) continue;
+            const long long g = vz * sz + vy * sy + vx;
+            if (zj) J0[g] = J1[g] = J2[g] = (R)0;
+            if (zr) rho[g] = (R)0;
+        }
+        if (threadIdx.x == 0) {
+            ar.jdirty[tg] = 0;
+            ar.rdirty[dst][tg] = 0;
+        }
+        return;
+    }
 
     constexpr int NENT = 363;  // 11 x 11 rows of start cells, up to 3 key ranges each
+    constexpr int QCAP = 3 * BLOCK;
     __shared__ unsigned long long acc[4][TILE_CELLS];
     __shared__ int rstart[384], rpre[384];
     // queues (0: particles that stay in their cell, 1: the others): particle
     // index, packed start cell and move
-    __shared__ int qp[2][2 * BLOCK], qi[2][2 * BLOCK];
+    __shared__ int qp[2][QCAP], qi[2][QCAP];
     __shared__ int wsum[BLOCK / 64];
-    __shared__ int any, qn[2];
-
-    R *J0 = (R *)ar.J[0] + S.cell0, *J1 = (R *)ar.J[1] + S.cell0, *J2 = (R *)ar.J[2] + S.cell0;
-    const int dst = init ? par : par ^ 1;
-    R *rho = (R *)ar.rho[dst] + S.cell0;
-    const long long sy = S.n[0], sz = (long long)S.n[0] * S.n[1];
-    const int tg = S.tile0 + t;
-
-    // No particle in the 27 surrounding tiles: the tile's sources are zero.
-    // They are written only if they still hold values from an earlier step.
-    // (The first deposit after loading particles has no push before it and
-    // takes every tile.)
-    if (threadIdx.x == 0) any = init;
-    __syncthreads();
-    if (!init && threadIdx.x < 27) {
-        const int a = tX + (int)threadIdx.x % 3 - 1, b = tY + ((int)threadIdx.x / 3) % 3 - 1,
-                  cc = tZ + (int)threadIdx.x / 9 - 1;
-        if (a >= 0 && a < S.nt[0] && b >= 0 && b < S.nt[1] && cc >= 0 && cc < S.nt[2] &&
-            ar.tocc[S.tile0 + (cc * S.nt[1] + b) * S.nt[0] + a] != 0)
-            atomicOr(&any, 1);
-    }
-    __syncthreads();
-    if (!any) {
-        const bool zj = ar.jdirty[tg] != 0, zr = ar.rdirty[dst][tg] != 0;
-        if (zj || zr) {
-            for (int e = threadIdx.x; e < TILE_CELLS; e += BLOCK) {
-                const int vx = L[0] + (e & 7), vy = L[1] + ((e >> 3) & 7), vz = L[2] + (e >> 6);
-                if (vx >= S.n[0] || vy >= S.n[1] || vz >= S.n[2]) continue;
-                const long long g = vz * sz + vy * sy + vx;
-                if (zj) J0[g] = J1[g] = J2[g] = (R)0;
-                if (zr) rho[g] = (R)0;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                ar.jdirty[tg] = 0;
-                ar.rdirty[dst][tg] = 0;
-            }
-        }
-        return;
-    }
+    __shared__ int qn[2];
 
     // particle ranges: rows of start cells (y, z) in [L-2, L+8], x-range
     // [L-2, L+8] split at tile boundaries (at most 3 contiguous key ranges)
@@ -945,41 +962,43 @@ __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ si
     // time.  The queue order varies between runs, the integer sums do not.
     const int *__restrict__ okey = ar.okey;
     const int *__restrict__ key = ar.key[par];
-    for (int g = 0; g < total; g += BLOCK) {
-        const int w = g + threadIdx.x;
-        bool take = false;
-        int p = 0, info = 0;
-        if (w < total) {
-            int lo = 0, hi = NENT - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (rpre[mid] <= w) lo = mid;
-                else hi = mid - 1;
-            }
-            p = rstart[lo] + (w - rpre[lo]);
-            int rec;
-            if (init) {
-                const int nk = key[p] - (int)S.key0;
-                rec = nk >= S.nkeys ? OKEY_LOST : (nk & 7) | (0x15 << 3);  // no move
-            } else {
-                rec = okey[p];
-            }
-            if (!(rec & OKEY_LOST)) {
-                const int row = lo / 3;
-                const int c0[3] = {(tX - 1 + lo % 3) * TILE + (rec & 7) - L[0],
-                                   row % 11 - 2, row / 11 - 2};
-                take = true;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const int mv = ((rec >> (3 + 2 * a)) & 3) - 1;
-                    const int mn = min(c0[a], c0[a] + mv), mx = max(c0[a], c0[a] + mv);
-                    take = take && mx + 1 >= 0 && mn <= TILE - 1;
-                    info |= (c0[a] + 2) << (4 * a);
-                    info |= (mv + 1) << (12 + 2 * a);
-                }
-            }
+    // the candidate's range, particle index and move record
+    auto locate = [&](int w, int *lo_out) __attribute__((always_inline)) {
+        int lo = 0, hi = NENT - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rpre[mid] <= w) lo = mid;
+            else hi = mid - 1;
         }
-        const bool still = info == (0x15 << 12) + (info & 0xfff);  // no move on any axis
+        *lo_out = lo;
+        return rstart[lo] + (w - rpre[lo]);
+    };
+    auto record = [&](int p) __attribute__((always_inline)) {
+        if (!init) return okey[p];
+        const int nk = key[p] - (int)S.key0;
+        return nk >= S.nkeys ? OKEY_LOST : (nk & 7) | (0x15 << 3);  // no move
+    };
+    // keep the particle if its vertex support meets the tile; packs the
+    // start cell relative to the tile (+2, 4 bits per axis) and the move
+    // (+1, 2 bits per axis)
+    auto filter = [&](int lo, int rec, int *info) __attribute__((always_inline)) {
+        *info = 0;
+        if (rec & OKEY_LOST) return false;
+        const int row = lo / 3;
+        const int c0[3] = {(tX - 1 + lo % 3) * TILE + (rec & 7) - L[0], row % 11 - 2,
+                           row / 11 - 2};
+        bool take = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int mv = ((rec >> (3 + 2 * a)) & 3) - 1;
+            const int mn = min(c0[a], c0[a] + mv), mx = max(c0[a], c0[a] + mv);
+            take = take && mx + 1 >= 0 && mn <= TILE - 1;
+            *info |= (c0[a] + 2) << (4 * a) | (mv + 1) << (12 + 2 * a);
+        }
+        return take;
+    };
+    auto append = [&](bool take, int p, int info) __attribute__((always_inline)) {
+        const bool still = (info >> 12) == 0x15;  // no move on any axis
 #pragma unroll
         for (int Q = 0; Q < 2; ++Q) {
             const bool mine = take && (still == (Q == 0));
@@ -993,38 +1012,40 @@ __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ si
                 qi[Q][pos] = info;
             }
         }
+    };
+    // Candidates in chunks of two per thread.  The filter reads only the
+    // 4-byte move record; the kept particles wait in LDS queues and are
+    // deposited a full block at a time (taken from the end of the queue).
+    // The order varies between runs, the integer sums do not.
+    for (int g = 0; g < total; g += 2 * BLOCK) {
+        const int wa = g + threadIdx.x, wb = wa + BLOCK;
+        int la = 0, lb = 0, pa = 0, pb = 0, ra = OKEY_LOST, rb = OKEY_LOST;
+        if (wa < total) pa = locate(wa, &la);
+        if (wb < total) pb = locate(wb, &lb);
+        if (wa < total) ra = record(pa);
+        if (wb < total) rb = record(pb);
+        int ia, ib;
+        const bool ta = filter(la, ra, &ia), tb = filter(lb, rb, &ib);
+        append(ta, pa, ia);
+        append(tb, pb, ib);
         __syncthreads();
-        // a full block's worth of one queue at a time; at the end, the rest
-        const bool last = g + BLOCK >= total;
+        const bool last = g + 2 * BLOCK >= total;
         auto drain = [&](auto nm) __attribute__((always_inline)) {
             constexpr int Q = decltype(nm)::value ? 0 : 1;
-            const int n = qn[Q];
-            const int cnt = last ? n : (n >= BLOCK ? BLOCK : 0);
-            if (cnt == 0) return;  // uniform
-            // up to two entries per thread, read before the rest moves down
-            const int e0 = threadIdx.x, e1 = threadIdx.x + BLOCK;
-            int p0 = 0, i0 = 0, p1 = 0, i1 = 0;
-            if (e0 < cnt) {
-                p0 = qp[Q][e0];
-                i0 = qi[Q][e0];
-            }
-            if (e1 < cnt) {
-                p1 = qp[Q][e1];
-                i1 = qi[Q][e1];
-            }
-            if (!last) {
-                __syncthreads();
-                if ((int)threadIdx.x < n - BLOCK) {
-                    qp[Q][threadIdx.x] = qp[Q][BLOCK + threadIdx.x];
-                    qi[Q][threadIdx.x] = qi[Q][BLOCK + threadIdx.x];
+            for (;;) {
+                const int n = qn[Q];
+                if (last ? n == 0 : n < BLOCK) break;  // uniform
+                const int cnt = min(n, BLOCK);
+                const bool has = (int)threadIdx.x < cnt;
+                int p = 0, info = 0;
+                if (has) {
+                    p = qp[Q][n - cnt + threadIdx.x];
+                    info = qi[Q][n - cnt + threadIdx.x];
                 }
-                if (threadIdx.x == 0) qn[Q] = n - BLOCK;
-            }
-            const int mine = (e0 < cnt) + (e1 < cnt);
-            for (int j = 0; j < mine; ++j) {
-                deposit_one(nm, p0, i0);
-                p0 = p1;
-                i0 = i1;
+                __syncthreads();
+                if (threadIdx.x == 0) qn[Q] = n - cnt;
+                if (has) deposit_one(nm, p, info);
+                __syncthreads();
             }
         };
         drain(std::integral_constant<bool, true>());
@@ -1033,6 +1054,7 @@ __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ si
     }
 
     // flush: every owned vertex, zeros included
+    if (threadIdx.x == 0) ar.tact[tg] = 0;  // set again by the next push
     const double inv = ldexp(1.0, -fx_bits);
     const double ju0 = S.J_unit[0] * inv, ju1 = S.J_unit[1] * inv, ju2 = S.J_unit[2] * inv,
                  ru = S.rho_unit * inv;
@@ -1384,20 +1406,28 @@ void launch_boundary(hipStream_t st, const SimDev *sims, const BSeg *segs, int n
                        total, ar);
 }
 
+static int dealt_grid(int nitems, int chunk)
+{
+    const long long round = 8LL * chunk;
+    return (int)((nitems + round - 1) / round * round);
+}
+
 template <typename R>
-void launch_push(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
+void launch_push(hipStream_t st, const SimDev *sims, const int2 *items, int nitems, int chunk,
                  const Arena &ar)
 {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL((k_push<R>), dim3(nitems), dim3(BLOCK), 0, st, sims, items, ar);
+    hipLaunchKernelGGL((k_push<R>), dim3(dealt_grid(nitems, chunk)), dim3(BLOCK), 0, st, sims,
+                       items, nitems, chunk, ar);
 }
 
 template <typename R>
 void launch_deposit(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
-                    const Arena &ar, int init)
+                    int chunk, const Arena &ar, int init)
 {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL((k_deposit<R>), dim3(nitems), dim3(BLOCK), 0, st, sims, items, ar, init);
+    hipLaunchKernelGGL((k_deposit<R>), dim3(dealt_grid(nitems, chunk)), dim3(BLOCK), 0, st,
+                       sims, items, nitems, chunk, ar, init);
 }
 
 void launch_scan(hipStream_t st, const Arena &ar, long long nkeys_total, int *block_sums,
@@ -1452,8 +1482,9 @@ void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long
                                     const Arena &, int, int, int);                              \
     template void launch_boundary<R>(hipStream_t, const SimDev *, const BSeg *, int, long long, \
                                      const Arena &);                                            \
-    template void launch_push<R>(hipStream_t, const SimDev *, const int2 *, int, const Arena &); \
-    template void launch_deposit<R>(hipStream_t, const SimDev *, const int2 *, int,             \
+    template void launch_push<R>(hipStream_t, const SimDev *, const int2 *, int, int,           \
+                                 const Arena &);                                                \
+    template void launch_deposit<R>(hipStream_t, const SimDev *, const int2 *, int, int,        \
                                     const Arena &, int);                                        \
     template void launch_scatter<R>(hipStream_t, const Arena &, long long);                     \
     template void launch_diag<R>(hipStream_t, const SimDev *, int, const int2 *, int,           \

@@ -86,7 +86,8 @@ struct Arena {
     double *partial;    // diagnostic partial sums
     double *ring;       // diagnostic rows
     int *flags;         // per simulation: a non-finite value was produced
-    int *tocc;          // per tile: particles at the start of the step (written by the push)
+    int *tact;          // per tile: a particle in the 27-tile neighbourhood at the start of
+                        // the step (set by the push, cleared by the deposit)
     int *jdirty;        // per tile: J holds non-zero values
     int *rdirty[2];     // per tile: rho[b] holds non-zero values
     long long *d_step;  // completed steps (all simulations advance together)
@@ -104,12 +105,14 @@ void launch_stencil(hipStream_t st, const SimDev *sims, const int4 *items, int n
 template <typename R>
 void launch_boundary(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg,
                      long long total, const Arena &ar);
+// push and deposit: the tile table is dealt to the XCDs in chunks of `chunk`
+// tiles
 template <typename R>
-void launch_push(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
+void launch_push(hipStream_t st, const SimDev *sims, const int2 *items, int nitems, int chunk,
                  const Arena &ar);
 template <typename R>
 void launch_deposit(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
-                    const Arena &ar, int init);
+                    int chunk, const Arena &ar, int init);
 void launch_scan(hipStream_t st, const Arena &ar, long long nkeys_total, int *block_sums,
                  int nblocks, const long long *d_step);
 template <typename R>

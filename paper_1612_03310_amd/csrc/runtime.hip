@@ -86,6 +86,7 @@ struct Batch {
     long long nb_total = 0;
     int2 *d_tiles = nullptr;
     int n_tiles = 0;
+    int tile_chunk = 1;  // tiles per chunk dealt to one XCD (push, deposit)
     int2 *d_plane = nullptr, *d_mesh = nullptr, *d_kin = nullptr;
     int n_plane = 0, n_mesh = 0, n_kin = 0;
     int *d_bsum = nullptr;
@@ -411,6 +412,11 @@ static mithra_status build_tables(Batch &b)
         for (int i = 0; i < S.nb_kin; ++i) kin.push_back(make_int2(s, i));
     }
     b.n_tiles = (int)tiles.size();
+    // chunks of two tile layers of the widest simulation, but at least 32
+    // chunks in all so that the dense region spreads over the XCDs
+    int layer = 1;
+    for (int s = 0; s < b.nsim; ++s) layer = std::max(layer, b.sd[s].nt[0] * b.sd[s].nt[1]);
+    b.tile_chunk = std::max(1, std::min(2 * layer, (b.n_tiles + 31) / 32));
     b.n_plane = (int)plane.size();
     b.n_mesh = (int)mesh.size();
     b.n_kin = (int)kin.size();
@@ -422,14 +428,14 @@ static mithra_status build_tables(Batch &b)
     b.n_scan_blocks = (int)((b.total_keys + SCAN_CHUNK - 1) / SCAN_CHUNK);
     b.d_bsum = (int *)dev_alloc(b, sizeof(int) * std::max(b.n_scan_blocks, 1), b.mem_tab);
     const size_t tb = sizeof(int) * std::max(b.n_tiles, 1);
-    b.ar.tocc = (int *)dev_alloc(b, tb, b.mem_tab);
+    b.ar.tact = (int *)dev_alloc(b, tb, b.mem_tab);
     b.ar.jdirty = (int *)dev_alloc(b, tb, b.mem_tab);
     for (int r = 0; r < 2; ++r) b.ar.rdirty[r] = (int *)dev_alloc(b, tb, b.mem_tab);
-    if (!b.ar.partial || !b.d_bsum || !b.ar.tocc || !b.ar.jdirty || !b.ar.rdirty[0] ||
+    if (!b.ar.partial || !b.d_bsum || !b.ar.tact || !b.ar.jdirty || !b.ar.rdirty[0] ||
         !b.ar.rdirty[1])
         return fail(MITHRA_ENOMEM, "device allocation failed");
     HIP_TRY(hipMemsetAsync(b.ar.partial, 0, sizeof(double) * std::max(slot, 1), b.stream));
-    HIP_TRY(hipMemsetAsync(b.ar.tocc, 0, tb, b.stream));
+    HIP_TRY(hipMemsetAsync(b.ar.tact, 0, tb, b.stream));
     HIP_TRY(mark_sources_dirty(b));
     HIP_TRY(hipMemcpyAsync(b.d_sims, b.sd.data(), sizeof(SimDev) * b.nsim, hipMemcpyHostToDevice,
                            b.stream));
@@ -716,7 +722,7 @@ static mithra_status commit_impl(Batch &b)
     mithra_status s2 = build_tables(b);
     if (s2) return s2;
     // rho^{s+1/2} from the loaded positions; J^s = 0 (start = end position)
-    launch_deposit<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.ar, 1);
+    launch_deposit<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar, 1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     b.committed = true;
@@ -763,10 +769,10 @@ static void enqueue_step(Batch &b, bool timed)
     launch_boundary<R>(st, b.d_sims, b.d_bseg, b.nbseg, b.nb_total, b.ar);
     mark(K_BOUNDARY, false);
     mark(K_PUSH, true);
-    launch_push<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.ar);
+    launch_push<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar);
     mark(K_PUSH, false);
     mark(K_DEPOSIT, true);
-    launch_deposit<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.ar, 0);
+    launch_deposit<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar, 0);
     mark(K_DEPOSIT, false);
     mark(K_SCAN, true);
     launch_scan(st, b.ar, b.total_keys, b.d_bsum, b.n_scan_blocks, b.ar.d_step);
