@@ -1079,33 +1079,71 @@ __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ si
 //    with its base.  Wavefront scans use cross-lane shuffles.
 // ---------------------------------------------------------------------------
 
+// A chunk is SCAN_CHUNK / SCAN_ROW rows of SCAN_ROW keys; in a row, thread t
+// holds keys 4t .. 4t+3, so every load and store instruction is one
+// contiguous 1 KB span per wavefront.
+constexpr int SCAN_ROW = BLOCK * 4;
+static_assert(SCAN_CHUNK % SCAN_ROW == 0, "a chunk is whole rows");
+
+__device__ __forceinline__ int4 load4(const int *__restrict__ a, long long i, long long n)
+{
+    if (i + 3 < n) return *reinterpret_cast<const int4 *>(a + i);
+    int4 v = make_int4(0, 0, 0, 0);
+    if (i < n) v.x = a[i];
+    if (i + 1 < n) v.y = a[i + 1];
+    if (i + 2 < n) v.z = a[i + 2];
+    return v;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int *__restrict__ counts,
                                                         long long n, int *__restrict__ bsum)
 {
-    const long long base = (long long)blockIdx.x * SCAN_CHUNK;
+    const long long base = (long long)blockIdx.x * SCAN_CHUNK + 4 * threadIdx.x;
+    int4 v[SCAN_CHUNK / SCAN_ROW];
+#pragma unroll
+    for (int r = 0; r < SCAN_CHUNK / SCAN_ROW; ++r) v[r] = load4(counts, base + r * SCAN_ROW, n);
     int s = 0;
 #pragma unroll
-    for (int r = 0; r < SCAN_PER_THREAD; ++r) {
-        const long long i = base + (long long)r * BLOCK + threadIdx.x;
-        if (i < n) s += counts[i];
-    }
+    for (int r = 0; r < SCAN_CHUNK / SCAN_ROW; ++r) s += v[r].x + v[r].y + v[r].z + v[r].w;
     __shared__ int sh[BLOCK / 64];
     int tot;
     block_excl_scan(s, sh, &tot);
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
+// One block: exclusive scan of the chunk sums, TOP_SEG at a time, staged
+// through LDS (padded by one word per 32 so that each thread's consecutive
+// run lies in distinct banks).
+constexpr int TOP_PER_THREAD = 32;
+constexpr int TOP_SEG = BLOCK * TOP_PER_THREAD;
+
 __global__ __launch_bounds__(BLOCK) void k_scan_top(int *__restrict__ bsum, int nb)
 {
+    __shared__ int seg[TOP_SEG + TOP_SEG / 32];
     __shared__ int sh[BLOCK / 64];
+    auto pad = [](int j) { return j + (j >> 5); };
     int carry = 0;
-    for (int base = 0; base < nb; base += BLOCK) {
-        const int i = base + threadIdx.x;
-        const int v = i < nb ? bsum[i] : 0;
+    for (int base = 0; base < nb; base += TOP_SEG) {
+        for (int j = threadIdx.x; j < TOP_SEG; j += BLOCK)
+            seg[pad(j)] = base + j < nb ? bsum[base + j] : 0;
+        __syncthreads();
+        const int j0 = threadIdx.x * TOP_PER_THREAD;
+        int s = 0;
+#pragma unroll
+        for (int k = 0; k < TOP_PER_THREAD; ++k) s += seg[pad(j0 + k)];
         int tot;
-        const int ex = block_excl_scan(v, sh, &tot);
-        if (i < nb) bsum[i] = carry + ex;
+        int run = carry + block_excl_scan(s, sh, &tot);
+#pragma unroll
+        for (int k = 0; k < TOP_PER_THREAD; ++k) {
+            const int v = seg[pad(j0 + k)];
+            seg[pad(j0 + k)] = run;
+            run += v;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < TOP_SEG && base + j < nb; j += BLOCK)
+            bsum[base + j] = seg[pad(j)];
         carry += tot;
+        __syncthreads();
     }
 }
 
@@ -1114,25 +1152,33 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const int *__restrict__ cou
 {
     const long long step = *ar.d_step;
     int *__restrict__ out = ar.offs[(step + 1) & 1];
-    const long long base = (long long)blockIdx.x * SCAN_CHUNK;
-    // each thread scans SCAN_PER_THREAD consecutive entries
-    const long long i0 = base + (long long)threadIdx.x * SCAN_PER_THREAD;
-    int v[SCAN_PER_THREAD];
-    int s = 0;
+    const long long chunk0 = (long long)blockIdx.x * SCAN_CHUNK;
+    const long long base = chunk0 + 4 * threadIdx.x;
+    int4 v[SCAN_CHUNK / SCAN_ROW];
 #pragma unroll
-    for (int r = 0; r < SCAN_PER_THREAD; ++r) {
-        v[r] = (i0 + r < n) ? counts[i0 + r] : 0;
-        s += v[r];
-    }
+    for (int r = 0; r < SCAN_CHUNK / SCAN_ROW; ++r) v[r] = load4(counts, base + r * SCAN_ROW, n);
     __shared__ int sh[BLOCK / 64];
-    int tot;
-    int run = bsum[blockIdx.x] + block_excl_scan(s, sh, &tot);
+    int carry = bsum[blockIdx.x];
 #pragma unroll
-    for (int r = 0; r < SCAN_PER_THREAD; ++r) {
-        if (i0 + r < n) out[i0 + r] = run;
-        run += v[r];
+    for (int r = 0; r < SCAN_CHUNK / SCAN_ROW; ++r) {
+        int tot;
+        const int ex = block_excl_scan(v[r].x + v[r].y + v[r].z + v[r].w, sh, &tot);
+        int4 o;
+        o.x = carry + ex;
+        o.y = o.x + v[r].x;
+        o.z = o.y + v[r].y;
+        o.w = o.z + v[r].z;
+        const long long i = base + r * SCAN_ROW;
+        if (i + 3 < n) {
+            *reinterpret_cast<int4 *>(out + i) = o;
+        } else {
+            if (i < n) out[i] = o.x;
+            if (i + 1 < n) out[i + 1] = o.y;
+            if (i + 2 < n) out[i + 2] = o.z;
+        }
+        carry += tot;
     }
-    if (i0 < n && i0 + SCAN_PER_THREAD >= n) out[n] = run;  // total
+    if (threadIdx.x == 0 && chunk0 + SCAN_CHUNK >= n) out[n] = carry;  // total
 }
 
 // ---------------------------------------------------------------------------
