@@ -50,13 +50,26 @@ def kernel_bytes(kind, w, rs, nb_points=0):
     return 0
 
 
-def boundary_points(w):
-    nx, ny, nz = w.n
+def x_faces_in_stencil(w, tile_x):
+    """The library's rule: the stencil pass updates the x faces when no high
+    x face column falls on the first lane of a wavefront (all axes Mur here)."""
+    comps = 4 if w.space_charge else 3
+    return tile_x >= 2 and all((w.n[0] - (1 if c == 0 else 0) - 1) % tile_x % 64 != 0
+                               for c in range(comps))
+
+
+def boundary_points(w, tile_x=None):
+    """Points the boundary kernel updates: every face, edge and corner point of
+    each component grid, less the x faces (y, z inside) when the stencil pass
+    takes them."""
     tot = 0
     comps = 4 if w.space_charge else 3
+    fused = tile_x is not None and x_faces_in_stencil(w, tile_x)
     for c in range(comps):
         ext = [w.n[a] - (1 if c == a else 0) for a in range(3)]
         tot += ext[0] * ext[1] * ext[2] - (ext[0] - 2) * (ext[1] - 2) * (ext[2] - 2)
+        if fused:
+            tot -= 2 * (ext[1] - 2) * (ext[2] - 2)
     return tot
 
 
@@ -212,7 +225,7 @@ def main():
     pushes = w.np * K * w.substeps / dt
     log("  %.4f ms/step, %.3e cell-updates/s, %.3e pushes/s" % (ms_step, value, pushes))
 
-    nbp = boundary_points(w)
+    nbp = boundary_points(w, info["stencil_tile"][0])
     kernels = {}
     for kind, t in per.items():
         b = kernel_bytes(kind, w, rs, nbp)

@@ -214,12 +214,17 @@ __device__ __forceinline__ bool vertex_valid(const SimDev &S, int i, int j, int 
 //      psi^{s+1} = -psi^{s-1} + a1 P + A (T_{k-1} + T_{k+1}) + (1 - 2A) T_k
 //                  + az (P_{k+1} + P_{k-1}) + src S,
 //    an exact regrouping of the z-averaged transverse neighbours.
+//    With fuse_x the same pass applies first-order Mur on the two x faces
+//    (points with y and z inside; the boundary kernel keeps the y and z
+//    faces): the face's inward neighbour along x is the adjacent lane of the
+//    wavefront, whose psi^{s-1}, psi^s and fresh psi^{s+1} arrive by shuffle.
+//    The host enables it only when no face column sits at a wavefront edge.
 // ---------------------------------------------------------------------------
 
 template <typename R, int TX, int TY>
 __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ sims,
                                                      const int4 *__restrict__ items, Arena ar,
-                                                     int KZ)
+                                                     int KZ, int fuse_x)
 {
     const int4 it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const SimDev &S = sims[it.x];
@@ -247,6 +252,9 @@ __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ s
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int i = it.y * TX + tx, j = it.z * TY + ty;
     const bool act = i >= lo[0] && i <= hi[0] && j >= lo[1] && j <= hi[1];
+    const int ext0 = comp_extent(S, comp, 0);
+    const bool face = fuse_x && !S.bc[0] && j >= lo[1] && j <= hi[1] && (i == 0 || i == ext0 - 1);
+    const R mb0 = (R)S.murb0[0], mb1 = (R)S.murb1[0];
 
     const R a1 = (R)S.a1, ax = (R)S.ax, ay = (R)S.ay, az = (R)S.az, A = (R)S.A;
     const R oma = (R)(1.0 - 2.0 * S.A);
@@ -292,10 +300,8 @@ __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ s
     commit(1);
     fetch(k0 + 1);
     R qn = 0, sn = 0;
-    if (act) {
-        qn = __builtin_nontemporal_load(&Q[(long long)k0 * sxy + col]);
-        sn = __builtin_nontemporal_load(&Src[(long long)k0 * sxy + col]);
-    }
+    if (act || face) qn = __builtin_nontemporal_load(&Q[(long long)k0 * sxy + col]);
+    if (act) sn = __builtin_nontemporal_load(&Src[(long long)k0 * sxy + col]);
     __syncthreads();
     R Tm = trans(0), Tc = trans(1);
     R Pm = sP[0][ty + 1][tx + 1], Pc = sP[1][ty + 1][tx + 1];
@@ -307,18 +313,25 @@ __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ s
         const R q = qn, s = sn;
         if (k < k1) {
             fetch(k + 2);
-            if (act) {
-                qn = __builtin_nontemporal_load(&Q[(long long)(k + 1) * sxy + col]);
-                sn = __builtin_nontemporal_load(&Src[(long long)(k + 1) * sxy + col]);
-            }
+            if (act || face) qn = __builtin_nontemporal_load(&Q[(long long)(k + 1) * sxy + col]);
+            if (act) sn = __builtin_nontemporal_load(&Src[(long long)(k + 1) * sxy + col]);
         }
         __syncthreads();
         const R Pp = sP[slot][ty + 1][tx + 1];
         const R Tp = trans(slot);
-        if (act)
-            __builtin_nontemporal_store(
-                -q + a1 * Pc + A * (Tm + Tp) + oma * Tc + az * (Pp + Pm) + src * s,
-                &Rn[(long long)k * sxy + col]);
+        const R val = -q + a1 * Pc + A * (Tm + Tp) + oma * Tc + az * (Pp + Pm) + src * s;
+        if (act) __builtin_nontemporal_store(val, &Rn[(long long)k * sxy + col]);
+        if (fuse_x) {
+            // the low face reads lane + 1, the high face lane - 1
+            const R vd = __shfl_down(val, 1), qd = __shfl_down(q, 1), pd = __shfl_down(Pc, 1);
+            const R vu = __shfl_up(val, 1), qu = __shfl_up(q, 1), pu = __shfl_up(Pc, 1);
+            if (face) {
+                const bool low = i == 0;
+                const R vq = low ? vd : vu, Qq = low ? qd : qu, Pq = low ? pd : pu;
+                __builtin_nontemporal_store(mb0 * q + mb1 * Pc - Qq + mb1 * Pq + mb0 * vq,
+                                            &Rn[(long long)k * sxy + col]);
+            }
+        }
         Pm = Pc;
         Pc = Pp;
         Tm = Tc;
@@ -1228,16 +1241,16 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Arena ar, long long np)
 }
 
 // ---------------------------------------------------------------------------
-// 7. double-precision diagnostics.  Per-block partial sums in fixed order,
-//    then one block per simulation sums its partials in fixed order and
-//    writes the row: deterministic run to run.
+// 7. double-precision diagnostics.  Per-block partial sums in fixed order
+//    (one launch: power-plane blocks, then mesh blocks, then kinetic-energy
+//    blocks), then one block per simulation sums its partials in fixed order
+//    and writes the row: deterministic run to run.  The last of those blocks
+//    to finish advances the step counter.
 // ---------------------------------------------------------------------------
 
 template <typename R>
-__global__ __launch_bounds__(BLOCK) void k_diag_plane(const SimDev *__restrict__ sims,
-                                                       const int2 *__restrict__ items, Arena ar)
+__device__ __forceinline__ void diag_plane(const SimDev *__restrict__ sims, int2 it, Arena &ar)
 {
-    const int2 it = items[blockIdx.x];
     const SimDev &S = sims[it.x];
     const long long step = *ar.d_step;
     const FieldPtrs<R> f = field_ptrs<R>(S, ar, step % 3, (step + 1) % 3, (int)(step % 3));
@@ -1257,10 +1270,8 @@ __global__ __launch_bounds__(BLOCK) void k_diag_plane(const SimDev *__restrict__
 }
 
 template <typename R>
-__global__ __launch_bounds__(BLOCK) void k_diag_mesh(const SimDev *__restrict__ sims,
-                                                      const int2 *__restrict__ items, Arena ar)
+__device__ __forceinline__ void diag_mesh(const SimDev *__restrict__ sims, int2 it, Arena &ar)
 {
-    const int2 it = items[blockIdx.x];
     const SimDev &S = sims[it.x];
     const long long step = *ar.d_step;
     if (S.mesh_every <= 0 || ((step + 1) % S.mesh_every) != 0) return;
@@ -1308,10 +1319,8 @@ __global__ __launch_bounds__(BLOCK) void k_diag_mesh(const SimDev *__restrict__ 
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_diag_kin(const SimDev *__restrict__ sims,
-                                                     const int2 *__restrict__ items, Arena ar)
+__device__ __forceinline__ void diag_kin(const SimDev *__restrict__ sims, int2 it, Arena &ar)
 {
-    const int2 it = items[blockIdx.x];
     const SimDev &S = sims[it.x];
     const long long step = *ar.d_step;
     if (S.mesh_every <= 0 || ((step + 1) % S.mesh_every) != 0) return;
@@ -1324,6 +1333,18 @@ __global__ __launch_bounds__(BLOCK) void k_diag_kin(const SimDev *__restrict__ s
     __shared__ double sh[BLOCK];
     const double tot = block_sum(s, sh);
     if (threadIdx.x == 0) ar.partial[S.part_kin0 + it.y] = tot;
+}
+
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_diag_parts(const SimDev *__restrict__ sims,
+                                                       const int2 *__restrict__ plane, int nplane,
+                                                       const int2 *__restrict__ mesh, int nmesh,
+                                                       const int2 *__restrict__ kin, Arena ar)
+{
+    const int b = blockIdx.x;  // the role is uniform over the block
+    if (b < nplane) diag_plane<R>(sims, plane[b], ar);
+    else if (b < nplane + nmesh) diag_mesh<R>(sims, mesh[b - nplane], ar);
+    else diag_kin(sims, kin[b - nplane - nmesh], ar);
 }
 
 template <typename R>
@@ -1379,12 +1400,12 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
         if (nf) atomicOr(&ar.flags[blockIdx.x], 2);
         row[14] = (double)nf;
         row[15] = mesh ? 1.0 : 0.0;
+        // every block has read the step counter before it counts itself done
+        if (atomicAdd(ar.fin_ctr, 1) == (int)gridDim.x - 1) {
+            *ar.fin_ctr = 0;
+            *ar.d_step = step + 1;
+        }
     }
-}
-
-__global__ void k_advance(long long *d_step)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *d_step += 1;
 }
 
 // E and B at every vertex of one simulation for the last completed push
@@ -1427,14 +1448,14 @@ bool stencil_shape_supported(int tx, int ty)
 
 template <typename R>
 void launch_stencil(hipStream_t st, const SimDev *sims, const int4 *items, int nitems,
-                    const Arena &ar, int tx, int ty, int kz)
+                    const Arena &ar, int tx, int ty, int kz, int fuse_x)
 {
     if (nitems <= 0) return;
     dim3 grid(nitems, 4);
 #define LAUNCH(a, b)                                                                        \
     if (tx == a && ty == b) {                                                               \
         hipLaunchKernelGGL((k_stencil<R, a, b>), grid, dim3(a * b), 0, st, sims, items, ar, \
-                           kz);                                                             \
+                           kz, fuse_x);                                                     \
         return;                                                                             \
     }
     MITHRA_STENCIL_SHAPES(LAUNCH)
@@ -1499,20 +1520,11 @@ void launch_diag(hipStream_t st, const SimDev *sims, int nsim, const int2 *plane
                  int nplane, const int2 *mesh_items, int nmesh, const int2 *kin_items, int nkin,
                  const Arena &ar)
 {
-    if (nplane > 0)
-        hipLaunchKernelGGL((k_diag_plane<R>), dim3(nplane), dim3(BLOCK), 0, st, sims, plane_items,
-                           ar);
-    if (nmesh > 0)
-        hipLaunchKernelGGL((k_diag_mesh<R>), dim3(nmesh), dim3(BLOCK), 0, st, sims, mesh_items,
-                           ar);
-    if (nkin > 0)
-        hipLaunchKernelGGL(k_diag_kin, dim3(nkin), dim3(BLOCK), 0, st, sims, kin_items, ar);
+    const int nparts = nplane + nmesh + nkin;
+    if (nparts > 0)
+        hipLaunchKernelGGL((k_diag_parts<R>), dim3(nparts), dim3(BLOCK), 0, st, sims, plane_items,
+                           nplane, mesh_items, nmesh, kin_items, ar);
     hipLaunchKernelGGL((k_diag_final<R>), dim3(nsim), dim3(BLOCK), 0, st, sims, ar);
-}
-
-void launch_advance(hipStream_t st, long long *d_step)
-{
-    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, d_step);
 }
 
 template <typename R>
@@ -1525,7 +1537,7 @@ void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long
 
 #define MITHRA_INSTANTIATE(R)                                                                   \
     template void launch_stencil<R>(hipStream_t, const SimDev *, const int4 *, int,             \
-                                    const Arena &, int, int, int);                              \
+                                    const Arena &, int, int, int, int);                         \
     template void launch_boundary<R>(hipStream_t, const SimDev *, const BSeg *, int, long long, \
                                      const Arena &);                                            \
     template void launch_push<R>(hipStream_t, const SimDev *, const int2 *, int, int,           \

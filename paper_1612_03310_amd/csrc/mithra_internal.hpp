@@ -90,7 +90,9 @@ struct Arena {
                         // the step (set by the push, cleared by the deposit)
     int *jdirty;        // per tile: J holds non-zero values
     int *rdirty[2];     // per tile: rho[b] holds non-zero values
-    long long *d_step;  // completed steps (all simulations advance together)
+    long long *d_step;  // completed steps (all simulations advance together); the
+                        // diagnostics advance it at the end of a step
+    int *fin_ctr;       // row-writing blocks done in this step (back to 0 after it)
 };
 
 struct BSeg {
@@ -100,8 +102,9 @@ struct BSeg {
 
 // Host-side launchers (kernels.hip).
 template <typename R>
+// fuse_x: the stencil pass also updates the x faces (first-order Mur)
 void launch_stencil(hipStream_t st, const SimDev *sims, const int4 *items, int nitems,
-                    const Arena &ar, int tx, int ty, int kz);
+                    const Arena &ar, int tx, int ty, int kz, int fuse_x);
 template <typename R>
 void launch_boundary(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg,
                      long long total, const Arena &ar);
@@ -121,7 +124,6 @@ template <typename R>
 void launch_diag(hipStream_t st, const SimDev *sims, int nsim, const int2 *plane_items,
                  int nplane, const int2 *mesh_items, int nmesh, const int2 *kin_items, int nkin,
                  const Arena &ar);
-void launch_advance(hipStream_t st, long long *d_step);
 template <typename R>
 void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long ncell,
                           const Arena &ar, double *out6);

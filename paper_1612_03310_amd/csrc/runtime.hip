@@ -79,6 +79,7 @@ struct Batch {
     SimDev *d_sims = nullptr;
     // work tables
     int tile_x = 64, tile_y = 4, kz = 64;
+    int fuse_x = 0;  // the stencil pass updates the x faces
     int4 *d_stencil = nullptr;
     int n_stencil = 0;
     BSeg *d_bseg = nullptr;
@@ -343,6 +344,24 @@ static hipError_t mark_sources_dirty(Batch &b)
     return e;
 }
 
+// The stencil can update the x faces when every face column has its inward
+// neighbour in the same wavefront row: the low face (x = 0) always does, the
+// high face (x = ext - 1) unless it is the first lane of a wavefront.
+static bool x_faces_fusable(const Batch &b, int tx)
+{
+    if (tx < 2) return false;
+    for (int s = 0; s < b.nsim; ++s) {
+        const SimDev &S = b.sd[s];
+        if (S.bc[0]) continue;
+        for (int c = 0; c < 4; ++c) {
+            if (c == 3 && !S.sc) continue;
+            const int ext = c == 0 ? S.n[0] - 1 : S.n[0];
+            if ((ext - 1) % tx % 64 == 0) return false;
+        }
+    }
+    return true;
+}
+
 static mithra_status build_tables(Batch &b)
 {
     (void)hipStreamSynchronize(b.stream);
@@ -355,7 +374,9 @@ static mithra_status build_tables(Batch &b)
     stencil_items(b, b.tile_x, b.tile_y, b.kz, items);
     b.n_stencil = (int)items.size();
     if ((st = upload_table(b, items, &b.d_stencil))) return st;
-    // boundary segments (Mur axes only)
+    // boundary segments (Mur axes only; the x faces go with the stencil when
+    // it can take them)
+    b.fuse_x = x_faces_fusable(b, b.tile_x) ? 1 : 0;
     std::vector<BSeg> segs;
     long long start = 0;
     for (int s = 0; s < b.nsim; ++s) {
@@ -370,7 +391,7 @@ static mithra_status build_tables(Batch &b)
             const long long cnt[3] = {2LL * ni[1] * ni[2], 2LL * ext[0] * ni[2],
                                       2LL * ext[0] * ext[1]};
             for (int g = 2; g >= 0; --g) {
-                if (S.bc[g]) continue;
+                if (S.bc[g] || (g == 0 && b.fuse_x)) continue;
                 BSeg sg;
                 sg.sim = s;
                 sg.comp = c;
@@ -536,6 +557,7 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     ok &= (b->ar.ring = (double *)A(sizeof(double) * NDIAG * ring)) != nullptr;
     ok &= (b->ar.flags = (int *)A(sizeof(int) * nsim)) != nullptr;
     ok &= (b->ar.d_step = (long long *)A(sizeof(long long))) != nullptr;
+    ok &= (b->ar.fin_ctr = (int *)A(sizeof(int))) != nullptr;
     ok &= (b->d_sims = (SimDev *)A(sizeof(SimDev) * nsim)) != nullptr;
     if (!ok) {
         destroy_batch(b);
@@ -553,6 +575,7 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.ring, 0, sizeof(double) * NDIAG * ring, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.flags, 0, sizeof(int) * nsim, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.d_step, 0, sizeof(long long), b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->ar.fin_ctr, 0, sizeof(int), b->stream);
     if (e != hipSuccess) {
         destroy_batch(b);
         return fail(MITHRA_EDEVICE, "clearing device memory failed: %s", hipGetErrorString(e));
@@ -763,7 +786,8 @@ static void enqueue_step(Batch &b, bool timed)
         }
     };
     mark(K_STENCIL, true);
-    launch_stencil<R>(st, b.d_sims, b.d_stencil, b.n_stencil, b.ar, b.tile_x, b.tile_y, b.kz);
+    launch_stencil<R>(st, b.d_sims, b.d_stencil, b.n_stencil, b.ar, b.tile_x, b.tile_y, b.kz,
+                      b.fuse_x);
     mark(K_STENCIL, false);
     mark(K_BOUNDARY, true);
     launch_boundary<R>(st, b.d_sims, b.d_bseg, b.nbseg, b.nb_total, b.ar);
@@ -783,7 +807,6 @@ static void enqueue_step(Batch &b, bool timed)
     mark(K_DIAG, true);
     launch_diag<R>(st, b.d_sims, b.nsim, b.d_plane, b.n_plane, b.d_mesh, b.n_mesh, b.d_kin,
                    b.n_kin, b.ar);
-    launch_advance(st, b.ar.d_step);
     mark(K_DIAG, false);
 }
 
@@ -1140,10 +1163,12 @@ static mithra_status tune_impl(Batch &b, int trials)
             if (!d) continue;
             HIP_TRY(hipMemcpyAsync(d, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice,
                                    b.stream));
-            launch_stencil<R>(b.stream, b.d_sims, d, (int)items.size(), b.ar, sh[0], sh[1], kz);
+            const int fx = x_faces_fusable(b, sh[0]) ? 1 : 0;
+            launch_stencil<R>(b.stream, b.d_sims, d, (int)items.size(), b.ar, sh[0], sh[1], kz, fx);
             HIP_TRY(hipEventRecord(e0, b.stream));
             for (int t = 0; t < trials; ++t)
-                launch_stencil<R>(b.stream, b.d_sims, d, (int)items.size(), b.ar, sh[0], sh[1], kz);
+                launch_stencil<R>(b.stream, b.d_sims, d, (int)items.size(), b.ar, sh[0], sh[1], kz,
+                                  fx);
             HIP_TRY(hipEventRecord(e1, b.stream));
             HIP_TRY(hipEventSynchronize(e1));
             HIP_TRY(hipGetLastError());

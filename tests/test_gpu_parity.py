@@ -130,12 +130,16 @@ def _random_fields(n, bc, rng):
     return out
 
 
-@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 0), (1, 1, 1), (0, 1, 0)])
-def test_potential_update_and_mur_match_oracle(bc):
+@pytest.mark.parametrize("bc,n", [((0, 0, 0), (40, 36, 50)), ((1, 1, 0), (40, 36, 50)),
+                                  ((1, 1, 1), (40, 36, 50)), ((0, 1, 0), (40, 36, 50)),
+                                  ((0, 0, 0), (65, 36, 50))])
+def test_potential_update_and_mur_match_oracle(bc, n):
     """One step of eq. (updateEquation) plus first-order Mur on faces, edges
-    and corners, with random potentials and sources, on a mesh whose sizes are
-    not multiples of the 8-cell tiles."""
-    n = (40, 36, 50)
+    and corners, with random potentials and sources, on meshes whose sizes are
+    not multiples of the 8-cell tiles.  At 40 cells along x the stencil pass
+    updates the x faces itself; at 65 the high x face of the potentials
+    falls on the first lane of a wavefront and the boundary kernel takes
+    them."""
     dz = 2e-6
     d = (4 * dz, 3 * dz, dz)
     origin = tuple(-(n[a] - 1) / 2 * d[a] for a in range(3))
