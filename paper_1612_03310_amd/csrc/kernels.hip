@@ -551,20 +551,23 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
         u[2] = u2[p];
     }
 
-    // E and B at the tile's 9^3 vertices.  The potentials of the box
-    // [L-1, L+9]^3 are staged in LDS in one pass: for each A component the
-    // level difference (for E = -dA/dt) and the level sum (for the mean
-    // curl), and phi.  The kick-scaled E, B table then overwrites the staging.
+    // E and B at the tile's 9^3 vertices, from the potentials of the box
+    // [L-1, L+9]^3 in two passes over one LDS staging area of 4 x 11^3
+    // values: first the level differences of A (for E = -dA/dt) and phi,
+    // then the level sums of A (for B, the mean of curl A over the two
+    // levels).  E waits in registers during the second pass; the kick-scaled
+    // table then overwrites the staging.
     constexpr int NV = TILE_VERT * TILE_VERT * TILE_VERT;  // 729
     constexpr int SG = TILE_VERT + 2;                      // 11
     constexpr int NS = SG * SG * SG;                       // 1331
     constexpr int NSE = (NS + BLOCK - 1) / BLOCK;          // staged points per thread
     constexpr int VPT = (NV + BLOCK - 1) / BLOCK;          // vertices per thread
     constexpr int OX = 1, OY = SG, OZ = SG * SG;
-    static_assert(6 * NV <= 7 * NS, "the field table must fit in the staging area");
-    __shared__ R smem[7 * NS];
-    R(*stg)[NS] = reinterpret_cast<R(*)[NS]>(smem);  // D_x D_y D_z S_x S_y S_z phi
+    static_assert(6 * NV <= 4 * NS, "the field table must fit in the staging area");
+    __shared__ R smem[4 * NS];
+    R(*stg)[NS] = reinterpret_cast<R(*)[NS]>(smem);  // D_x D_y D_z phi, then S_x S_y S_z
     R(*sF)[NV] = reinterpret_cast<R(*)[NV]>(smem);
+    R ssum[3][NSE];
     {
         const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
         const long long l0 = step % 3, l1 = (step + 1) % 3;
@@ -589,13 +592,15 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
 #pragma unroll
         for (int m = 0; m < NSE; ++m) {
             const int e = threadIdx.x + m * BLOCK;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ssum[c][m] = (R)0;
             if (e < NS) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
+                    ssum[c][m] = a0[c][m] + a1[c][m];
                     stg[c][e] = a1[c][m] - a0[c][m];
-                    stg[3 + c][e] = a0[c][m] + a1[c][m];
                 }
-                stg[6][e] = ph[m];
+                stg[3][e] = ph[m];
             }
         }
     }
@@ -607,21 +612,41 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
                 q2z = (R)(0.25 * S.inv_2d[2]);
         const R i2x = (R)S.inv_2d[0], i2y = (R)S.inv_2d[1], i2z = (R)S.inv_2d[2];
         R EB[VPT][6];
+        bool ok[VPT];
+        int pp[VPT];
 #pragma unroll
         for (int m = 0; m < VPT; ++m) {
             const int v = threadIdx.x + m * BLOCK;
             const int vi = v % TILE_VERT, vj = (v / TILE_VERT) % TILE_VERT,
                       vk = v / (TILE_VERT * TILE_VERT);
+            ok[m] = v < NV && vertex_valid(S, L0 + vi, L1 + vj, L2 + vk);
+            pp[m] = ((vk + 1) * SG + (vj + 1)) * SG + (vi + 1);
 #pragma unroll
             for (int a = 0; a < 6; ++a) EB[m][a] = (R)0;
-            if (v < NV && vertex_valid(S, L0 + vi, L1 + vj, L2 + vk)) {
-                const int p = ((vk + 1) * SG + (vj + 1)) * SG + (vi + 1);
-                const R *Dx = stg[0], *Dy = stg[1], *Dz = stg[2];
-                const R *Sx = stg[3], *Sy = stg[4], *Sz = stg[5], *P = stg[6];
+            if (ok[m]) {
+                const int p = pp[m];
+                const R *Dx = stg[0], *Dy = stg[1], *Dz = stg[2], *P = stg[3];
                 // E = -dA/dt - grad phi
                 EB[m][0] = -hidt * (Dx[p] + Dx[p - OX]) - (P[p + OX] - P[p - OX]) * i2x;
                 EB[m][1] = -hidt * (Dy[p] + Dy[p - OY]) - (P[p + OY] - P[p - OY]) * i2y;
                 EB[m][2] = -hidt * (Dz[p] + Dz[p - OZ]) - (P[p + OZ] - P[p - OZ]) * i2z;
+            }
+        }
+        __syncthreads();  // the level sums overwrite the differences
+#pragma unroll
+        for (int m = 0; m < NSE; ++m) {
+            const int e = threadIdx.x + m * BLOCK;
+            if (e < NS) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) stg[c][e] = ssum[c][m];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < VPT; ++m) {
+            if (ok[m]) {
+                const int p = pp[m];
+                const R *Sx = stg[0], *Sy = stg[1], *Sz = stg[2];
                 // B = mean over the two levels of curl A
                 EB[m][3] = q2y * ((Sz[p + OY] + Sz[p + OY - OZ]) - (Sz[p - OY] + Sz[p - OY - OZ])) -
                            q2z * ((Sy[p + OZ] + Sy[p + OZ - OY]) - (Sy[p - OZ] + Sy[p - OZ - OY]));
