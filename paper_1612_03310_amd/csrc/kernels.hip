@@ -930,11 +930,13 @@ __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ si
         const R f0[3] = {q0[p], q1[p], q2[p]};
         const R f1[3] = {n0[p], n1[p], n2[p]};
         int base[3];
+        bool moved[3];
         R S0[3][3], DS[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int c0 = ((info >> (4 * a)) & 15) - 2;        // start cell - L
             const int mv = NM ? 0 : ((info >> (12 + 2 * a)) & 3) - 1;  // cell move
+            moved[a] = mv != 0;
             base[a] = min(c0, c0 + mv);
             // the start (end) cell is base or base + 1
             const bool s0 = mv >= 0, s1 = mv <= 0;
@@ -949,7 +951,10 @@ __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ si
             for (int m = 0; m < 3; ++m) DS[a][m] = S1[m] - S0[a][m];
         }
         // the 3x3x3 box [base, base+2] in tile-local vertex coordinates;
-        // J_l sits on the edges from vertex a to a + 1 along l (a = 0, 1)
+        // J_l sits on the edges from vertex a to a + 1 along l (a = 0, 1).
+        // Without a move along l the weights along l sit on two vertices and
+        // the current on the second edge is DS_0 + DS_1 = -DS_2 = 0 exactly;
+        // only its rounding residue would remain, so it is not added.
         auto own = [](int v) { return v >= 0 && v < TILE; };
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
@@ -964,6 +969,7 @@ __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ si
                     R run = 0;
 #pragma unroll
                     for (int a = 0; a < 2; ++a) {
+                        if (a == 1 && (NM || !moved[l])) break;
                         run += DS[l][a] * Y;
                         int v[3];
                         v[l] = base[l] + a;
@@ -1461,7 +1467,8 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_fields(const SimDev *__restric
 // launchers
 // ---------------------------------------------------------------------------
 
-#define MITHRA_STENCIL_SHAPES(X) X(64, 4) X(32, 8) X(128, 2) X(64, 2) X(32, 4) X(16, 16)
+#define MITHRA_STENCIL_SHAPES(X) \
+    X(64, 4) X(32, 8) X(128, 2) X(64, 2) X(32, 4) X(16, 16) X(256, 1) X(128, 1) X(128, 4) X(256, 2) X(64, 8)
 
 bool stencil_shape_supported(int tx, int ty)
 {

@@ -1144,14 +1144,20 @@ static mithra_status get_info(Batch &b, int s, mithra_info *info)
 template <typename R>
 static mithra_status tune_impl(Batch &b, int trials)
 {
-    static const int shapes[][2] = {{64, 4}, {32, 8}, {128, 2}, {64, 2}, {32, 4}, {16, 16}};
+    static const int shapes[][2] = {{64, 4}, {32, 8}, {128, 2}, {64, 2}, {32, 4}, {16, 16},
+                                    {256, 1}, {128, 1}, {128, 4}, {256, 2}, {64, 8}};
     static const int kzs[] = {16, 32, 64, 128, 256};
     int maxn[3] = {0, 0, 0};
     for (int s = 0; s < b.nsim; ++s)
         for (int a = 0; a < 3; ++a) maxn[a] = std::max(maxn[a], b.sd[s].n[a]);
     hipEvent_t e0 = new_event(), e1 = new_event();
-    float best = 1e30f;
     int bx = b.tile_x, by = b.tile_y, bk = b.kz;
+    struct Cand {
+        int tx, ty, kz, fx, n;
+        int4 *items;
+        float ms;
+    };
+    std::vector<Cand> cands;
     std::vector<int4> items;
     std::vector<void *> scratch;
     for (auto &sh : shapes) {
@@ -1163,25 +1169,34 @@ static mithra_status tune_impl(Batch &b, int trials)
             if (!d) continue;
             HIP_TRY(hipMemcpyAsync(d, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice,
                                    b.stream));
-            const int fx = x_faces_fusable(b, sh[0]) ? 1 : 0;
-            launch_stencil<R>(b.stream, b.d_sims, d, (int)items.size(), b.ar, sh[0], sh[1], kz, fx);
+            cands.push_back({sh[0], sh[1], kz, x_faces_fusable(b, sh[0]) ? 1 : 0,
+                             (int)items.size(), d, 1e30f});
+        }
+    }
+    // two passes, the second in reverse order; each candidate keeps its best
+    for (int pass = 0; pass < 2; ++pass) {
+        for (size_t q = 0; q < cands.size(); ++q) {
+            Cand &c = cands[pass ? cands.size() - 1 - q : q];
+            launch_stencil<R>(b.stream, b.d_sims, c.items, c.n, b.ar, c.tx, c.ty, c.kz, c.fx);
             HIP_TRY(hipEventRecord(e0, b.stream));
             for (int t = 0; t < trials; ++t)
-                launch_stencil<R>(b.stream, b.d_sims, d, (int)items.size(), b.ar, sh[0], sh[1], kz,
-                                  fx);
+                launch_stencil<R>(b.stream, b.d_sims, c.items, c.n, b.ar, c.tx, c.ty, c.kz, c.fx);
             HIP_TRY(hipEventRecord(e1, b.stream));
             HIP_TRY(hipEventSynchronize(e1));
             HIP_TRY(hipGetLastError());
             float ms = 0.0f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                bx = sh[0];
-                by = sh[1];
-                bk = kz;
-            }
+            c.ms = std::min(c.ms, ms);
         }
     }
+    float best = 1e30f;
+    for (const Cand &c : cands)
+        if (c.ms < best) {
+            best = c.ms;
+            bx = c.tx;
+            by = c.ty;
+            bk = c.kz;
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_TRY(hipStreamSynchronize(b.stream));
