@@ -567,40 +567,92 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
     __shared__ R smem[4 * NS];
     R(*stg)[NS] = reinterpret_cast<R(*)[NS]>(smem);  // D_x D_y D_z phi, then S_x S_y S_z
     R(*sF)[NV] = reinterpret_cast<R(*)[NV]>(smem);
+    // Tiles away from the x ends of the mesh load each box row as aligned
+    // 16-byte vectors over [L-VW, L+8+VW) (VW values per vector): fewer,
+    // wider load instructions for a few more bytes.  Other tiles load point
+    // by point with wrapped or clamped indices.
+    constexpr int VW = 16 / (int)sizeof(R);
+    constexpr int NVR = 8 / VW + 2;               // vectors per box row
+    constexpr int NIT = SG * SG * NVR;            // vectors per array
+    constexpr int NVE = (NIT + BLOCK - 1) / BLOCK;
+    typedef R V __attribute__((ext_vector_type(VW)));
+    const bool vec = S.n[0] % VW == 0 && S.cell0 % VW == 0 && L0 >= VW && L0 + 8 + VW <= S.n[0];
     R ssum[3][NSE];
+    V vsum[3][NVE];
+    int vrow[NVE], vvi[NVE];
     {
         const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
         const long long l0 = step % 3, l1 = (step + 1) % 3;
-        R a0[3][NSE], a1[3][NSE], ph[NSE];
+        if (vec) {
+            V v0[3][NVE], v1[3][NVE], vp[NVE];
 #pragma unroll
-        for (int m = 0; m < NSE; ++m) {
-            const int e = threadIdx.x + m * BLOCK;
-            if (e < NS) {
-                const int r0 = e % SG, r1 = (e / SG) % SG, r2 = e / (SG * SG);
-                const int gi = axis_index(L0 - 1 + r0, nx, S.bc[0]);
-                const int gj = axis_index(L1 - 1 + r1, ny, S.bc[1]);
-                const int gkk = axis_index(L2 - 1 + r2, nz, S.bc[2]);
-                const long long g = ((long long)gkk * ny + gj) * nx + gi;
+            for (int m = 0; m < NVE; ++m) {
+                const int it = threadIdx.x + m * BLOCK;
+                vrow[m] = it / NVR;
+                vvi[m] = it % NVR;
+                if (it < NIT) {
+                    const int gj = axis_index(L1 - 1 + vrow[m] % SG, ny, S.bc[1]);
+                    const int gkk = axis_index(L2 - 1 + vrow[m] / SG, nz, S.bc[2]);
+                    const long long g =
+                        ((long long)gkk * ny + gj) * nx + (L0 - VW + vvi[m] * VW) + S.cell0;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    a0[c][m] = ((const R *)ar.pot[l0][c] + S.cell0)[g];
-                    a1[c][m] = ((const R *)ar.pot[l1][c] + S.cell0)[g];
+                    for (int c = 0; c < 3; ++c) {
+                        v0[c][m] = *reinterpret_cast<const V *>((const R *)ar.pot[l0][c] + g);
+                        v1[c][m] = *reinterpret_cast<const V *>((const R *)ar.pot[l1][c] + g);
+                    }
+                    vp[m] = *reinterpret_cast<const V *>((const R *)ar.pot[l0][3] + g);
                 }
-                ph[m] = ((const R *)ar.pot[l0][3] + S.cell0)[g];
             }
-        }
 #pragma unroll
-        for (int m = 0; m < NSE; ++m) {
-            const int e = threadIdx.x + m * BLOCK;
+            for (int m = 0; m < NVE; ++m) {
+                const int it = threadIdx.x + m * BLOCK;
+                if (it < NIT) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ssum[c][m] = (R)0;
-            if (e < NS) {
+                    for (int c = 0; c < 3; ++c) vsum[c][m] = v0[c][m] + v1[c][m];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    ssum[c][m] = a0[c][m] + a1[c][m];
-                    stg[c][e] = a1[c][m] - a0[c][m];
+                    for (int k = 0; k < VW; ++k) {
+                        const int rx = vvi[m] * VW + k - VW + 1;  // box x index
+                        if (rx >= 0 && rx < SG) {
+                            const int e = vrow[m] * SG + rx;
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) stg[c][e] = v1[c][m][k] - v0[c][m][k];
+                            stg[3][e] = vp[m][k];
+                        }
+                    }
                 }
-                stg[3][e] = ph[m];
+            }
+        } else {
+            R a0[3][NSE], a1[3][NSE], ph[NSE];
+#pragma unroll
+            for (int m = 0; m < NSE; ++m) {
+                const int e = threadIdx.x + m * BLOCK;
+                if (e < NS) {
+                    const int r0 = e % SG, r1 = (e / SG) % SG, r2 = e / (SG * SG);
+                    const int gi = axis_index(L0 - 1 + r0, nx, S.bc[0]);
+                    const int gj = axis_index(L1 - 1 + r1, ny, S.bc[1]);
+                    const int gkk = axis_index(L2 - 1 + r2, nz, S.bc[2]);
+                    const long long g = ((long long)gkk * ny + gj) * nx + gi;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        a0[c][m] = ((const R *)ar.pot[l0][c] + S.cell0)[g];
+                        a1[c][m] = ((const R *)ar.pot[l1][c] + S.cell0)[g];
+                    }
+                    ph[m] = ((const R *)ar.pot[l0][3] + S.cell0)[g];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < NSE; ++m) {
+                const int e = threadIdx.x + m * BLOCK;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ssum[c][m] = (R)0;
+                if (e < NS) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        ssum[c][m] = a0[c][m] + a1[c][m];
+                        stg[c][e] = a1[c][m] - a0[c][m];
+                    }
+                    stg[3][e] = ph[m];
+                }
             }
         }
     }
@@ -633,12 +685,29 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
             }
         }
         __syncthreads();  // the level sums overwrite the differences
+        if (vec) {
 #pragma unroll
-        for (int m = 0; m < NSE; ++m) {
-            const int e = threadIdx.x + m * BLOCK;
-            if (e < NS) {
+            for (int m = 0; m < NVE; ++m) {
+                const int it = threadIdx.x + m * BLOCK;
+                if (it < NIT) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) stg[c][e] = ssum[c][m];
+                    for (int k = 0; k < VW; ++k) {
+                        const int rx = vvi[m] * VW + k - VW + 1;
+                        if (rx >= 0 && rx < SG) {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) stg[c][vrow[m] * SG + rx] = vsum[c][m][k];
+                        }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < NSE; ++m) {
+                const int e = threadIdx.x + m * BLOCK;
+                if (e < NS) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) stg[c][e] = ssum[c][m];
+                }
             }
         }
         __syncthreads();
