@@ -499,22 +499,32 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
                                                  const int2 *__restrict__ items, int nitems,
                                                  int chunk, Arena ar)
 {
-    const int ti = tile_deal(blockIdx.x, nitems, chunk);
+    const int ti = tile_deal(blockIdx.x, nitems, chunk);  // global tile index
     if (ti < 0) return;
-    const int2 it = items[ti];
-    const SimDev &S = sims[it.x];
+    // A tile that no particle entered in the previous step (flag written by
+    // that step's push, or set for all tiles after particles are loaded) has
+    // nothing to do: one round trip decides it.
+    const int occ0 = ar.pocc[0][ti], occ1 = ar.pocc[1][ti];
     const long long step = *ar.d_step;
     const int par = (int)(step & 1);
+    if ((par ? occ1 : occ0) == 0) return;
+    const int2 it = items[ti];
+    const SimDev &S = sims[it.x];
     const int *__restrict__ offs = ar.offs[par];
     if (it.y == 0 && threadIdx.x == 0) {
-        // particles lost in earlier steps stay in the lost bucket
+        // particles lost in earlier steps stay in the lost bucket; tile 0
+        // runs every step for that
         const long long g = S.key0 + S.nkeys;
         const int n_lost = offs[g + 1] - offs[g];
         if (n_lost) atomicAdd(&ar.counts[g], n_lost);
+        ar.pocc[par ^ 1][ti] = 1;
     }
     const long long g0 = S.key0 + (long long)it.y * TILE_CELLS;
     const int p_lo = offs[g0], p_hi = offs[g0 + TILE_CELLS];
-    if (p_lo == p_hi) return;
+    if (p_lo == p_hi) {
+        if (threadIdx.x == 0 && it.y != 0) ar.pocc[par][ti] = 0;
+        return;
+    }
 
     const int t = it.y;
     const int L0 = (t % S.nt[0]) * TILE, L1 = ((t / S.nt[0]) % S.nt[1]) * TILE,
@@ -847,7 +857,16 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
             }
         }
         count_runs(ar.counts, ngk, active);
+        // flag the tiles this wavefront's particles entered (one write per
+        // run of equal tiles)
+        const int nloc = ngk - (int)S.key0;
+        const bool inside = active && nloc < S.nkeys;
+        const int ntile = inside ? S.tile0 + (nloc >> 9) : -1;
+        const int prev = __shfl_up(ntile, 1);
+        if (inside && ((threadIdx.x & 63) == 0 || prev != ntile)) ar.pocc[par ^ 1][ntile] = 1;
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && it.y != 0) ar.pocc[par][ti] = 0;  // set again by a later push
 }
 
 // ---------------------------------------------------------------------------

@@ -88,6 +88,8 @@ struct Arena {
     int *flags;         // per simulation: a non-finite value was produced
     int *tact;          // per tile: a particle in the 27-tile neighbourhood at the start of
                         // the step (set by the push, cleared by the deposit)
+    int *pocc[2];       // per tile: particles may sit in it at the start of step s
+                        // (pocc[s & 1]; written by the push of step s - 1)
     int *jdirty;        // per tile: J holds non-zero values
     int *rdirty[2];     // per tile: rho[b] holds non-zero values
     long long *d_step;  // completed steps (all simulations advance together); the

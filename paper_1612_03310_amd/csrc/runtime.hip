@@ -451,12 +451,15 @@ static mithra_status build_tables(Batch &b)
     const size_t tb = sizeof(int) * std::max(b.n_tiles, 1);
     b.ar.tact = (int *)dev_alloc(b, tb, b.mem_tab);
     b.ar.jdirty = (int *)dev_alloc(b, tb, b.mem_tab);
+    for (int r = 0; r < 2; ++r) b.ar.pocc[r] = (int *)dev_alloc(b, tb, b.mem_tab);
     for (int r = 0; r < 2; ++r) b.ar.rdirty[r] = (int *)dev_alloc(b, tb, b.mem_tab);
     if (!b.ar.partial || !b.d_bsum || !b.ar.tact || !b.ar.jdirty || !b.ar.rdirty[0] ||
-        !b.ar.rdirty[1])
+        !b.ar.rdirty[1] || !b.ar.pocc[0] || !b.ar.pocc[1])
         return fail(MITHRA_ENOMEM, "device allocation failed");
     HIP_TRY(hipMemsetAsync(b.ar.partial, 0, sizeof(double) * std::max(slot, 1), b.stream));
     HIP_TRY(hipMemsetAsync(b.ar.tact, 0, tb, b.stream));
+    // every tile may hold particles until a push says otherwise
+    for (int r = 0; r < 2; ++r) HIP_TRY(hipMemsetAsync(b.ar.pocc[r], 1, tb, b.stream));
     HIP_TRY(mark_sources_dirty(b));
     HIP_TRY(hipMemcpyAsync(b.d_sims, b.sd.data(), sizeof(SimDev) * b.nsim, hipMemcpyHostToDevice,
                            b.stream));
