@@ -181,7 +181,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--extra", action="store_true", help="also time the batched scan")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device 5 times (a kernel of known "
                          "traffic, to scale hardware byte counters)")
