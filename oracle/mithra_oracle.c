@@ -35,6 +35,18 @@
  *   R16 first-order Mur on faces, then edges, then corners; a point on
  *       several faces uses the rule of its highest-priority axis
  *       (z > y > x);
+ *   R19 second-order Mur: on faces the printed update with gamma_0..12
+ *       (those coefficients discretise the condition with +c/2 times the
+ *       transverse Laplacian, the standard form; the printed equation's
+ *       minus sign is read as a typo).  On edges and corners the face
+ *       conditions involved, written in the inward coordinate s of each
+ *       face, are added and discretised at the centre of the edge square or
+ *       corner cube; the second derivatives along the face normals, which
+ *       would need points outside the domain, are replaced through the wave
+ *       equation, leaving
+ *         edge:   (d_sa + d_sb) d_t xi - 3/(2c) d_tt xi + c/2 d_ee xi = 0,
+ *         corner: (d_sa + d_sb + d_sc) d_t xi - 2/c d_tt xi = 0;
+ *       faces first, then edges, then corners;
  *   R17 a particle whose cell leaves [2, n_d - 3] on any axis is lost.
  */
 #include <math.h>
@@ -56,7 +68,8 @@ typedef struct orc_sim {
     int n[3];
     double d[3], o[3];
     double nu, A;
-    int N, sc, bc[3]; /* bc: 0 = first-order Mur, 1 = periodic */
+    int N, sc, bc[3]; /* bc: 0 = Mur absorbing boundary, 1 = periodic */
+    int mur2;         /* the Mur boundaries are of second order */
     double lambda_u, K, gamma_beam, z_e;
     /* derived constants */
     double dt, dtb, a1, a2, a4, a6, a8;
@@ -129,7 +142,18 @@ orc_sim *orc_create(const int n[3], const double d[3], const double origin[3],
         s->n[a] = n[a];
         s->d[a] = d[a];
         s->o[a] = origin[a];
-        s->bc[a] = bc[a];
+        s->bc[a] = bc[a] == 1;
+    }
+    /* input codes per axis: 0 first-order Mur, 1 periodic, 2 second-order Mur;
+       the absorbing axes share one order */
+    {
+        int has1 = 0, has2 = 0;
+        for (int a = 0; a < 3; a++) {
+            has1 |= bc[a] == 0;
+            has2 |= bc[a] == 2;
+        }
+        if (has1 && has2) abort();
+        s->mur2 = has2;
     }
     s->nu = courant;
     s->N = substeps;
@@ -355,6 +379,7 @@ int orc_set_particles(orc_sim *s, long np, const double *x, const double *u, dou
 /* ---- O2: potential update, eq. (updateEquation) -------------------------- */
 
 static void boundary_mur1(orc_sim *s, int comp);
+static void boundary_mur2(orc_sim *s, int comp);
 
 void orc_field_update(orc_sim *s)
 {
@@ -395,7 +420,8 @@ void orc_field_update(orc_sim *s)
                            s->a4 * bym + s->a6 * P[IX(s, i, j, k + 1)] + s->a6 * P[IX(s, i, j, k - 1)] +
                            s->a8 * zeta;
                 }
-        boundary_mur1(s, c);
+        if (s->mur2) boundary_mur2(s, c);
+        else boundary_mur1(s, c);
     }
 }
 
@@ -422,6 +448,117 @@ static void boundary_mur1(orc_sim *s, int c)
                     long p = IX(s, v[0], v[1], v[2]), q = IX(s, w[0], w[1], w[2]);
                     const double *b = s->mur[top];
                     R[p] = b[0] * Q[p] + b[1] * P[p] + b[2] * Q[q] + b[3] * P[q] + b[4] * R[q];
+                }
+}
+
+/* ---- O3b: second-order Mur boundary (section "Boundary Truncation"),
+        faces with the printed gamma coefficients, edges and corners by
+        reading R19 --------------------------------------------------------- */
+
+/* face normal to axis a (either side): transverse axes u < v */
+static void mur2_face(orc_sim *s, int c, const int v[3], int a)
+{
+    const double *P = s->pot[s->lcur][c], *Q = s->pot[s->lprev][c];
+    double *R = s->pot[s->lnext][c];
+    int u = (a == 0) ? 1 : 0, w = (a == 2) ? 1 : 2;
+    double cdt = ORC_C * s->dt, h = s->d[a];
+    double ru = cdt / s->d[u], rw = cdt / s->d[w];
+    double g0 = (cdt - h) / (cdt + h), g4 = g0;
+    double g1 = h * (2.0 - rw * rw - ru * ru) / (cdt + h), g3 = g1;
+    double g2 = -1.0;
+    double gu = ru * ru * h / (2.0 * (cdt + h)); /* gamma_5, 6, 9, 10 */
+    double gw = rw * rw * h / (2.0 * (cdt + h)); /* gamma_7, 8, 11, 12 */
+    int in[3] = {v[0], v[1], v[2]};
+    in[a] += (v[a] == 0) ? 1 : -1; /* the layer inside */
+    int bp[3], bm[3], ip[3], im[3];
+    double tb = 0.0, ti = 0.0; /* transverse neighbours at level n, boundary / inner layer */
+    for (int t = 0; t < 2; t++) {
+        int ax = t ? w : u;
+        double g = t ? gw : gu;
+        memcpy(bp, v, sizeof bp);
+        memcpy(bm, v, sizeof bm);
+        memcpy(ip, in, sizeof ip);
+        memcpy(im, in, sizeof im);
+        bp[ax]++;
+        bm[ax]--;
+        ip[ax]++;
+        im[ax]--;
+        tb += g * (P[IX(s, bp[0], bp[1], bp[2])] + P[IX(s, bm[0], bm[1], bm[2])]);
+        ti += g * (P[IX(s, ip[0], ip[1], ip[2])] + P[IX(s, im[0], im[1], im[2])]);
+    }
+    long p = IX(s, v[0], v[1], v[2]), q = IX(s, in[0], in[1], in[2]);
+    R[p] = g0 * Q[p] + g1 * P[p] + g2 * Q[q] + g3 * P[q] + g4 * R[q] + ti + tb;
+}
+
+/* the summed edge / corner condition of reading R19, discretised at the
+   centre of the square (na = 2 face axes) or cube (na = 3) whose corner v is
+   the unknown point, evaluated with the value x in place of xi^{n+1}(v) */
+static double mur2_joint_residual(orc_sim *s, int c, const int v[3], const int ax[3], int na,
+                                  double x)
+{
+    const double *P = s->pot[s->lcur][c], *Q = s->pot[s->lprev][c], *R = s->pot[s->lnext][c];
+    double dt = s->dt;
+    int npt = 1 << na;
+    double sum_dt[3] = {0.0, 0.0, 0.0}, dtt = 0.0, dee = 0.0;
+    int e = 3 - ax[0] - ax[1]; /* the edge direction (edges only) */
+    for (int m = 0; m < npt; m++) {
+        int pt[3] = {v[0], v[1], v[2]};
+        for (int t = 0; t < na; t++) {
+            int off = (m >> t) & 1;
+            pt[ax[t]] += off * ((v[ax[t]] == 0) ? 1 : -1);
+        }
+        long p = IX(s, pt[0], pt[1], pt[2]);
+        double rn = (m == 0) ? x : R[p];
+        /* d_s d_t: inner minus outer layer along each face normal */
+        for (int t = 0; t < na; t++) {
+            double sgn = ((m >> t) & 1) ? 1.0 : -1.0;
+            sum_dt[t] += sgn * (rn - Q[p]);
+        }
+        dtt += rn - 2.0 * P[p] + Q[p];
+        if (na == 2) {
+            int pe[3], me[3];
+            memcpy(pe, pt, sizeof pe);
+            memcpy(me, pt, sizeof me);
+            pe[e]++;
+            me[e]--;
+            dee += P[IX(s, pe[0], pe[1], pe[2])] - 2.0 * P[p] + P[IX(s, me[0], me[1], me[2])];
+        }
+    }
+    /* averages over the points of the square / cube */
+    double inv = 1.0 / npt, pairs = 2.0 / npt;
+    double res = 0.0;
+    for (int t = 0; t < na; t++) res += sum_dt[t] * pairs / (2.0 * dt * s->d[ax[t]]);
+    dtt *= inv / (dt * dt);
+    if (na == 2) {
+        dee *= inv / (s->d[e] * s->d[e]);
+        res += -3.0 / (2.0 * ORC_C) * dtt + 0.5 * ORC_C * dee;
+    } else {
+        res += -2.0 / ORC_C * dtt;
+    }
+    return res;
+}
+
+static void boundary_mur2(orc_sim *s, int c)
+{
+    double *R = s->pot[s->lnext][c];
+    int ext[3];
+    for (int a = 0; a < 3; a++) ext[a] = extent(s, c, a);
+    for (int stage = 1; stage <= 3; stage++)
+        for (int k = 0; k < ext[2]; k++)
+            for (int j = 0; j < ext[1]; j++)
+                for (int i = 0; i < ext[0]; i++) {
+                    int v[3] = {i, j, k}, ax[3], nb = 0;
+                    for (int a = 0; a < 3; a++)
+                        if (!s->bc[a] && (v[a] == 0 || v[a] == ext[a] - 1)) ax[nb++] = a;
+                    if (nb != stage) continue;
+                    if (nb == 1) {
+                        mur2_face(s, c, v, ax[0]);
+                    } else {
+                        /* linear in the unknown: solve r(0) + (r(1) - r(0)) x = 0 */
+                        double r0 = mur2_joint_residual(s, c, v, ax, nb, 0.0);
+                        double r1 = mur2_joint_residual(s, c, v, ax, nb, 1.0);
+                        R[IX(s, v[0], v[1], v[2])] = -r0 / (r1 - r0);
+                    }
                 }
 }
 

@@ -234,6 +234,186 @@ def test_mur1_absorbs_most_of_an_oblique_pulse():
 
 
 # ---------------------------------------------------------------------------
+# Second-order Mur (section "Boundary Truncation", reading R19)
+# ---------------------------------------------------------------------------
+
+POT = ("Ax", "Ay", "Az", "phi")
+
+
+def _ext(n, bc, c):
+    return [n[a] - 1 if (c == a and bc[a] != 1) else n[a] for a in range(3)]
+
+
+def _random_level_fields(sim, n, rng, scale=1.0, smooth=False):
+    for lev in ("cur", "prev"):
+        for c in range(4):
+            a = rng.standard_normal((n[2], n[1], n[0])) * scale
+            sim.pot(c, lev)[:] = a
+
+
+def test_mur2_faces_equal_mur1_for_transversely_uniform_fields():
+    """With no variation across a z face the transverse second differences
+    vanish and gamma_1 + gamma_9..12 = beta_1, gamma_3 + gamma_5..8 = beta_3:
+    the second-order face update is the first-order one."""
+    n = (8, 8, 40)
+    d, origin = _mesh(n)
+    kk = np.arange(n[2])
+    out = []
+    for bc in ((1, 1, 0), (1, 1, 2)):
+        sim = oracle.OracleSim(n, d, origin, courant=0.9, bc=bc, K=0.0)
+        _empty(sim)
+        for c in range(4):
+            sim.pot(c, "cur")[:] = np.sin(0.37 * kk + c)[:, None, None]
+            sim.pot(c, "prev")[:] = np.sin(0.37 * kk + c - 0.2)[:, None, None]
+        sim.field_update()
+        out.append([sim.pot(c, "next").copy() for c in range(4)])
+    for c in range(4):
+        ez = _ext(n, (1, 1, 2), c)[2]
+        for k in (0, ez - 1):
+            a, b = out[0][c][k], out[1][c][k]
+            assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a)), (POT[c], k)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (2, 2, 2), (2, 1, 2)])
+def test_mur_keeps_a_uniform_field_linear_in_time(bc):
+    """A field constant in space and linear in time solves the wave equation
+    and every discrete boundary condition (faces, edges, corners): one update
+    must return its next value everywhere."""
+    n = (9, 10, 12)
+    d, origin = _mesh(n, ax=2.0, ay=3.0)
+    sim = oracle.OracleSim(n, d, origin, courant=0.8, bc=bc, K=0.0)
+    _empty(sim)
+    c0, c1 = 0.3, 1.7
+    for c in range(4):
+        sim.pot(c, "prev")[:] = c0 + c1 * (c + 1)
+        sim.pot(c, "cur")[:] = c0 + c1 * (c + 2)
+    sim.field_update()
+    for c in range(4):
+        e = _ext(n, bc, c)
+        got = sim.pot(c, "next")[:e[2], :e[1], :e[0]]
+        want = c0 + c1 * (c + 3)
+        assert np.max(np.abs(got - want)) < 1e-12 * abs(want), POT[c]
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_mur2_face_update_satisfies_the_discretised_condition(axis):
+    """The printed gamma_0..12 update solves the discretised second-order
+    condition  d_s d_t xi - (1/c) d_tt xi + (c/2) (d_uu + d_vv) xi = 0
+    (s inward, u and v across the face; the + sign of reading R19), each
+    derivative discretised as printed for the z face: central in time, the
+    transverse second differences at level n averaged over the two layers.
+    Checked on both faces normal to each axis, random fields."""
+    n = (10, 11, 12)
+    d, origin = _mesh(n, ax=2.0, ay=3.0)
+    bc = (2, 2, 2)
+    sim = oracle.OracleSim(n, d, origin, courant=0.9, bc=bc, K=0.0)
+    _empty(sim)
+    _random_level_fields(sim, n, np.random.default_rng(5))
+    dt = sim.const["dt"]
+    sim.field_update()
+    for c in range(4):
+        P = np.moveaxis(sim.pot(c, "cur"), [2, 1, 0], [0, 1, 2])   # [i, j, k]
+        Q = np.moveaxis(sim.pot(c, "prev"), [2, 1, 0], [0, 1, 2])
+        R = np.moveaxis(sim.pot(c, "next"), [2, 1, 0], [0, 1, 2])
+        e = _ext(n, bc, c)
+        u, v = [t for t in range(3) if t != axis]
+        for side in (0, 1):
+            b = 0 if side == 0 else e[axis] - 1
+            inner = 1 if side == 0 else e[axis] - 2
+            worst = 0.0
+            for pu in range(1, e[u] - 1):
+                for pv in range(1, e[v] - 1):
+                    def at(arr, s_, du=0, dv=0):
+                        idx = [0, 0, 0]
+                        idx[axis] = s_
+                        idx[u] = pu + du
+                        idx[v] = pv + dv
+                        return arr[tuple(idx)]
+                    dsdt = ((at(R, inner) - at(R, b)) - (at(Q, inner) - at(Q, b))) / (2 * dt * d[axis])
+                    dtt = ((at(R, inner) - 2 * at(P, inner) + at(Q, inner)) +
+                           (at(R, b) - 2 * at(P, b) + at(Q, b))) / (2 * dt * dt)
+                    lap = 0.0
+                    for lay in (inner, b):
+                        lap += (at(P, lay, du=1) - 2 * at(P, lay) + at(P, lay, du=-1)) / d[u] ** 2
+                        lap += (at(P, lay, dv=1) - 2 * at(P, lay) + at(P, lay, dv=-1)) / d[v] ** 2
+                    res = dsdt - dtt / C + C / 4.0 * lap
+                    scale = abs(at(R, b)) / (dt * d[axis]) + abs(at(P, b)) / (C * dt * dt)
+                    worst = max(worst, abs(res) / scale)
+            assert worst < 1e-12, (POT[c], axis, side, worst)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_mur2_boundary_is_mirror_symmetric(axis):
+    """Fields mirror-symmetric along one axis stay so after an update with
+    second-order Mur on every face, edge and corner: low and high sides of
+    each condition agree."""
+    n = (9, 10, 11)
+    d, origin = _mesh(n, ax=2.0, ay=3.0)
+    bc = (2, 2, 2)
+    sim = oracle.OracleSim(n, d, origin, courant=0.9, bc=bc, K=0.0)
+    _empty(sim)
+    rng = np.random.default_rng(7)
+    for lev in ("cur", "prev"):
+        for c in range(4):
+            e = _ext(n, bc, c)
+            a = rng.standard_normal((n[2], n[1], n[0]))
+            ax = 2 - axis
+            sl = [slice(None)] * 3
+            sl[ax] = slice(0, e[axis])
+            part = a[tuple(sl)]
+            a[tuple(sl)] = 0.5 * (part + np.flip(part, axis=ax))
+            sim.pot(c, lev)[:] = a
+    sim.field_update()
+    for c in range(4):
+        e = _ext(n, bc, c)
+        g = sim.pot(c, "next")[:e[2], :e[1], :e[0]]
+        m = np.flip(g, axis=2 - axis)
+        assert np.max(np.abs(g - m)) < 1e-12 * np.max(np.abs(g)), (POT[c], axis)
+
+
+def _oblique_packet_reflection(bc, theta_deg, nx=32, nz=320, steps=480):
+    """Energy (sum of phi^2) left after a plane-wave packet, periodic across
+    (x, y) with k_x = 2 pi / L_x and incident at theta on the z faces, has
+    met them; relative to the incident energy."""
+    dz = 1e-6
+    d, n = (2 * dz, 2 * dz, dz), (nx, 2, nz)
+    origin = tuple(-(n[a] - 1) / 2.0 * d[a] for a in range(3))
+    sim = oracle.OracleSim(n, d, origin, courant=0.9, bc=bc, K=0.0)
+    _empty(sim)
+    dt = sim.const["dt"]
+    kx = 2 * np.pi / (nx * d[0])
+    kz = kx / np.tan(np.radians(theta_deg))
+    x, z = np.arange(nx) * d[0], np.arange(nz) * dz
+    z0, w = 0.5 * nz * dz, 50 * dz
+    om = C * np.hypot(kx, kz)
+    cg = C * kz / np.hypot(kx, kz)
+
+    def packet(t):  # travelling towards -z
+        env = np.exp(-((z - z0 + cg * t) / w) ** 2) * np.cos(kz * z + om * t)
+        return env[:, None, None] * np.ones((1, 2, 1)) * np.cos(kx * x)[None, None, :]
+
+    sim.pot(3, "cur")[:] = packet(0.0)
+    sim.pot(3, "prev")[:] = packet(-dt)
+    e0 = np.sum(sim.pot(3, "cur") ** 2)
+    sim.step(steps)
+    return float(np.sum(sim.pot(3, "cur") ** 2) / e0)
+
+
+def test_mur_oblique_reflection_matches_the_closed_forms():
+    """At incidence angle theta the first-order condition reflects the
+    amplitude (cos t - 1)/(cos t + 1), the second-order one its square
+    (Engquist-Majda).  A well-resolved packet at 30 degrees reproduces both
+    energy fractions (5.2e-3 and 2.7e-5): the second-order faces are
+    the printed gamma update with the sign of reading R19."""
+    theta = 30.0
+    r1 = (np.cos(np.radians(theta)) - 1) / (np.cos(np.radians(theta)) + 1)
+    e1 = _oblique_packet_reflection((1, 1, 0), theta)
+    e2 = _oblique_packet_reflection((1, 1, 2), theta)
+    assert 0.8 * r1 ** 2 < e1 < 1.25 * r1 ** 2, (e1, r1 ** 2)
+    assert 0.6 * r1 ** 4 < e2 < 1.6 * r1 ** 4, (e2, r1 ** 4)
+
+
+# ---------------------------------------------------------------------------
 # Field evaluation and interpolation
 # ---------------------------------------------------------------------------
 
