@@ -69,8 +69,15 @@ typedef enum {
 } mithra_precision;
 
 typedef enum {
-    MITHRA_BC_MUR1 = 0,    /* first-order Mur absorbing boundary */
-    MITHRA_BC_PERIODIC = 1 /* wrap-around (test configurations) */
+    MITHRA_BC_MUR1 = 0,     /* first-order Mur absorbing boundary (section
+                               "Boundary Truncation", beta coefficients) */
+    MITHRA_BC_PERIODIC = 1, /* wrap-around (test configurations) */
+    MITHRA_BC_MUR2 = 2      /* second-order Mur (same section): faces by the
+                               printed gamma_0..12 update, edges and corners
+                               from the face conditions involved, added at
+                               the centre of the edge square or corner cube.
+                               The absorbing axes of one mesh share one order
+                               (mixing 0 and 2 is EINVAL). */
 } mithra_bc;
 
 typedef enum {

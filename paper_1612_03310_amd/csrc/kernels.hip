@@ -13,6 +13,8 @@
 
 namespace mithra {
 
+constexpr double C_LIGHT_D = 299792458.0;  // speed of light [m/s]
+
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
@@ -253,7 +255,8 @@ __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ s
     const int i = it.y * TX + tx, j = it.z * TY + ty;
     const bool act = i >= lo[0] && i <= hi[0] && j >= lo[1] && j <= hi[1];
     const int ext0 = comp_extent(S, comp, 0);
-    const bool face = fuse_x && !S.bc[0] && j >= lo[1] && j <= hi[1] && (i == 0 || i == ext0 - 1);
+    const bool face = fuse_x && !S.bc[0] && !S.mur2 && j >= lo[1] && j <= hi[1] &&
+                      (i == 0 || i == ext0 - 1);
     const R mb0 = (R)S.murb0[0], mb1 = (R)S.murb1[0];
 
     const R a1 = (R)S.a1, ax = (R)S.ax, ay = (R)S.ay, az = (R)S.az, A = (R)S.A;
@@ -425,6 +428,159 @@ __global__ __launch_bounds__(BLOCK) void k_boundary(const SimDev *__restrict__ s
             val = b0 * Q[p] + b1 * P[p] - Q[q] + b1 * P[q] + b0 * val;
         }
         Rn[pts[0]] = val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2b. second-order Mur (section "Boundary Truncation"), in three launches:
+//     faces (points on one face), then edges, then corners, each reading
+//     only psi^{s+1} values written before it.  On a face normal to a, with
+//     b the boundary point, q its inward neighbour and u, w the other axes:
+//       psi^{s+1}_b = g0 (psi^{s-1}_b + psi^{s+1}_q) + g1 (psi^s_b + psi^s_q)
+//                     - psi^{s-1}_q + gu sum_{+-u} (psi^s_b + psi^s_q)
+//                     + gw sum_{+-w} (psi^s_b + psi^s_q)
+//     (the printed gamma coefficients).  Edges and corners: the face
+//     conditions involved, added in inward coordinates and discretised at
+//     the centre of the edge square or corner cube, with the second
+//     derivatives along the face normals replaced through the wave
+//     equation:  (d_sa + d_sb) d_t - 3/(2c) d_tt + c/2 d_ee = 0 on an edge
+//     along e, (d_sa + d_sb + d_sc) d_t - 2/c d_tt = 0 at a corner; each is
+//     solved for the one unknown corner of the square or cube.
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_mur2(const SimDev *__restrict__ sims,
+                                                 const BSeg *__restrict__ segs, int nseg,
+                                                 long long total, Arena ar)
+{
+    const long long step = *ar.d_step;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < total;
+         t += (long long)gridDim.x * BLOCK) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segs[mid].start <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BSeg g = segs[lo];
+        const SimDev &S = sims[g.sim];
+        const int c = g.comp;
+        const long long r = t - g.start;
+        int ext[3], ilo[3], nin[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ext[a] = comp_extent(S, c, a);
+            ilo[a] = S.bc[a] ? 0 : 1;
+            nin[a] = S.bc[a] ? ext[a] : ext[a] - 2;
+        }
+        const R *P = (const R *)ar.pot[step % 3][c] + S.cell0;
+        const R *Q = (const R *)ar.pot[(step + 2) % 3][c] + S.cell0;
+        R *Rn = (R *)ar.pot[(step + 1) % 3][c] + S.cell0;
+        auto idx = [&](const int *v) {
+            const int i = axis_index(v[0], S.n[0], S.bc[0]);
+            const int j = axis_index(v[1], S.n[1], S.bc[1]);
+            const int k = axis_index(v[2], S.n[2], S.bc[2]);
+            return ((long long)k * S.n[1] + j) * S.n[0] + i;
+        };
+        int v[3];
+        if (g.group < 3) {
+            const int a = g.group, u = a == 0 ? 1 : 0, w = a == 2 ? 1 : 2;
+            const long long fa = (long long)nin[u] * nin[w];
+            const int side = (int)(r / fa), rem = (int)(r % fa);
+            v[u] = ilo[u] + rem % nin[u];
+            v[w] = ilo[w] + rem / nin[u];
+            v[a] = side ? ext[a] - 1 : 0;
+            int q[3] = {v[0], v[1], v[2]};
+            q[a] += side ? -1 : 1;
+            double tr = 0.0;
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                const int ax = tt ? w : u;
+                const double gt = S.murg[a][2 + tt];
+#pragma unroll
+                for (int sgn = -1; sgn <= 1; sgn += 2) {
+                    int vb[3] = {v[0], v[1], v[2]}, vq[3] = {q[0], q[1], q[2]};
+                    vb[ax] += sgn;
+                    vq[ax] += sgn;
+                    tr += gt * ((double)P[idx(vb)] + (double)P[idx(vq)]);
+                }
+            }
+            const long long pb = idx(v), pq = idx(q);
+            const double g0 = S.murg[a][0], g1 = S.murg[a][1];
+            Rn[pb] = (R)(g0 * ((double)Q[pb] + (double)Rn[pq]) + g1 * ((double)P[pb] + (double)P[pq]) -
+                         (double)Q[pq] + tr);
+        } else if (g.group < 6) {
+            const int e = g.group - 3, a = e == 0 ? 1 : 0, b = e == 2 ? 1 : 2;
+            const int corner = (int)(r / nin[e]);
+            v[e] = ilo[e] + (int)(r % nin[e]);
+            const int sa = corner & 1, sb = corner >> 1;
+            v[a] = sa ? ext[a] - 1 : 0;
+            v[b] = sb ? ext[b] - 1 : 0;
+            // square points (ia, ib): ia, ib = steps inward along a, b
+            double Rv[2][2], Pv[2][2], Qv[2][2], De = 0.0;
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                for (int ia = 0; ia < 2; ++ia) {
+                    int pt[3] = {v[0], v[1], v[2]};
+                    pt[a] += ia * (sa ? -1 : 1);
+                    pt[b] += ib * (sb ? -1 : 1);
+                    const long long p = idx(pt);
+                    Rv[ia][ib] = (ia | ib) ? (double)Rn[p] : 0.0;
+                    Pv[ia][ib] = (double)P[p];
+                    Qv[ia][ib] = (double)Q[p];
+                    int pp[3] = {pt[0], pt[1], pt[2]}, pm[3] = {pt[0], pt[1], pt[2]};
+                    pp[e] += 1;
+                    pm[e] -= 1;
+                    De += (double)P[idx(pp)] - 2.0 * Pv[ia][ib] + (double)P[idx(pm)];
+                }
+            const double ka = 0.25 / (S.dt * S.d[a]), kb = 0.25 / (S.dt * S.d[b]);
+            const double kt = 3.0 / (8.0 * C_LIGHT_D * S.dt * S.dt);
+            const double ke = C_LIGHT_D / (8.0 * S.d[e] * S.d[e]);
+            double sP = 0.0, sQ = 0.0;
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                for (int ia = 0; ia < 2; ++ia) {
+                    sP += Pv[ia][ib];
+                    sQ += Qv[ia][ib];
+                }
+            const double rest =
+                ka * ((Rv[1][0] - Qv[1][0] + Qv[0][0]) + (Rv[1][1] - Rv[0][1]) - (Qv[1][1] - Qv[0][1])) +
+                kb * ((Rv[0][1] - Qv[0][1] + Qv[0][0]) + (Rv[1][1] - Rv[1][0]) - (Qv[1][1] - Qv[1][0])) -
+                kt * ((Rv[1][0] + Rv[0][1] + Rv[1][1]) - 2.0 * sP + sQ) + ke * De;
+            Rn[idx(v)] = (R)(rest / (ka + kb + kt));
+        } else {
+            const int corner = (int)r;
+            int sd[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                sd[a] = (corner >> a) & 1;
+                v[a] = sd[a] ? ext[a] - 1 : 0;
+            }
+            double k[3], kt = 1.0 / (4.0 * C_LIGHT_D * S.dt * S.dt), rest = 0.0, den = kt;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                k[a] = 0.125 / (S.dt * S.d[a]);
+                den += k[a];
+            }
+            double sR = 0.0, sP = 0.0, sQ = 0.0;
+            for (int m = 0; m < 8; ++m) {
+                int pt[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) pt[a] = v[a] + ((m >> a) & 1) * (sd[a] ? -1 : 1);
+                const long long p = idx(pt);
+                const double rv = m ? (double)Rn[p] : 0.0, qv = (double)Q[p];
+                sR += rv;
+                sP += (double)P[p];
+                sQ += qv;
+                // d_s d_t along each axis: inner layer minus outer layer
+#pragma unroll
+                for (int a = 0; a < 3; ++a) rest += k[a] * (((m >> a) & 1) ? 1.0 : -1.0) * (rv - qv);
+            }
+            rest -= kt * (sR - 2.0 * sP + sQ);
+            Rn[idx(v)] = (R)(rest / den);
+        }
     }
 }
 
@@ -1593,6 +1749,17 @@ void launch_boundary(hipStream_t st, const SimDev *sims, const BSeg *segs, int n
                        total, ar);
 }
 
+template <typename R>
+void launch_mur2(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg, long long total,
+                 const Arena &ar)
+{
+    if (total <= 0) return;
+    long long nb = (total + BLOCK - 1) / BLOCK;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL((k_mur2<R>), dim3((unsigned)nb), dim3(BLOCK), 0, st, sims, segs, nseg, total,
+                       ar);
+}
+
 static int dealt_grid(int nitems, int chunk)
 {
     const long long round = 8LL * chunk;
@@ -1660,6 +1827,8 @@ void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long
                                     const Arena &, int, int, int, int);                         \
     template void launch_boundary<R>(hipStream_t, const SimDev *, const BSeg *, int, long long, \
                                      const Arena &);                                            \
+    template void launch_mur2<R>(hipStream_t, const SimDev *, const BSeg *, int, long long,     \
+                                 const Arena &);                                                \
     template void launch_push<R>(hipStream_t, const SimDev *, const int2 *, int, int,           \
                                  const Arena &);                                                \
     template void launch_deposit<R>(hipStream_t, const SimDev *, const int2 *, int, int,        \

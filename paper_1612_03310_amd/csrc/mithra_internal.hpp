@@ -28,7 +28,8 @@ enum Kind { K_STENCIL = 0, K_BOUNDARY, K_PUSH, K_DEPOSIT, K_SCAN, K_SCATTER, K_D
 // Per-simulation constants, read by every kernel (device copy in an array).
 struct SimDev {
     int n[3];
-    int bc[3];          // 0 Mur-1, 1 periodic
+    int bc[3];          // 1: periodic axis, 0: absorbing (Mur) faces
+    int mur2;           // the Mur faces are of second order
     int sc;             // space charge on
     int nsub;           // particle sub-steps per field step
     int nt[3];          // tiles per axis
@@ -50,6 +51,9 @@ struct SimDev {
     // potential update, eq. (updateEquation) in the regrouped form
     double a1, ax, ay, az, A, srcA, srcPhi;
     double murb0[3], murb1[3];  // first-order Mur beta_0 (= beta_4), beta_1 (= beta_3)
+    double murg[3][4];  // second-order Mur, per face axis: gamma_0 (= gamma_4),
+                        // gamma_1 (= gamma_3), and the transverse weights along
+                        // the lower (gamma_5,6,9,10) and higher (7,8,11,12) other axis
     // vertex fields
     double inv_dt, inv_2d[3];
     // particles
@@ -110,6 +114,10 @@ void launch_stencil(hipStream_t st, const SimDev *sims, const int4 *items, int n
 template <typename R>
 void launch_boundary(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg,
                      long long total, const Arena &ar);
+// second-order Mur, one stage (faces, edges or corners) per call
+template <typename R>
+void launch_mur2(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg, long long total,
+                 const Arena &ar);
 // push and deposit: the tile table is dealt to the XCDs in chunks of `chunk`
 // tiles
 template <typename R>

@@ -85,6 +85,10 @@ struct Batch {
     BSeg *d_bseg = nullptr;
     int nbseg = 0;
     long long nb_total = 0;
+    // second-order Mur: faces, edges, corners (one launch each, in order)
+    BSeg *d_m2seg[3] = {nullptr, nullptr, nullptr};
+    int nm2seg[3] = {0, 0, 0};
+    long long nm2_total[3] = {0, 0, 0};
     int2 *d_tiles = nullptr;
     int n_tiles = 0;
     int tile_chunk = 1;  // tiles per chunk dealt to one XCD (push, deposit)
@@ -182,8 +186,19 @@ static mithra_status validate(int s, const mithra_mesh &m, const mithra_undulato
             return fail(MITHRA_EINVAL, "sim %d: d[%d] must be positive and finite", s, a);
         if (!std::isfinite(m.origin[a]))
             return fail(MITHRA_EINVAL, "sim %d: origin[%d] must be finite", s, a);
-        if (m.bc[a] != MITHRA_BC_MUR1 && m.bc[a] != MITHRA_BC_PERIODIC)
-            return fail(MITHRA_EINVAL, "sim %d: bc[%d] must be 0 (Mur) or 1 (periodic)", s, a);
+        if (m.bc[a] != MITHRA_BC_MUR1 && m.bc[a] != MITHRA_BC_PERIODIC &&
+            m.bc[a] != MITHRA_BC_MUR2)
+            return fail(MITHRA_EINVAL,
+                        "sim %d: bc[%d] must be 0 (Mur-1), 1 (periodic) or 2 (Mur-2)", s, a);
+    }
+    {
+        bool o1 = false, o2 = false;
+        for (int a = 0; a < 3; ++a) {
+            o1 |= m.bc[a] == MITHRA_BC_MUR1;
+            o2 |= m.bc[a] == MITHRA_BC_MUR2;
+        }
+        if (o1 && o2)
+            return fail(MITHRA_EINVAL, "sim %d: first- and second-order Mur axes cannot be mixed", s);
     }
     const double cells = (double)m.n[0] * m.n[1] * m.n[2];
     if (cells > 1.5e9) return fail(MITHRA_EINVAL, "sim %d: more than 1.5e9 grid points", s);
@@ -244,11 +259,14 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     const mithra_mesh &m = h.mesh;
     for (int a = 0; a < 3; ++a) {
         S.n[a] = m.n[a];
-        S.bc[a] = m.bc[a];
+        S.bc[a] = m.bc[a] == MITHRA_BC_PERIODIC ? 1 : 0;
         S.nt[a] = (m.n[a] + TILE - 1) / TILE;
         S.d[a] = m.d[a];
         S.origin[a] = m.origin[a];
     }
+    S.mur2 = (m.bc[0] == MITHRA_BC_MUR2 || m.bc[1] == MITHRA_BC_MUR2 || m.bc[2] == MITHRA_BC_MUR2)
+                 ? 1
+                 : 0;
     S.sc = m.space_charge;
     S.nsub = m.substeps;
     S.nkeys = S.nt[0] * S.nt[1] * S.nt[2] * TILE_CELLS;
@@ -266,6 +284,15 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     for (int a = 0; a < 3; ++a) {
         S.murb0[a] = (cdt - m.d[a]) / (cdt + m.d[a]);
         S.murb1[a] = 2.0 * m.d[a] / (cdt + m.d[a]);
+        {
+            // second-order face normal to a: transverse axes u < w
+            const int u = a == 0 ? 1 : 0, w = a == 2 ? 1 : 2;
+            const double h = m.d[a], ru = cdt / m.d[u], rw = cdt / m.d[w];
+            S.murg[a][0] = (cdt - h) / (cdt + h);
+            S.murg[a][1] = h * (2.0 - rw * rw - ru * ru) / (cdt + h);
+            S.murg[a][2] = ru * ru * h / (2.0 * (cdt + h));
+            S.murg[a][3] = rw * rw * h / (2.0 * (cdt + h));
+        }
         S.inv_2d[a] = 0.5 / m.d[a];
         S.cdtb_d[a] = C_LIGHT * h.dtb / m.d[a];
     }
@@ -352,7 +379,7 @@ static bool x_faces_fusable(const Batch &b, int tx)
     if (tx < 2) return false;
     for (int s = 0; s < b.nsim; ++s) {
         const SimDev &S = b.sd[s];
-        if (S.bc[0]) continue;
+        if (S.bc[0] || S.mur2) continue;
         for (int c = 0; c < 4; ++c) {
             if (c == 3 && !S.sc) continue;
             const int ext = c == 0 ? S.n[0] - 1 : S.n[0];
@@ -381,6 +408,7 @@ static mithra_status build_tables(Batch &b)
     long long start = 0;
     for (int s = 0; s < b.nsim; ++s) {
         const SimDev &S = b.sd[s];
+        if (S.mur2) continue;
         for (int c = 0; c < 4; ++c) {
             if (c == 3 && !S.sc) continue;
             int ext[3], ni[3];
@@ -407,6 +435,44 @@ static mithra_status build_tables(Batch &b)
     b.nbseg = (int)segs.size();
     b.nb_total = start;
     if ((st = upload_table(b, segs, &b.d_bseg))) return st;
+    // second-order Mur: faces without their edges (group = face axis), edges
+    // without their corners (group 3 + edge axis), corners (group 6)
+    for (int stage = 0; stage < 3; ++stage) {
+        std::vector<BSeg> m2;
+        long long st2 = 0;
+        for (int s = 0; s < b.nsim; ++s) {
+            const SimDev &S = b.sd[s];
+            if (!S.mur2) continue;
+            for (int c = 0; c < 4; ++c) {
+                if (c == 3 && !S.sc) continue;
+                int ext[3], ni[3];
+                for (int a = 0; a < 3; ++a) {
+                    ext[a] = (c == a && !S.bc[a]) ? S.n[a] - 1 : S.n[a];
+                    ni[a] = S.bc[a] ? ext[a] : ext[a] - 2;
+                }
+                auto add = [&](int group, long long count) {
+                    BSeg sg;
+                    sg.sim = s;
+                    sg.comp = c;
+                    sg.group = group;
+                    sg.pad = 0;
+                    sg.start = st2;
+                    sg.count = count;
+                    st2 += count;
+                    m2.push_back(sg);
+                };
+                for (int a = 0; a < 3; ++a) {
+                    const int u = a == 0 ? 1 : 0, w = a == 2 ? 1 : 2;
+                    if (stage == 0 && !S.bc[a]) add(a, 2LL * ni[u] * ni[w]);
+                    if (stage == 1 && !S.bc[u] && !S.bc[w]) add(3 + a, 4LL * ni[a]);
+                }
+                if (stage == 2 && !S.bc[0] && !S.bc[1] && !S.bc[2]) add(6, 8);
+            }
+        }
+        b.nm2seg[stage] = (int)m2.size();
+        b.nm2_total[stage] = st2;
+        if ((st = upload_table(b, m2, &b.d_m2seg[stage]))) return st;
+    }
     // tiles
     std::vector<int2> tiles, plane, mesh, kin;
     int slot = 0;
@@ -794,6 +860,8 @@ static void enqueue_step(Batch &b, bool timed)
     mark(K_STENCIL, false);
     mark(K_BOUNDARY, true);
     launch_boundary<R>(st, b.d_sims, b.d_bseg, b.nbseg, b.nb_total, b.ar);
+    for (int stage = 0; stage < 3; ++stage)
+        launch_mur2<R>(st, b.d_sims, b.d_m2seg[stage], b.nm2seg[stage], b.nm2_total[stage], b.ar);
     mark(K_BOUNDARY, false);
     mark(K_PUSH, true);
     launch_push<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar);

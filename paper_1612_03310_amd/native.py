@@ -173,10 +173,19 @@ _hooks = []
 
 
 def use_torch_allocator(enable: bool = True):
-    """Route the library's device allocations through torch's caching allocator."""
+    """Route the library's device allocations through torch's caching allocator.
+
+    The two callbacks are created once and kept for the life of the module:
+    every simulation keeps the function pointers it was created with, so the
+    callback objects must outlive all of them."""
     lib = load_library()
     if not enable:
         _check(lib.mithra_set_allocator(None, None, None))
+        return
+    if _hooks:
+        a, f = _hooks
+        _check(lib.mithra_set_allocator(ctypes.cast(a, ctypes.c_void_p),
+                                        ctypes.cast(f, ctypes.c_void_p), None))
         return
     import torch
 
@@ -194,7 +203,7 @@ def use_torch_allocator(enable: bool = True):
         live.pop(int(ptr) if ptr else 0, None)
 
     a, f = _ALLOC_T(_alloc), _FREE_T(_free)
-    _hooks[:] = [a, f]
+    _hooks.extend((a, f))
     _check(lib.mithra_set_allocator(ctypes.cast(a, ctypes.c_void_p),
                                     ctypes.cast(f, ctypes.c_void_p), None))
 

@@ -49,3 +49,16 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.mithra_run(None, 1) == native.EINVAL
     assert b"NULL" in lib.mithra_last_error()
     assert lib.mithra_set_allocator(ctypes.c_void_p(1), None, None) == native.EINVAL
+
+
+def test_allocator_callbacks_outlive_every_simulation():
+    """Each simulation keeps the allocator function pointers it was created
+    with; installing the hook again must not replace (and free) the callback
+    objects an existing simulation still calls."""
+    native.use_torch_allocator(True)
+    first = list(native._hooks)
+    native.use_torch_allocator(True)
+    native.use_torch_allocator(False)
+    native.use_torch_allocator(True)
+    assert len(native._hooks) == 2
+    assert native._hooks[0] is first[0] and native._hooks[1] is first[1]

@@ -122,7 +122,7 @@ def _random_fields(n, bc, rng):
     out = {}
     for c, name in enumerate(POT):
         a = rng.standard_normal((nz, ny, nx))
-        if c < 3 and not bc[c]:
+        if c < 3 and bc[c] != 1:  # an absorbing axis (Mur of either order)
             idx = [slice(None)] * 3
             idx[2 - c] = -1
             a[tuple(idx)] = 0.0
@@ -132,14 +132,17 @@ def _random_fields(n, bc, rng):
 
 @pytest.mark.parametrize("bc,n", [((0, 0, 0), (40, 36, 50)), ((1, 1, 0), (40, 36, 50)),
                                   ((1, 1, 1), (40, 36, 50)), ((0, 1, 0), (40, 36, 50)),
-                                  ((0, 0, 0), (65, 36, 50))])
+                                  ((0, 0, 0), (65, 36, 50)), ((2, 2, 2), (40, 36, 50)),
+                                  ((1, 1, 2), (40, 36, 50)), ((2, 1, 2), (40, 36, 50)),
+                                  ((2, 2, 1), (40, 36, 50)), ((2, 2, 2), (65, 36, 50))])
 def test_potential_update_and_mur_match_oracle(bc, n):
     """One step of eq. (updateEquation) plus first-order Mur on faces, edges
     and corners, with random potentials and sources, on meshes whose sizes are
     not multiples of the 8-cell tiles.  At 40 cells along x the stencil pass
     updates the x faces itself; at 65 the high x face of the potentials
     falls on the first lane of a wavefront and the boundary kernel takes
-    them."""
+    them.  Code 2 selects second-order Mur (faces, edges and corners in the
+    boundary kernels)."""
     dz = 2e-6
     d = (4 * dz, 3 * dz, dz)
     origin = tuple(-(n[a] - 1) / 2 * d[a] for a in range(3))
@@ -223,7 +226,7 @@ def test_tiny_config_full_loop_f64():
 
 
 @pytest.mark.parametrize("variant", ["ragged_substeps", "no_space_charge", "courant_one",
-                                     "standard_scheme"])
+                                     "standard_scheme", "mur2"])
 def test_variants_full_loop_f64(variant):
     kw = dict()
     n = (40, 44, 72)
@@ -233,6 +236,8 @@ def test_variants_full_loop_f64(variant):
         kw = dict(space_charge=0)
     elif variant == "courant_one":
         kw = dict(courant=1.0)
+    elif variant == "mur2":
+        kw = dict(bc=(2, 2, 2))
     w = W.make_workload(variant, n, 3000, 120.0, 1.3, 0.015, 1e-4, 77, 60, **kw)
     if variant == "standard_scheme":
         w.nsfd_A = 0.0
@@ -418,6 +423,12 @@ def test_invalid_meshes_are_rejected():
     assert e.value.status == native.EINVAL
     with pytest.raises(native.MithraError) as e:
         native.Sim((4, 16, 16), (4e-6, 4e-6, 1e-6), (0, 0, 0))
+    assert e.value.status == native.EINVAL
+    with pytest.raises(native.MithraError) as e:  # Mur orders cannot be mixed
+        native.Sim(n, (4e-6, 4e-6, 1e-6), (0, 0, 0), bc=(0, 2, 2))
+    assert e.value.status == native.EINVAL and "mixed" in str(e.value)
+    with pytest.raises(native.MithraError) as e:
+        native.Sim(n, (4e-6, 4e-6, 1e-6), (0, 0, 0), bc=(3, 0, 0))
     assert e.value.status == native.EINVAL
 
 
