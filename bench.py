@@ -73,6 +73,24 @@ def boundary_points(w, tile_x=None):
     return tot
 
 
+def mur2_boundary_bytes(w, rs):
+    """Algorithmic bytes of the second-order Mur launches per step: a face
+    point reads 13 values (psi^{s-1}, psi^s of itself and its inward
+    neighbour, psi^{s+1} of the neighbour, psi^s of the four transverse
+    neighbours of both) and writes one; an edge point 20 + 1; a corner 24 + 1."""
+    comps = 4 if w.space_charge else 3
+    faces = edges = corners = 0
+    for c in range(comps):
+        ext = [w.n[a] - (1 if c == a else 0) for a in range(3)]
+        ni = [e - 2 for e in ext]
+        for a in range(3):
+            u, v = [t for t in range(3) if t != a]
+            faces += 2 * ni[u] * ni[v]
+            edges += 4 * ni[a]
+        corners += 8
+    return (14 * faces + 21 * edges + 25 * corners) * rs
+
+
 def source_hash():
     h = hashlib.sha256()
     for f in ("kernels.hip", "mithra_internal.hpp"):
@@ -186,6 +204,8 @@ def main():
                     help="first copy 1 GiB device-to-device 5 times (a kernel of known "
                          "traffic, to scale hardware byte counters)")
     ap.add_argument("--skip-large", action="store_true")
+    ap.add_argument("--no-mur2", action="store_true",
+                    help="skip the second-order Mur leg (mid configuration, bc code 2)")
     ap.add_argument("--workload", choices=("mid", "large"), default="mid",
                     help="headline workload: mid (128x128x512, 1M particles, f64, the "
                          "default) or large (256x256x2048, 16.8M particles, f32 split)")
@@ -245,6 +265,20 @@ def main():
 
     # ---- the large float configuration and the same shape in double ---------
     out_extra = {}
+    if args.workload == "mid" and not args.no_mur2:
+        import dataclasses
+        w2 = dataclasses.replace(w, bc=(2, 2, 2))
+        k2 = max(50, K // 4)
+        log("second-order Mur on the mid configuration, %d steps" % k2)
+        dt2, _, per2, _, info2 = measure(w2, prec, k2, Wm, torch, native)
+        b2 = mur2_boundary_bytes(w2, rs)
+        out_extra["mur2_mid"] = {
+            "bc": [2, 2, 2], "steps": k2, "ms_per_step": round(dt2 * 1e3 / k2, 5),
+            "cell_updates_per_s": w2.ncell * k2 / dt2, "boundary_ms": round(per2["boundary"], 5),
+            "boundary_algorithmic_GBs": round(b2 / (per2["boundary"] * 1e-3) / 1e9, 1),
+            "boundary_frac_hbm": round(b2 / (per2["boundary"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernels_ms": {k: round(v, 5) for k, v in per2.items()}}
+        log("  %.4f ms/step, boundary %.4f ms" % (dt2 * 1e3 / k2, per2["boundary"]))
     wl = None if args.skip_large else W.config(3)
     kl = max(20, min(200, K // 10))
     if wl is not None:

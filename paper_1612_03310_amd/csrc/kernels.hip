@@ -216,10 +216,12 @@ __device__ __forceinline__ bool vertex_valid(const SimDev &S, int i, int j, int 
 //      psi^{s+1} = -psi^{s-1} + a1 P + A (T_{k-1} + T_{k+1}) + (1 - 2A) T_k
 //                  + az (P_{k+1} + P_{k-1}) + src S,
 //    an exact regrouping of the z-averaged transverse neighbours.
-//    With fuse_x the same pass applies first-order Mur on the two x faces
-//    (points with y and z inside; the boundary kernel keeps the y and z
-//    faces): the face's inward neighbour along x is the adjacent lane of the
-//    wavefront, whose psi^{s-1}, psi^s and fresh psi^{s+1} arrive by shuffle.
+//    With fuse_x the same pass applies Mur on the two x faces (points with y
+//    and z inside; the boundary kernels keep the y and z faces, edges and
+//    corners): the face's inward neighbour along x is the adjacent lane of
+//    the wavefront, whose psi^{s-1}, psi^s and fresh psi^{s+1} arrive by
+//    shuffle; for second order the transverse neighbours at level s come
+//    from the plane-k LDS slot (y) and the z-march registers (z).
 //    The host enables it only when no face column sits at a wavefront edge.
 // ---------------------------------------------------------------------------
 
@@ -255,9 +257,12 @@ __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ s
     const int i = it.y * TX + tx, j = it.z * TY + ty;
     const bool act = i >= lo[0] && i <= hi[0] && j >= lo[1] && j <= hi[1];
     const int ext0 = comp_extent(S, comp, 0);
-    const bool face = fuse_x && !S.bc[0] && !S.mur2 && j >= lo[1] && j <= hi[1] &&
-                      (i == 0 || i == ext0 - 1);
-    const R mb0 = (R)S.murb0[0], mb1 = (R)S.murb1[0];
+    const bool face = fuse_x && !S.bc[0] && j >= lo[1] && j <= hi[1] && (i == 0 || i == ext0 - 1);
+    const bool m2 = S.mur2 != 0;
+    // first order: beta_0, beta_1; second order: gamma_0, gamma_1, and the
+    // transverse weights along y and z
+    const R mb0 = (R)(m2 ? S.murg[0][0] : S.murb0[0]), mb1 = (R)(m2 ? S.murg[0][1] : S.murb1[0]);
+    const R mgy = (R)S.murg[0][2], mgz = (R)S.murg[0][3];
 
     const R a1 = (R)S.a1, ax = (R)S.ax, ay = (R)S.ay, az = (R)S.az, A = (R)S.A;
     const R oma = (R)(1.0 - 2.0 * S.A);
@@ -328,10 +333,24 @@ __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ s
             // the low face reads lane + 1, the high face lane - 1
             const R vd = __shfl_down(val, 1), qd = __shfl_down(q, 1), pd = __shfl_down(Pc, 1);
             const R vu = __shfl_up(val, 1), qu = __shfl_up(q, 1), pu = __shfl_up(Pc, 1);
+            R trv = 0;  // second order: transverse neighbours at level s, both layers
+            if (m2) {
+                const R pmd = __shfl_down(Pm, 1), ppd = __shfl_down(Pp, 1);
+                const R pmu = __shfl_up(Pm, 1), ppu = __shfl_up(Pp, 1);
+                if (face) {
+                    const bool low = i == 0;
+                    // plane k sits in the slot before the one plane k+1 just went to
+                    const int cs = slot == 0 ? 2 : slot - 1;
+                    const int xi = low ? tx + 2 : tx;                     // the inner column
+                    trv = mgy * ((sP[cs][ty + 2][tx + 1] + sP[cs][ty][tx + 1]) +
+                                 (sP[cs][ty + 2][xi] + sP[cs][ty][xi])) +
+                          mgz * ((Pp + Pm) + (low ? ppd + pmd : ppu + pmu));
+                }
+            }
             if (face) {
                 const bool low = i == 0;
                 const R vq = low ? vd : vu, Qq = low ? qd : qu, Pq = low ? pd : pu;
-                __builtin_nontemporal_store(mb0 * q + mb1 * Pc - Qq + mb1 * Pq + mb0 * vq,
+                __builtin_nontemporal_store(mb0 * q + mb1 * Pc - Qq + mb1 * Pq + mb0 * vq + trv,
                                             &Rn[(long long)k * sxy + col]);
             }
         }

@@ -379,7 +379,7 @@ static bool x_faces_fusable(const Batch &b, int tx)
     if (tx < 2) return false;
     for (int s = 0; s < b.nsim; ++s) {
         const SimDev &S = b.sd[s];
-        if (S.bc[0] || S.mur2) continue;
+        if (S.bc[0]) continue;
         for (int c = 0; c < 4; ++c) {
             if (c == 3 && !S.sc) continue;
             const int ext = c == 0 ? S.n[0] - 1 : S.n[0];
@@ -463,7 +463,7 @@ static mithra_status build_tables(Batch &b)
                 };
                 for (int a = 0; a < 3; ++a) {
                     const int u = a == 0 ? 1 : 0, w = a == 2 ? 1 : 2;
-                    if (stage == 0 && !S.bc[a]) add(a, 2LL * ni[u] * ni[w]);
+                    if (stage == 0 && !S.bc[a] && !(a == 0 && b.fuse_x)) add(a, 2LL * ni[u] * ni[w]);
                     if (stage == 1 && !S.bc[u] && !S.bc[w]) add(3 + a, 4LL * ni[a]);
                 }
                 if (stage == 2 && !S.bc[0] && !S.bc[1] && !S.bc[2]) add(6, 8);
