@@ -58,6 +58,9 @@ def _load():
     lib.orc_set_particles.argtypes = [P, L, dp, dp, D, D]
     lib.orc_set_particles.restype = I
     lib.orc_set_background.argtypes = [P, dp]
+    lib.orc_set_seed.argtypes = [P, I, D, D, D, D, D, D, D, I, D]
+    lib.orc_seed_signal.argtypes = [P, D]
+    lib.orc_seed_signal.restype = D
     lib.orc_config_diag.argtypes = [P, I, I, I, I]
     for name in ("orc_field_update", "orc_vertex_fields", "orc_push", "orc_deposit",
                  "orc_rotate"):
@@ -132,6 +135,17 @@ class OracleSim:
     def set_background(self, bg):
         bg = np.ascontiguousarray(bg, dtype=np.float64).reshape(-1)
         self._lib.orc_set_background(self._h, _dptr(bg))
+
+    SIGNALS = {"neumann": 0, "gaussian": 1, "secant": 2, "flat-top": 3}
+
+    def set_seed(self, a0, polarization=(1.0, 0.0), frequency=0.0, t0=0.0, tau=1.0, cep=0.0,
+                 signal="gaussian", z_ref=0.0, on=True):
+        self._lib.orc_set_seed(self._h, int(on), float(a0), float(polarization[0]),
+                               float(polarization[1]), float(frequency), float(t0), float(tau),
+                               float(cep), int(self.SIGNALS[signal]), float(z_ref))
+
+    def seed_signal(self, t):
+        return float(self._lib.orc_seed_signal(self._h, float(t)))
 
     def config_diag(self, probe, kp):
         self._lib.orc_config_diag(self._h, int(probe[0]), int(probe[1]), int(probe[2]), int(kp))

@@ -47,6 +47,14 @@
  *         edge:   (d_sa + d_sb) d_t xi - 3/(2c) d_tt xi + c/2 d_ee xi = 0,
  *         corner: (d_sa + d_sb + d_sc) d_t xi - 2/c d_tt xi = 0;
  *       faces first, then edges, then corners;
+ *   R20 seed (section "Seed Field"): a plane wave of vector potential
+ *       travelling towards +z, A = A0 p s(t - (z - z_ref)/c) with p in the
+ *       x-y plane and s one of the printed signal shapes, is brought in by
+ *       the TF/SF corrections at the second (scattered-field) and third
+ *       (total-field) planes after the z_min boundary.  The corrections take
+ *       the standard signs, so that the total-field region carries +A; the
+ *       printed signs would inject -A.  The printed "sinusoidal pulse" is
+ *       the job file's "flat-top" signal;
  *   R17 a particle whose cell leaves [2, n_d - 3] on any axis is lost.
  */
 #include <math.h>
@@ -70,6 +78,9 @@ typedef struct orc_sim {
     double nu, A;
     int N, sc, bc[3]; /* bc: 0 = Mur absorbing boundary, 1 = periodic */
     int mur2;         /* the Mur boundaries are of second order */
+    /* seed plane wave (reading R20) */
+    int seed_on, seed_sig;
+    double seed_a0, seed_p[2], seed_f, seed_t0, seed_tau, seed_cep, seed_zref;
     double lambda_u, K, gamma_beam, z_e;
     /* derived constants */
     double dt, dtb, a1, a2, a4, a6, a8;
@@ -380,6 +391,7 @@ int orc_set_particles(orc_sim *s, long np, const double *x, const double *u, dou
 
 static void boundary_mur1(orc_sim *s, int comp);
 static void boundary_mur2(orc_sim *s, int comp);
+static void seed_tfsf(orc_sim *s, int c, const int lo[3], const int hi[3]);
 
 void orc_field_update(orc_sim *s)
 {
@@ -420,9 +432,75 @@ void orc_field_update(orc_sim *s)
                            s->a4 * bym + s->a6 * P[IX(s, i, j, k + 1)] + s->a6 * P[IX(s, i, j, k - 1)] +
                            s->a8 * zeta;
                 }
+        seed_tfsf(s, c, lo, hi);
         if (s->mur2) boundary_mur2(s, c);
         else boundary_mur1(s, c);
     }
+}
+
+/* ---- O2b: seed plane wave by the TF/SF technique (section "Seed Field",
+        reading R20) ------------------------------------------------------- */
+
+/* the printed signal shapes; x = t - t0 */
+double orc_seed_signal(const orc_sim *s, double t)
+{
+    double x = t - s->seed_t0, ln2 = log(2.0), tau = s->seed_tau;
+    double carrier = cos(2.0 * ORC_PI * s->seed_f * x + s->seed_cep);
+    double g = exp(-2.0 * ln2 * x * x / (tau * tau));
+    switch (s->seed_sig) {
+    case 0: /* modulated Neumann */
+        return -s->seed_a0 * 4.0 * ln2 * carrier * x / (tau * tau) * g;
+    case 1: /* modulated Gaussian */
+        return s->seed_a0 * carrier * g;
+    case 2: /* modulated hyperbolic secant */
+        return s->seed_a0 * carrier / cosh(x / tau);
+    default: /* sinusoidal pulse: Gaussian rise, then the bare carrier */
+        return s->seed_a0 * carrier * (x <= 0.0 ? g : 1.0);
+    }
+}
+
+void orc_set_seed(orc_sim *s, int on, double a0, double px, double py, double freq, double t0,
+                  double tau, double cep, int signal, double z_ref)
+{
+    s->seed_on = on;
+    s->seed_a0 = a0;
+    s->seed_p[0] = px;
+    s->seed_p[1] = py;
+    s->seed_f = freq;
+    s->seed_t0 = t0;
+    s->seed_tau = tau;
+    s->seed_cep = cep;
+    s->seed_sig = signal;
+    s->seed_zref = z_ref;
+}
+
+/* incident potential component c at grid plane k, time level n */
+static double seed_incident(const orc_sim *s, int c, int k, double t)
+{
+    double z = s->o[2] + k * s->d[2];
+    return s->seed_p[c] * orc_seed_signal(s, t - (z - s->seed_zref) / ORC_C);
+}
+
+/* after the interior update of component c (A_x or A_y): the scattered-field
+   plane k_s = 2 loses what its update took from the incident field on the
+   total-field plane k_t = 3, and k_t gains what its update missed on k_s */
+static void seed_tfsf(orc_sim *s, int c, const int lo[3], const int hi[3])
+{
+    if (!s->seed_on || c > 1 || s->seed_p[c] == 0.0) return;
+    double *R = s->pot[s->lnext][c];
+    double t = s->step * s->dt, A = s->A;
+    const int ks = 2, kt = 3;
+    for (int j = lo[1]; j <= hi[1]; j++)
+        for (int i = lo[0]; i <= hi[0]; i++) {
+            /* the incident field is uniform across a plane; the neighbours are
+               written out as in eq. (updateEquation) */
+            double ft_ip = seed_incident(s, c, kt, t), ft_im = ft_ip, ft_jp = ft_ip, ft_jm = ft_ip;
+            double fs_ip = seed_incident(s, c, ks, t), fs_im = fs_ip, fs_jp = fs_ip, fs_jm = fs_ip;
+            R[IX(s, i, j, ks)] -= A * (s->a2 * ft_ip + s->a2 * ft_im + s->a4 * ft_jp + s->a4 * ft_jm) +
+                                  s->a6 * seed_incident(s, c, kt, t);
+            R[IX(s, i, j, kt)] += A * (s->a2 * fs_ip + s->a2 * fs_im + s->a4 * fs_jp + s->a4 * fs_jm) +
+                                  s->a6 * seed_incident(s, c, ks, t);
+        }
 }
 
 /* ---- O3: first-order Mur boundary, staged as reading R16 ----------------- */

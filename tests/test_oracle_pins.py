@@ -414,6 +414,93 @@ def test_mur_oblique_reflection_matches_the_closed_forms():
 
 
 # ---------------------------------------------------------------------------
+# Seed plane wave by TF/SF (section "Seed Field", reading R20)
+# ---------------------------------------------------------------------------
+
+def _seeded(courant, signal="gaussian", nz=240, steps=160, pol=(0.6, 0.8), start=4.0):
+    """The pulse peaks start*tau after t = 0 at z = 0, far enough for the
+    domain to be empty at the start (the TF/SF premise)."""
+    dz = 1e-6
+    d, n = (2 * dz, 2 * dz, dz), (4, 4, nz)
+    sim = oracle.OracleSim(n, d, (0.0, 0.0, 0.0), courant=courant, bc=(1, 1, 0), K=0.0)
+    _empty(sim)
+    lam = 20 * dz
+    tau = 15 * dz / C
+    sim.set_seed(1e-3, pol, C / lam, start * tau, tau, 0.3, signal, z_ref=0.0)
+    sim.step(steps)
+    t = steps * sim.const["dt"]
+    z = np.arange(nz) * dz
+    inc = np.array([sim.seed_signal(t - zz / C) for zz in z])
+    return sim, inc
+
+
+@pytest.mark.parametrize("signal", ["gaussian", "secant"])
+def test_seed_tfsf_is_exact_at_courant_one(signal):
+    """At c dt = dz the transversely uniform NSFD update is the 1-D leapfrog
+    with the magic time step, for which any s(t - z/c) sampled on the grid is
+    an exact solution: the total-field region (third plane on) holds the
+    incident wave to round-off and the scattered-field region stays empty."""
+    # the secant's exponential tails need an earlier start
+    start, steps = (4.0, 160) if signal == "gaussian" else (25.0, 500)
+    sim, inc = _seeded(1.0, signal, steps=steps, start=start)
+    for c, p in ((0, 0.6), (1, 0.8)):
+        a = sim.pot(c, "cur")[:, 1, 1]
+        assert np.max(np.abs(a[3:-2] - p * inc[3:-2])) < 1e-10 * 1e-3, c
+        assert np.max(np.abs(a[:3])) < 1e-10 * 1e-3, c
+    assert np.max(np.abs(inc)) > 0.5e-3  # the pulse is inside the box
+    assert np.max(np.abs(sim.pot(2, "cur"))) == 0.0 and np.max(np.abs(sim.pot(3, "cur"))) == 0.0
+
+
+def test_seed_tfsf_below_courant_one_keeps_the_scattered_region_empty():
+    """Away from the magic time step the pulse disperses slightly inside the
+    total-field region (a few per cent after 160 steps at 20 cells per
+    wavelength) while nothing leaks into the scattered-field region."""
+    sim, inc = _seeded(0.9)
+    a = sim.pot(0, "cur")[:, 1, 1]
+    assert np.max(np.abs(a[3:-2] - 0.6 * inc[3:-2])) < 0.05 * 0.6e-3
+    assert np.max(np.abs(a[:3])) < 1e-9 * 1e-3
+
+
+def test_seed_signal_shapes():
+    """The printed signal shapes: the modulated Neumann pulse is the time
+    derivative of the Gaussian envelope under the same carrier; the Gaussian
+    intensity has full width tau at half maximum, the hyperbolic secant
+    2 ln(1 + sqrt 2) tau; the sinusoidal (flat-top) pulse rises as the
+    Gaussian and continues as the bare carrier."""
+    n = (8, 8, 16)
+    d, origin = _mesh(n)
+    sim = oracle.OracleSim(n, d, origin, courant=0.9, bc=(1, 1, 0), K=0.0)
+    tau, t0 = 2e-15, 10e-15
+    ts = np.linspace(t0 - 4 * tau, t0 + 4 * tau, 4001)
+    # envelopes: zero carrier frequency and phase
+    sim.set_seed(1.0, frequency=0.0, t0=t0, tau=tau, cep=0.0, signal="gaussian")
+    g = np.array([sim.seed_signal(t) for t in ts])
+    sim.set_seed(1.0, frequency=0.0, t0=t0, tau=tau, cep=0.0, signal="neumann")
+    nm = np.array([sim.seed_signal(t) for t in ts])
+    dg = np.gradient(g, ts)
+    assert np.max(np.abs(nm - dg)) < 1e-5 * np.max(np.abs(dg))
+
+    def fwhm(y):
+        # half-maximum crossings of the intensity, linearly interpolated
+        w = y * y - 0.5 * np.max(y * y)
+        i = np.nonzero(np.diff(np.sign(w)))[0]
+        cross = [ts[k] - w[k] * (ts[k + 1] - ts[k]) / (w[k + 1] - w[k]) for k in (i[0], i[-1])]
+        return cross[1] - cross[0]
+
+    assert abs(fwhm(g) - tau) < 1e-5 * tau
+    sim.set_seed(1.0, frequency=0.0, t0=t0, tau=tau, cep=0.0, signal="secant")
+    sc = np.array([sim.seed_signal(t) for t in ts])
+    assert abs(fwhm(sc) - 2 * np.log(1 + np.sqrt(2)) * tau) < 1e-5 * tau
+    f, cep = 3e14, 0.4
+    sim.set_seed(1.0, frequency=f, t0=t0, tau=tau, cep=cep, signal="flat-top")
+    ft = np.array([sim.seed_signal(t) for t in ts])
+    car = np.cos(2 * np.pi * f * (ts - t0) + cep)
+    before, after = ts <= t0, ts > t0
+    assert np.allclose(ft[before], car[before] * g[before], rtol=0, atol=1e-14)
+    assert np.allclose(ft[after], car[after], rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
 # Field evaluation and interpolation
 # ---------------------------------------------------------------------------
 
