@@ -105,6 +105,39 @@ typedef struct {
     int32_t bc[3];      /* mithra_bc per axis (both faces of the axis) */
 } mithra_mesh;
 
+/* Seed (section "Seed Field"): a plane wave of vector potential travelling
+   towards +z in the rest frame,
+     A(z, t) = amplitude (polarization[0], polarization[1], 0) s(t - (z - z_ref)/c),
+   brought into the mesh by the total-field/scattered-field technique: after
+   each update the scattered-field plane k = 2 loses, and the total-field
+   plane k = 3 gains, the incident field its update took from, or missed on,
+   the other plane.  Everything from plane 3 on carries the seed.  s is one
+   of the printed signal shapes (section "FIELD", field-initialization) with
+   x = t - t0:
+     NEUMANN   -4 ln2 cos(2 pi f x + cep) x / tau^2 exp(-2 ln2 x^2 / tau^2)
+     GAUSSIAN  cos(2 pi f x + cep) exp(-2 ln2 x^2 / tau^2)
+     SECANT    cos(2 pi f x + cep) / cosh(x / tau)
+     FLAT_TOP  the Gaussian for x <= 0, then the bare carrier (the printed
+               "sinusoidal pulse"). */
+typedef enum {
+    MITHRA_SIGNAL_NEUMANN = 0,
+    MITHRA_SIGNAL_GAUSSIAN = 1,
+    MITHRA_SIGNAL_SECANT = 2,
+    MITHRA_SIGNAL_FLAT_TOP = 3
+} mithra_signal;
+
+typedef struct {
+    double amplitude;       /* A0 [V s / m]; 0 switches the seed off */
+    double polarization[2]; /* x and y weights of the polarization (used as given) */
+    double frequency;       /* carrier frequency f [Hz], rest frame, >= 0 */
+    double t0;              /* signal centre [s] */
+    double tau;             /* signal width [s], > 0 */
+    double cep;             /* carrier-envelope phase [rad] */
+    double z_ref;           /* position where the wave reads s(t) [m] */
+    int32_t signal;         /* mithra_signal */
+    int32_t pad;
+} mithra_seed;
+
 /* UNDULATOR: static planar undulator, eq. (undulatorField), and the beam
    energy that fixes the frame. */
 typedef struct {
@@ -180,6 +213,12 @@ mithra_status mithra_set_particles(mithra_sim *sim, int64_t np, const double *po
 
 mithra_status mithra_config_diag(mithra_sim *sim, const mithra_diag_cfg *cfg);
 
+/* Set (or, with amplitude 0 or seed == NULL, clear) the seed plane wave of
+   the simulation; it acts from the next step.  EINVAL for non-finite
+   values, tau <= 0, f < 0, an unknown signal, a periodic z axis or fewer
+   than 8 planes along z. */
+mithra_status mithra_set_seed(mithra_sim *sim, const mithra_seed *seed);
+
 /* Enqueue nsteps steps on the simulation's stream (asynchronous).  ESTATE if
    no particles were loaded (np = 0 is a valid load). */
 mithra_status mithra_run(mithra_sim *sim, int64_t nsteps);
@@ -240,6 +279,7 @@ mithra_status mithra_batch_set_particles(mithra_batch *b, int32_t sim, int64_t n
                                          const double *pos, const double *u, double q_macro,
                                          double m_macro);
 mithra_status mithra_batch_config_diag(mithra_batch *b, int32_t sim, const mithra_diag_cfg *cfg);
+mithra_status mithra_batch_set_seed(mithra_batch *b, int32_t sim, const mithra_seed *seed);
 /* Autotuner of the batch (see mithra_tune): one tile shape for all
    simulations, chosen by timing the whole batched launch. */
 mithra_status mithra_batch_tune(mithra_batch *b, int32_t trial_steps);

@@ -52,6 +52,20 @@ __device__ __forceinline__ int axis_index(int v, int n, int periodic)
 __device__ __forceinline__ void sin_cos(float x, float *s, float *c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sin_cos(double x, double *s, double *c) { sincos(x, s, c); }
 
+// seed signal shapes (section "FIELD", field-initialization), x = t - t0
+__device__ double seed_signal(const SimDev &S, double t)
+{
+    const double x = t - S.seed_t0, ln2 = 0.69314718055994530942;
+    const double carrier = cos(2.0 * 3.14159265358979323846 * S.seed_f * x + S.seed_cep);
+    const double g = exp(-2.0 * ln2 * x * x / (S.seed_tau * S.seed_tau));
+    switch (S.seed_sig) {
+    case 0: return -S.seed_a0 * 4.0 * ln2 * carrier * x / (S.seed_tau * S.seed_tau) * g;
+    case 1: return S.seed_a0 * carrier * g;
+    case 2: return S.seed_a0 * carrier / cosh(x / S.seed_tau);
+    default: return S.seed_a0 * carrier * (x <= 0.0 ? g : 1.0);
+    }
+}
+
 __device__ __forceinline__ int comp_extent(const SimDev &S, int c, int a)
 {
     return (c == a && !S.bc[a]) ? S.n[a] - 1 : S.n[a];
@@ -263,6 +277,19 @@ __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ s
     // transverse weights along y and z
     const R mb0 = (R)(m2 ? S.murg[0][0] : S.murb0[0]), mb1 = (R)(m2 ? S.murg[0][1] : S.murb1[0]);
     const R mgy = (R)S.murg[0][2], mgz = (R)S.murg[0][3];
+    // seed plane wave (total-field/scattered-field): the scattered-field plane
+    // k = 2 loses what its update took from the incident field on plane 3,
+    // which gains what its update missed on plane 2; both corrections are
+    // uniform over the plane
+    const bool seeded = S.seed_on && comp < 2 && S.seed_p[comp < 2 ? comp : 0] != 0.0 && !S.bc[2];
+    R corr_s = 0, corr_t = 0;
+    if (seeded) {
+        const double t = (double)step * S.dt;
+        const double wgt = S.A * (2.0 * S.ax + 2.0 * S.ay) + S.az;  // weight of plane k +- 1
+        const double p = S.seed_p[comp];
+        corr_s = (R)(-wgt * p * seed_signal(S, t - (S.origin[2] + 3.0 * S.d[2] - S.seed_zref) / C_LIGHT_D));
+        corr_t = (R)(wgt * p * seed_signal(S, t - (S.origin[2] + 2.0 * S.d[2] - S.seed_zref) / C_LIGHT_D));
+    }
 
     const R a1 = (R)S.a1, ax = (R)S.ax, ay = (R)S.ay, az = (R)S.az, A = (R)S.A;
     const R oma = (R)(1.0 - 2.0 * S.A);
@@ -327,7 +354,8 @@ __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ s
         __syncthreads();
         const R Pp = sP[slot][ty + 1][tx + 1];
         const R Tp = trans(slot);
-        const R val = -q + a1 * Pc + A * (Tm + Tp) + oma * Tc + az * (Pp + Pm) + src * s;
+        R val = -q + a1 * Pc + A * (Tm + Tp) + oma * Tc + az * (Pp + Pm) + src * s;
+        if (seeded) val += k == 2 ? corr_s : (k == 3 ? corr_t : (R)0);
         if (act) __builtin_nontemporal_store(val, &Rn[(long long)k * sxy + col]);
         if (fuse_x) {
             // the low face reads lane + 1, the high face lane - 1

@@ -69,6 +69,9 @@ struct SimDev {
     double rho_unit, J_unit[3];
     // diagnostics (SI)
     double dV, mc2, dxdy_mu0, eps0_half, inv_2mu0;
+    // seed plane wave along +z (TF/SF planes k = 2 and 3)
+    int seed_on, seed_sig;
+    double seed_a0, seed_p[2], seed_f, seed_t0, seed_tau, seed_cep, seed_zref;
 };
 
 // Device buffers of a batch (one arena per quantity, simulations concatenated).

@@ -54,6 +54,7 @@ struct HostSim {
     mithra_mesh mesh;
     mithra_undulator und;
     mithra_diag_cfg diag;
+    mithra_seed seed{};  // amplitude 0: none
     double dt, dtb, A, gamma0, beta0, B0, ku;
     bool loaded = false;
     double q = 0.0, m = 0.0;
@@ -253,6 +254,20 @@ static void derive(HostSim &h)
     h.ku = 2.0 * PI / h.und.lambda_u;
 }
 
+static void fill_seed(const HostSim &h, SimDev &S)
+{
+    S.seed_on = h.seed.amplitude != 0.0 ? 1 : 0;
+    S.seed_sig = h.seed.signal;
+    S.seed_a0 = h.seed.amplitude;
+    S.seed_p[0] = h.seed.polarization[0];
+    S.seed_p[1] = h.seed.polarization[1];
+    S.seed_f = h.seed.frequency;
+    S.seed_t0 = h.seed.t0;
+    S.seed_tau = h.seed.tau > 0.0 ? h.seed.tau : 1.0;
+    S.seed_cep = h.seed.cep;
+    S.seed_zref = h.seed.z_ref;
+}
+
 // fill the per-simulation constants (offsets are set by the layout)
 static void fill_simdev(const HostSim &h, SimDev &S)
 {
@@ -315,6 +330,7 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     S.rho_unit = q / dV;
     for (int a = 0; a < 3; ++a) S.J_unit[a] = -q * m.d[a] / (dV * h.dt);
     S.dV = dV;
+    fill_seed(h, S);
     S.mc2 = mm * C_LIGHT * C_LIGHT;
     S.dxdy_mu0 = m.d[0] * m.d[1] / MU0;
     S.eps0_half = 0.5 * EPS0;
@@ -1185,6 +1201,33 @@ static mithra_status config_diag(Batch &b, int s, const mithra_diag_cfg *cfg)
     return build_tables(b);
 }
 
+static mithra_status set_seed(Batch &b, int s, const mithra_seed *seed)
+{
+    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
+    HostSim &h = b.hs[s];
+    mithra_seed z{};
+    if (seed && seed->amplitude != 0.0) {
+        const double v[] = {seed->amplitude, seed->polarization[0], seed->polarization[1],
+                            seed->frequency, seed->t0, seed->tau, seed->cep, seed->z_ref};
+        for (double x : v)
+            if (!std::isfinite(x)) return fail(MITHRA_EINVAL, "seed: non-finite value");
+        if (!(seed->tau > 0.0)) return fail(MITHRA_EINVAL, "seed: tau must be > 0");
+        if (seed->frequency < 0.0) return fail(MITHRA_EINVAL, "seed: frequency must be >= 0");
+        if (seed->signal < MITHRA_SIGNAL_NEUMANN || seed->signal > MITHRA_SIGNAL_FLAT_TOP)
+            return fail(MITHRA_EINVAL, "seed: unknown signal %d", seed->signal);
+        if (h.mesh.bc[2] == MITHRA_BC_PERIODIC)
+            return fail(MITHRA_EINVAL, "seed: the z axis must be absorbing (the wave enters at z_min)");
+        z = *seed;
+    }
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    h.seed = z;
+    fill_seed(h, b.sd[s]);
+    // the per-simulation block on the device is read at every launch
+    HIP_TRY(hipMemcpyAsync(b.d_sims + s, &b.sd[s], sizeof(SimDev), hipMemcpyHostToDevice, b.stream));
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    return MITHRA_OK;
+}
+
 static mithra_status get_info(Batch &b, int s, mithra_info *info)
 {
     if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
@@ -1510,6 +1553,12 @@ mithra_status mithra_config_diag(mithra_sim *sim, const mithra_diag_cfg *cfg)
     return config_diag(*sim->b, 0, cfg);
 }
 
+mithra_status mithra_set_seed(mithra_sim *sim, const mithra_seed *seed)
+{
+    if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
+    return set_seed(*sim->b, 0, seed);
+}
+
 mithra_status mithra_run(mithra_sim *sim, int64_t nsteps)
 {
     if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
@@ -1644,6 +1693,12 @@ mithra_status mithra_batch_config_diag(mithra_batch *bb, int32_t sim, const mith
 {
     if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
     return config_diag(*bb->b, sim, cfg);
+}
+
+mithra_status mithra_batch_set_seed(mithra_batch *bb, int32_t sim, const mithra_seed *seed)
+{
+    if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
+    return set_seed(*bb->b, sim, seed);
 }
 
 mithra_status mithra_batch_tune(mithra_batch *bb, int32_t trial_steps)

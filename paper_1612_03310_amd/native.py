@@ -35,8 +35,10 @@ ABI_FUNCTIONS = (
     "mithra_batch_config_diag", "mithra_batch_tune", "mithra_batch_run", "mithra_batch_sync",
     "mithra_batch_get_diag", "mithra_batch_get_field", "mithra_batch_get_particles",
     "mithra_batch_get_info", "mithra_batch_set_timing", "mithra_batch_get_timing",
-    "mithra_batch_destroy",
+    "mithra_batch_destroy", "mithra_set_seed", "mithra_batch_set_seed",
 )
+
+SIGNALS = {"neumann": 0, "gaussian": 1, "secant": 2, "flat-top": 3}
 
 
 class Mesh(ctypes.Structure):
@@ -49,6 +51,28 @@ class Mesh(ctypes.Structure):
 class Undulator(ctypes.Structure):
     _fields_ = [("lambda_u", ctypes.c_double), ("K", ctypes.c_double),
                 ("gamma_beam", ctypes.c_double), ("z_entrance", ctypes.c_double)]
+
+
+class Seed(ctypes.Structure):
+    _fields_ = [("amplitude", ctypes.c_double), ("polarization", ctypes.c_double * 2),
+                ("frequency", ctypes.c_double), ("t0", ctypes.c_double), ("tau", ctypes.c_double),
+                ("cep", ctypes.c_double), ("z_ref", ctypes.c_double), ("signal", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+def make_seed(amplitude, polarization=(1.0, 0.0), frequency=0.0, t0=0.0, tau=1.0, cep=0.0,
+              signal="gaussian", z_ref=0.0) -> Seed:
+    s = Seed()
+    s.amplitude = float(amplitude)
+    s.polarization[0] = float(polarization[0])
+    s.polarization[1] = float(polarization[1])
+    s.frequency = float(frequency)
+    s.t0 = float(t0)
+    s.tau = float(tau)
+    s.cep = float(cep)
+    s.z_ref = float(z_ref)
+    s.signal = SIGNALS[signal] if isinstance(signal, str) else int(signal)
+    return s
 
 
 class DiagCfg(ctypes.Structure):
@@ -112,6 +136,8 @@ def load_library(path: str = LIB_PATH):
         "mithra_set_allocator": [P, P, P],
         "mithra_set_particles": [P, I64, dp, dp, D, D],
         "mithra_config_diag": [P, ctypes.POINTER(DiagCfg)],
+        "mithra_set_seed": [P, ctypes.POINTER(Seed)],
+        "mithra_batch_set_seed": [P, I32, ctypes.POINTER(Seed)],
         "mithra_run": [P, I64],
         "mithra_sync": [P],
         "mithra_get_field": [P, I32, dp],
@@ -284,6 +310,11 @@ class Sim:
                                               float(q), float(m)))
         self._np = pos.shape[0]
 
+    def set_seed(self, amplitude, **kw):
+        """Seed plane wave (see mithra_set_seed); amplitude 0 clears it."""
+        seed = make_seed(amplitude, **kw)
+        _check(self._lib.mithra_set_seed(self._h, ctypes.byref(seed)))
+
     def config_diag(self, probe, kp, every=1, capacity=4096):
         c = DiagCfg()
         for a in range(3):
@@ -396,6 +427,10 @@ class Batch:
         _check(self._lib.mithra_batch_set_particles(self._h, int(s), pos.shape[0], _dptr(pos),
                                                     _dptr(u), float(q), float(m)))
         self._np[s] = pos.shape[0]
+
+    def set_seed(self, s, amplitude, **kw):
+        seed = make_seed(amplitude, **kw)
+        _check(self._lib.mithra_batch_set_seed(self._h, int(s), ctypes.byref(seed)))
 
     def config_diag(self, s, probe, kp, every=1, capacity=4096):
         c = DiagCfg()

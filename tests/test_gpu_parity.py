@@ -182,6 +182,60 @@ def test_potential_update_and_mur_match_oracle(bc, n):
             assert rel_l2(g[mask], o[mask]) < TOL64, name
 
 
+@pytest.mark.parametrize("courant,precision", [(1.0, "f64"), (0.9, "f64"), (0.9, "f32")])
+def test_seed_plane_wave_matches_oracle(courant, precision):
+    """A modulated-Gaussian seed enters at z_min through the TF/SF planes and
+    crosses the mesh (periodic across, Mur along z): all four potentials
+    against the oracle after 150 steps."""
+    n = (8, 8, 160)
+    dz = 1e-6
+    d = (2 * dz, 2 * dz, dz)
+    origin = (0.0, 0.0, 0.0)
+    bc = (1, 1, 0)
+    tau = 15 * dz / C
+    seed = dict(polarization=(0.6, 0.8), frequency=C / (20 * dz), t0=4 * tau, tau=tau, cep=0.3,
+                signal="gaussian", z_ref=0.0)
+    say("case seed", n, courant, precision)
+    orc = oracle.OracleSim(n, d, origin, courant=courant, bc=bc, K=0.0, gamma_beam=50.0)
+    orc.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+    orc.set_seed(1e-3, **seed)
+    sim = native.Sim(n, d, origin, courant=courant, bc=bc, K=0.0, gamma_beam=50.0,
+                     precision=precision)
+    sim.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+    sim.set_seed(1e-3, **seed)
+    orc.step(150)
+    sim.run(150)
+    sim.sync()
+    tol = TOL64 if precision == "f64" else 1e-4
+    for c, name in enumerate(POT):
+        g, o = sim.get_field(name), orc.pot(c, "cur")
+        if c < 2:
+            assert np.max(np.abs(o)) > 1e-4  # the seed is in the mesh
+            assert rel_l2(g, o) < tol, (name, rel_l2(g, o))
+        else:
+            assert np.max(np.abs(g)) == 0.0, name
+
+
+def test_seeded_full_loop_f64():
+    """A seed and a bunch together, Mur on every face: the whole state and
+    the diagnostics against the oracle."""
+    n = (40, 44, 72)
+    w = W.make_workload("seeded", n, 3000, 120.0, 1.3, 0.015, 1e-4, 91, 60)
+    tau = 10 * w.d[2] / C
+    seed = dict(polarization=(1.0, 0.0), frequency=C / (16 * w.d[2]), t0=3 * tau, tau=tau,
+                cep=0.0, signal="flat-top", z_ref=w.origin[2])
+    say("case seeded full loop", n)
+    orc = oracle.from_workload(w)
+    orc.set_seed(2e-4, **seed)
+    sim = native.sim_from_workload(w, precision="f64", every=1)
+    sim.set_seed(2e-4, **seed)
+    sim.run(60)
+    sim.sync()
+    orc.step(60)
+    compare_state(sim, orc, TOL64, "seeded")
+    compare_diag(sim.get_diag(), orc.diag(), TOL64, "seeded")
+
+
 def test_plane_wave_dispersion_on_gpu():
     """Property at any size: a plane wave with the frequency of eq.
     (NSFDDispersionCD) stays an exact discrete solution on the GPU too."""
@@ -454,6 +508,19 @@ def test_invalid_meshes_are_rejected():
     with pytest.raises(native.MithraError) as e:
         native.Sim(n, (4e-6, 4e-6, 1e-6), (0, 0, 0), bc=(3, 0, 0))
     assert e.value.status == native.EINVAL
+    sim = native.Sim(n, (4e-6, 4e-6, 1e-6), (0, 0, 0), bc=(0, 0, 1))
+    with pytest.raises(native.MithraError) as e:  # the seed enters through z_min
+        sim.set_seed(1e-3, tau=1e-15)
+    assert e.value.status == native.EINVAL and "z axis" in str(e.value)
+    sim.close()
+    sim = native.Sim(n, (4e-6, 4e-6, 1e-6), (0, 0, 0))
+    for bad in (dict(tau=0.0), dict(tau=1e-15, signal=7), dict(tau=1e-15, frequency=-1.0),
+                dict(tau=1e-15, t0=float("nan"))):
+        with pytest.raises(native.MithraError) as e:
+            sim.set_seed(1e-3, **bad)
+        assert e.value.status == native.EINVAL, bad
+    sim.set_seed(0.0)  # clearing is always valid
+    sim.close()
 
 
 def test_run_before_particles_is_a_state_error():
