@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -128,11 +130,13 @@ def timed_run(sim, steps, torch):
     return time.perf_counter() - t0
 
 
-def measure(w, precision, steps, warmup, torch, native, tune=True, every=100):
+def measure(w, precision, steps, warmup, torch, native, tune=True, every=100, seed=None):
     """Graph-replayed timed region, then an event-timed region of the same
     length for the per-kernel durations."""
     t_setup = time.perf_counter()
     sim = native.sim_from_workload(w, precision=precision, every=every)
+    if seed is not None:
+        sim.set_seed(**seed)
     if tune:
         sim.tune(3)
     sim.run(warmup)
@@ -206,6 +210,8 @@ def main():
     ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--no-mur2", action="store_true",
                     help="skip the second-order Mur leg (mid configuration, bc code 2)")
+    ap.add_argument("--no-seed", action="store_true",
+                    help="skip the seeded leg (mid configuration with a TF/SF plane-wave seed)")
     ap.add_argument("--workload", choices=("mid", "large"), default="mid",
                     help="headline workload: mid (128x128x512, 1M particles, f64, the "
                          "default) or large (256x256x2048, 16.8M particles, f32 split)")
@@ -279,6 +285,23 @@ def main():
             "boundary_frac_hbm": round(b2 / (per2["boundary"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "kernels_ms": {k: round(v, 5) for k, v in per2.items()}}
         log("  %.4f ms/step, boundary %.4f ms" % (dt2 * 1e3 / k2, per2["boundary"]))
+    if args.workload == "mid" and not args.no_seed:
+        # a modulated-Gaussian plane wave at the rest-frame resonant
+        # wavelength (32 cells), a0 = 0.1, entering through z_min
+        c_light, q_e, m_e = 299792458.0, 1.602176634e-19, 9.1093837015e-31
+        lam = 32 * w.d[2]
+        tau = 40 * w.d[2] / c_light
+        seed = dict(amplitude=0.1 * m_e * c_light / q_e, polarization=(1.0, 0.0),
+                    frequency=c_light / lam, t0=3 * tau, tau=tau, cep=0.0, signal="gaussian",
+                    z_ref=w.origin[2])
+        k3 = max(50, K // 4)
+        log("seeded mid configuration (TF/SF plane wave), %d steps" % k3)
+        dt3, _, per3, dg3, _ = measure(w, prec, k3, Wm, torch, native, seed=seed)
+        out_extra["seed_mid"] = {
+            "steps": k3, "ms_per_step": round(dt3 * 1e3 / k3, 5),
+            "cell_updates_per_s": w.ncell * k3 / dt3, "stencil_ms": round(per3["stencil"], 5),
+            "probe_Ex_max": float(np.max(np.abs(dg3["probe_E"][:, 0]))) if len(dg3) else None}
+        log("  %.4f ms/step, stencil %.4f ms" % (dt3 * 1e3 / k3, per3["stencil"]))
     wl = None if args.skip_large else W.config(3)
     kl = max(20, min(200, K // 10))
     if wl is not None:
