@@ -1527,12 +1527,28 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const int *__restrict__ cou
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_scatter(Arena ar, long long np)
 {
-    const long long p = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    // each XCD takes one contiguous range of particles, so the lines where
+    // the destination ranges of neighbouring blocks meet are completed in one L2
+    const long long p = (long long)xcd_remap(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
     const bool active = p < np;  // every lane stays: the run logic is per wavefront
     const long long step = *ar.d_step;
     const int s = (int)(step & 1), d = s ^ 1;
     const int lane = threadIdx.x & 63;
-    const int g = active ? ar.key[s][p] : -1;
+    // All loads are issued up front, unconditionally (lanes past the end read
+    // the last particle), so none waits for another: the payload before any
+    // store, since the compiler cannot know that the source and destination
+    // buffers are distinct, and the bucket start while the atomic is in flight.
+    const long long pp = active ? p : np - 1;
+    const int gk = ar.key[s][pp];
+    const int pid = ar.id[s][pp];
+    R po[3], pu[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        po[a] = ((const R *)ar.off[s][a])[pp];
+        pu[a] = ((const R *)ar.u[s][a])[pp];
+    }
+    const int start = ar.offs[d][gk];
+    const int g = active ? gk : -1;
     const int prev = __shfl_up(g, 1, 64);
     const bool head = active && (lane == 0 || prev != g);
     const unsigned long long heads = __ballot(head);
@@ -1552,13 +1568,13 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Arena ar, long long np)
     const int hl = upto ? 63 - __clzll((long long)upto) : 0;
     base = __shfl(base, hl, 64);
     if (!active) return;
-    const int dst = ar.offs[d][g] + base + __popcll(act & ((2ull << lane) - 1) & ~((1ull << hl) - 1)) - 1;
+    const int dst = start + base + __popcll(act & ((2ull << lane) - 1) & ~((1ull << hl) - 1)) - 1;
     ar.key[d][dst] = g;
-    ar.id[d][dst] = ar.id[s][p];
+    ar.id[d][dst] = pid;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        ((R *)ar.off[d][a])[dst] = ((const R *)ar.off[s][a])[p];
-        ((R *)ar.u[d][a])[dst] = ((const R *)ar.u[s][a])[p];
+        ((R *)ar.off[d][a])[dst] = po[a];
+        ((R *)ar.u[d][a])[dst] = pu[a];
     }
 }
 

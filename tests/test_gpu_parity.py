@@ -490,6 +490,22 @@ def test_particles_outside_the_safe_interior_are_counted_lost():
     compare_state(sim, orc, TOL64, "lost")
 
 
+def test_many_lost_particles_are_carried_along():
+    """Lost particles stay in their bucket from step to step, in more than one
+    block's worth (600), next to live ones; every particle keeps its data."""
+    w = W.config(0, n_particles=1000, steps=6)
+    rng = np.random.default_rng(11)
+    x = w.x.copy()
+    far = rng.choice(len(x), 600, replace=False)
+    x[far, 2] = w.origin[2] + (w.n[2] - 1.5) * w.d[2]  # cell n-2 in z: lost in step 1
+    w.x = x
+    sim, orc = run_pair(w, 6)
+    pos, u, alive = sim.get_particles()
+    assert orc.lost >= 600 and sim.get_diag()["lost"][-1] == orc.lost
+    assert not alive[far].any()
+    compare_state(sim, orc, TOL64, "many lost")
+
+
 def test_invalid_meshes_are_rejected():
     n = (16, 16, 16)
     d = (1e-6, 1e-6, 1e-6)  # cubic cells: unstable for the NSFD scheme at courant 0.9
