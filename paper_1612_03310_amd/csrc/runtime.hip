@@ -70,6 +70,9 @@ struct Batch {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // the re-binning (scan, scatter) runs on a second stream beside the deposit
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     mithra_precision prec = MITHRA_F64;
     size_t rs = 8;  // bytes per real
     int nsim = 0;
@@ -162,7 +165,11 @@ static void destroy_batch(Batch *b)
     if (!b) return;
     (void)hipSetDevice(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->side) (void)hipStreamSynchronize(b->side);
     drop_graph(*b);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->side) (void)hipStreamDestroy(b->side);
     for (size_t i = 0; i < b->ev_a.size(); ++i) {
         (void)hipEventDestroy(b->ev_a[i]);
         (void)hipEventDestroy(b->ev_b[i]);
@@ -590,6 +597,12 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
         }
         b->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess) {
+        destroy_batch(b);
+        return fail(MITHRA_EDEVICE, "creating the second stream or its events failed");
+    }
     b->hs.resize(nsim);
     b->sd.resize(nsim);
     long long cells = 0, keys = 0, ring = 0;
@@ -882,15 +895,30 @@ static void enqueue_step(Batch &b, bool timed)
     mark(K_PUSH, true);
     launch_push<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar);
     mark(K_PUSH, false);
-    mark(K_DEPOSIT, true);
-    launch_deposit<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar, 0);
-    mark(K_DEPOSIT, false);
-    mark(K_SCAN, true);
-    launch_scan(st, b.ar, b.total_keys, b.d_bsum, b.n_scan_blocks, b.ar.d_step);
-    mark(K_SCAN, false);
-    mark(K_SCATTER, true);
-    launch_scatter<R>(st, b.ar, b.total_particles);
-    mark(K_SCATTER, false);
+    if (timed) {
+        // one stream, so that each kind's events bracket that kind alone
+        mark(K_DEPOSIT, true);
+        launch_deposit<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar, 0);
+        mark(K_DEPOSIT, false);
+        mark(K_SCAN, true);
+        launch_scan(st, b.ar, b.total_keys, b.d_bsum, b.n_scan_blocks, b.ar.d_step);
+        mark(K_SCAN, false);
+        mark(K_SCATTER, true);
+        launch_scatter<R>(st, b.ar, b.total_particles);
+        mark(K_SCATTER, false);
+    } else {
+        // The deposit reads the particle buffer of this step, its bucket
+        // starts and start records; the scan writes the other bucket starts
+        // and the scatter the other particle buffer.  Nothing is shared, so
+        // the re-binning runs on the second stream while the deposit runs.
+        (void)hipEventRecord(b.ev_fork, st);
+        (void)hipStreamWaitEvent(b.side, b.ev_fork, 0);
+        launch_scan(b.side, b.ar, b.total_keys, b.d_bsum, b.n_scan_blocks, b.ar.d_step);
+        launch_scatter<R>(b.side, b.ar, b.total_particles);
+        (void)hipEventRecord(b.ev_join, b.side);
+        launch_deposit<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar, 0);
+        (void)hipStreamWaitEvent(st, b.ev_join, 0);
+    }
     mark(K_DIAG, true);
     launch_diag<R>(st, b.d_sims, b.nsim, b.d_plane, b.n_plane, b.d_mesh, b.n_mesh, b.d_kin,
                    b.n_kin, b.ar);
