@@ -70,7 +70,7 @@
 #define ORC_MU0 (1.0 / (ORC_EPS0 * ORC_C * ORC_C))
 #define ORC_PI 3.14159265358979323846
 
-#define ORC_NDIAG 16
+#define ORC_NDIAG 20
 
 typedef struct orc_sim {
     int n[3];
@@ -813,7 +813,29 @@ void orc_deposit(orc_sim *s)
 /* ---- O10: diagnostics, one row per step ------------------------------------
    row: step, t, total charge, continuity residual, radiated power through the
    plane k = kp, field energy, kinetic energy, probe E (3), probe B (3), lost,
-   non-finite flag, spare */
+   non-finite flag, spare, bunching factor at harmonics 1..3, spare.
+
+   Bunching factor (the quantity <exp(j k z)> of section "Bunching factor",
+   reading R21): b_h = |(1/N) sum_p exp(i h K z_p)| over the N live particles,
+   z_p the rest-frame longitudinal position and K = 2 gamma0 k_u, the wave
+   number of the ponderomotive phase in the frame of the undulator-averaged
+   bunch (k_u = 2 pi / lambda_u in the lab). */
+
+static void bunching(const orc_sim *s, double *b)
+{
+    const double K = 2.0 * s->gamma0 * (2.0 * ORC_PI / s->lambda_u);
+    double re[3] = {0.0, 0.0, 0.0}, im[3] = {0.0, 0.0, 0.0};
+    long n = 0;
+    for (long p = 0; p < s->np; p++) {
+        if (!s->alive[p]) continue;
+        n++;
+        for (int h = 1; h <= 3; h++) {
+            re[h - 1] += cos(h * K * s->x[3 * p + 2]);
+            im[h - 1] += sin(h * K * s->x[3 * p + 2]);
+        }
+    }
+    for (int h = 0; h < 3; h++) b[h] = n > 0 ? sqrt(re[h] * re[h] + im[h] * im[h]) / (double)n : 0.0;
+}
 
 void orc_diag_row(orc_sim *s, double *row)
 {
@@ -874,6 +896,8 @@ void orc_diag_row(orc_sim *s, double *row)
         if (!isfinite(row[a])) nf = 1;
     row[14] = nf;
     row[15] = 0.0;
+    bunching(s, &row[16]);
+    row[19] = 0.0;
 }
 
 /* ---- O11: rotate the time levels ------------------------------------------ */

@@ -921,6 +921,85 @@ def test_radiation_frequency_is_the_boosted_resonance():
     assert abs(lam_lab / lam_r - 1.0) < 0.01
 
 
+# ---------------------------------------------------------------------------
+# Bunching factor <exp(j k z)> (section "Bunching factor"), at harmonics 1..3
+# ---------------------------------------------------------------------------
+
+def _bunching_of(z, xy=None, gamma=100.0, K=1.0, lambda_u=0.015, extra=None):
+    """The bunching terms of the oracle's diagnostic row for particles at
+    rest-frame longitudinal positions z (and optional extra positions)."""
+    n = (8, 8, 256)
+    d, origin = _mesh(n, dz=5e-6)
+    sim = oracle.OracleSim(n, d, origin, K=K, gamma_beam=gamma, lambda_u=lambda_u)
+    x = np.zeros((len(z), 3))
+    if xy is not None:
+        x[:, :2] = xy
+    x[:, 2] = z
+    if extra is not None:
+        x = np.concatenate([x, extra])
+    sim.set_particles(x, np.zeros_like(x), -QE, ME)
+    row = sim.diag_row_now()
+    return row[16:19], sim
+
+
+def _k_bunch(gamma=100.0, K=1.0, lambda_u=0.015):
+    """2 gamma0 k_u: the ponderomotive wave number in the frame of the
+    undulator-averaged bunch."""
+    return 2.0 * gamma / math.sqrt(1.0 + K * K / 2.0) * 2.0 * math.pi / lambda_u
+
+
+def test_bunching_of_evenly_spaced_phases_is_zero():
+    """M particles per period over three whole periods: every harmonic below M
+    sums roots of unity to zero (a wave number off by a factor would leave a
+    half-turn over)."""
+    kb = _k_bunch()
+    lam = 2.0 * math.pi / kb
+    M, P = 12, 3
+    z = -1.5 * lam + lam * np.arange(M * P) / M
+    b, sim = _bunching_of(z)
+    assert sim.lost == 0
+    assert np.all(b < 1e-12), b
+
+
+def test_bunching_of_one_common_position_is_one():
+    rng = np.random.default_rng(3)
+    xy = rng.uniform(-5e-5, 5e-5, (50, 2))
+    b, _ = _bunching_of(np.full(50, 1.234e-4), xy=xy)
+    assert np.allclose(b, 1.0, rtol=0, atol=1e-13), b
+
+
+@pytest.mark.parametrize("ka", [0.2, 0.4, 0.9])
+def test_bunching_of_a_sinusoidal_modulation_is_a_bessel_function(ka):
+    """z = z0 + a sin(K z0) with z0 evenly spaced over whole periods:
+    <exp(i h K z)> = J_{-h}(h K a), so b_h = |J_h(h K a)| (the discrete mean
+    differs by terms of order J_{h+M}, negligible for M = 64 per period)."""
+    from scipy.special import jv
+    kb = _k_bunch()
+    lam = 2.0 * math.pi / kb
+    M, P = 64, 5
+    z0 = -2.5 * lam + lam * (np.arange(M * P) + 0.5) / M
+    z = z0 + (ka / kb) * np.sin(kb * z0)
+    b, _ = _bunching_of(z)
+    want = np.array([abs(jv(h, h * ka)) for h in (1, 2, 3)])
+    assert np.allclose(b, want, rtol=1e-10, atol=1e-13), (b, want)
+
+
+def test_bunching_counts_live_particles_only():
+    """Particles outside the safe interior are lost at loading and take no
+    part, neither in the sum nor in the count: live particles at one common
+    position keep b = 1 beside lost ones spread over a period."""
+    kb = _k_bunch()
+    lam = 2.0 * math.pi / kb
+    n = (8, 8, 256)
+    d, origin = _mesh(n, dz=5e-6)
+    outside = np.zeros((10, 3))
+    outside[:, 0] = origin[0]  # cell 0 in x
+    outside[:, 2] = lam * np.arange(10) / 7.0
+    b, sim = _bunching_of(np.full(36, 2e-5), extra=outside)
+    assert sim.lost == 10
+    assert np.allclose(b, 1.0, rtol=0, atol=1e-13), b
+
+
 def _golden_rows():
     rows = []
     with open(os.path.join(GOLDEN, "resonance_wavelengths.txt")) as f:
