@@ -169,6 +169,10 @@ typedef struct {
     int64_t lost;               /* particles lost so far */
     int32_t nonfinite;          /* a non-finite value was produced */
     int32_t has_mesh_terms;     /* 1 if the mesh terms were computed this step */
+    double bunching[3];         /* |<exp(i h K z)>| over live particles, h = 1, 2, 3, after
+                                   the push; z the rest-frame longitudinal position,
+                                   K = 2 gamma0 k_u the ponderomotive wave number in
+                                   this frame (section "Bunching factor")  (mesh term) */
 } mithra_diag_row;
 
 /* Derived constants and bookkeeping of a simulation. */

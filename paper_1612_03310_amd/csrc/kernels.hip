@@ -1057,6 +1057,8 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
                               (double)u[2] * u[2]) -
                          1.0;
                 ar.ke[S.part0 + pid] = ke;
+                ar.zr[S.part0 + pid] =
+                    ok ? S.origin[2] + ((double)c[2] + (double)f[2]) * S.d[2] : __builtin_nan("");
             }
         }
         count_runs(ar.counts, ngk, active);
@@ -1657,20 +1659,41 @@ __device__ __forceinline__ void diag_mesh(const SimDev *__restrict__ sims, int2 
     }
 }
 
+// Per block of particle ids: sum (gamma - 1), the live count and the cos and
+// sin sums of h K z for h = 1, 2, 3 (section "Bunching factor").  By id, so
+// the order is fixed whatever the particles' order in memory; lost particles
+// hold z = NaN.
 __device__ __forceinline__ void diag_kin(const SimDev *__restrict__ sims, int2 it, Arena &ar)
 {
     const SimDev &S = sims[it.x];
     const long long step = *ar.d_step;
     if (S.mesh_every <= 0 || ((step + 1) % S.mesh_every) != 0) return;
-    double s = 0.0;
+    double t[KIN_TERMS];
+#pragma unroll
+    for (int q = 0; q < KIN_TERMS; ++q) t[q] = 0.0;
     const long long base = (long long)it.y * BLOCK * KIN_PER_THREAD;
     for (int r = 0; r < KIN_PER_THREAD; ++r) {
         const long long i = base + (long long)r * BLOCK + threadIdx.x;
-        if (i < S.np) s += ar.ke[S.part0 + i];
+        if (i >= S.np) continue;
+        t[0] += ar.ke[S.part0 + i];
+        const double z = ar.zr[S.part0 + i];
+        if (z == z) {
+            t[1] += 1.0;
+#pragma unroll
+            for (int h = 1; h <= 3; ++h) {
+                double sn, cs;
+                sincos((double)h * S.kbunch * z, &sn, &cs);
+                t[2 * h] += cs;
+                t[2 * h + 1] += sn;
+            }
+        }
     }
     __shared__ double sh[BLOCK];
-    const double tot = block_sum(s, sh);
-    if (threadIdx.x == 0) ar.partial[S.part_kin0 + it.y] = tot;
+#pragma unroll
+    for (int q = 0; q < KIN_TERMS; ++q) {
+        const double tot = block_sum(t[q], sh);
+        if (threadIdx.x == 0) ar.partial[S.part_kin0 + (long long)KIN_TERMS * it.y + q] = tot;
+    }
 }
 
 template <typename R>
@@ -1695,7 +1718,9 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
     double pw = 0.0;
     for (int b = threadIdx.x; b < S.nb_plane; b += BLOCK) pw += ar.partial[S.part_plane0 + b];
     pw = block_sum(pw, sh);
-    double q = 0.0, wf = 0.0, rmax = 0.0, res = 0.0, kin = 0.0;
+    double q = 0.0, wf = 0.0, rmax = 0.0, res = 0.0, kt[KIN_TERMS];
+#pragma unroll
+    for (int t = 0; t < KIN_TERMS; ++t) kt[t] = 0.0;
     if (mesh) {
         for (int b = threadIdx.x; b < S.nb_mesh; b += BLOCK) {
             const double *o = ar.partial + S.part_mesh0 + 4 * (long long)b;
@@ -1704,13 +1729,19 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
             rmax = fmax(rmax, o[2]);
             res = fmax(res, o[3]);
         }
-        for (int b = threadIdx.x; b < S.nb_kin; b += BLOCK) kin += ar.partial[S.part_kin0 + b];
+        for (int b = threadIdx.x; b < S.nb_kin; b += BLOCK) {
+            const double *o = ar.partial + S.part_kin0 + (long long)KIN_TERMS * b;
+#pragma unroll
+            for (int t = 0; t < KIN_TERMS; ++t) kt[t] += o[t];
+        }
         q = block_sum(q, sh);
         wf = block_sum(wf, sh);
         rmax = block_max(rmax, sh);
         res = block_max(res, sh);
-        kin = block_sum(kin, sh);
+#pragma unroll
+        for (int t = 0; t < KIN_TERMS; ++t) kt[t] = block_sum(kt[t], sh);
     }
+    const double kin = kt[0], live = kt[1];
     if (threadIdx.x == 0) {
         double *row = ar.ring + (S.ring0 + step % S.ring_cap) * NDIAG;
         R E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
@@ -1738,6 +1769,11 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
         if (nf) atomicOr(&ar.flags[blockIdx.x], 2);
         row[14] = (double)nf;
         row[15] = mesh ? 1.0 : 0.0;
+        for (int h = 0; h < 3; ++h)
+            row[16 + h] = mesh && live > 0.0
+                              ? sqrt(kt[2 + 2 * h] * kt[2 + 2 * h] + kt[3 + 2 * h] * kt[3 + 2 * h]) / live
+                              : 0.0;
+        row[19] = 0.0;
         // every block has read the step counter before it counts itself done
         if (atomicAdd(ar.fin_ctr, 1) == (int)gridDim.x - 1) {
             *ar.fin_ctr = 0;

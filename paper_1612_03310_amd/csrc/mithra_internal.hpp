@@ -15,12 +15,14 @@ constexpr int TILE = 8;
 constexpr int TILE_CELLS = TILE * TILE * TILE;
 constexpr int TILE_VERT = TILE + 1;  // vertices per axis a tile's cells touch
 constexpr int NKINDS = 7;            // kernel kinds for timing
-constexpr int NDIAG = 16;            // doubles per diagnostic row
+constexpr int NDIAG = 20;            // doubles per diagnostic row
 constexpr int BLOCK = 256;
 constexpr int SCAN_PER_THREAD = 16;
 constexpr int SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
 constexpr int MESH_DIAG_PER_THREAD = 8;
 constexpr int KIN_PER_THREAD = 8;
+constexpr int KIN_TERMS = 8;         // per kinetic block: sum (gamma - 1), live count,
+                                     // cos and sin sums of h K z for h = 1, 2, 3
 constexpr int OKEY_LOST = 1 << 9;
 
 enum Kind { K_STENCIL = 0, K_BOUNDARY, K_PUSH, K_DEPOSIT, K_SCAN, K_SCATTER, K_DIAG };
@@ -69,6 +71,7 @@ struct SimDev {
     double rho_unit, J_unit[3];
     // diagnostics (SI)
     double dV, mc2, dxdy_mu0, eps0_half, inv_2mu0;
+    double kbunch;      // 2 gamma0 k_u: wave number of the bunching factor
     // seed plane wave along +z (TF/SF planes k = 2 and 3)
     int seed_on, seed_sig;
     double seed_a0, seed_p[2], seed_f, seed_t0, seed_tau, seed_cep, seed_zref;
@@ -90,6 +93,7 @@ struct Arena {
                         // OKEY_LOST for a particle lost in the step
     void *ooff[3];
     double *ke;         // (gamma - 1) by particle id, for the kinetic-energy sum
+    double *zr;         // rest-frame z by particle id (NaN once lost), for the bunching factor
     double *partial;    // diagnostic partial sums
     double *ring;       // diagnostic rows
     int *flags;         // per simulation: a non-finite value was produced

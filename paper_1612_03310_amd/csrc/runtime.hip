@@ -342,6 +342,7 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     S.dxdy_mu0 = m.d[0] * m.d[1] / MU0;
     S.eps0_half = 0.5 * EPS0;
     S.inv_2mu0 = 0.5 / MU0;
+    S.kbunch = 2.0 * h.gamma0 * h.ku;
     S.probe[0] = h.diag.probe[0];
     S.probe[1] = h.diag.probe[1];
     S.probe[2] = h.diag.probe[2];
@@ -516,7 +517,7 @@ static mithra_status build_tables(Batch &b)
         S.part_mesh0 = slot;
         slot += 4 * S.nb_mesh;
         S.part_kin0 = slot;
-        slot += S.nb_kin;
+        slot += KIN_TERMS * S.nb_kin;
         for (int i = 0; i < S.nb_plane; ++i) plane.push_back(make_int2(s, i));
         for (int i = 0; i < S.nb_mesh; ++i) mesh.push_back(make_int2(s, i));
         for (int i = 0; i < S.nb_kin; ++i) kin.push_back(make_int2(s, i));
@@ -818,6 +819,7 @@ static mithra_status commit_impl(Batch &b)
     ok &= (b.ar.okey = (int *)A(ni)) != nullptr;
     for (int a = 0; a < 3; ++a) ok &= (b.ar.ooff[a] = A(nr)) != nullptr;
     ok &= (b.ar.ke = (double *)A(sizeof(double) * std::max(N, 1LL))) != nullptr;
+    ok &= (b.ar.zr = (double *)A(sizeof(double) * std::max(N, 1LL))) != nullptr;
     if (!ok) return fail(MITHRA_ENOMEM, "device allocation for %lld particles failed", N);
 
     std::vector<int> key, id, offs;
@@ -837,6 +839,9 @@ static mithra_status commit_impl(Batch &b)
                            hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemsetAsync(b.ar.counts, 0, sizeof(int) * b.total_keys, st));
     HIP_TRY(hipMemsetAsync(b.ar.ke, 0, sizeof(double) * std::max(N, 1LL), st));
+    // all-ones bytes are a NaN: no position until a live particle's first
+    // diagnostic push, and none ever for a particle lost at loading
+    HIP_TRY(hipMemsetAsync(b.ar.zr, 0xff, sizeof(double) * std::max(N, 1LL), st));
     HIP_TRY(hipMemsetAsync(b.ar.flags, 0, sizeof(int) * b.nsim, st));
     // the step counter on the device must match the host mirror
     HIP_TRY(hipMemcpyAsync(b.ar.d_step, &b.step, sizeof(long long), hipMemcpyHostToDevice, st));
@@ -1180,6 +1185,7 @@ static mithra_status get_diag(Batch &b, int s, mithra_diag_row *rows, int64_t ca
         o.lost = (int64_t)v[13];
         o.nonfinite = (int32_t)v[14];
         o.has_mesh_terms = (int32_t)v[15];
+        for (int h = 0; h < 3; ++h) o.bunching[h] = v[16 + h];
     }
     h.read_step = first + n;
     *nrows = n;

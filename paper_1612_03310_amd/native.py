@@ -86,7 +86,8 @@ class DiagRow(ctypes.Structure):
                 ("power", ctypes.c_double), ("field_energy", ctypes.c_double),
                 ("kinetic_energy", ctypes.c_double), ("probe_E", ctypes.c_double * 3),
                 ("probe_B", ctypes.c_double * 3), ("lost", ctypes.c_int64),
-                ("nonfinite", ctypes.c_int32), ("has_mesh_terms", ctypes.c_int32)]
+                ("nonfinite", ctypes.c_int32), ("has_mesh_terms", ctypes.c_int32),
+                ("bunching", ctypes.c_double * 3)]
 
 
 class Info(ctypes.Structure):
@@ -102,7 +103,7 @@ DIAG_DTYPE = np.dtype([("step", np.int64), ("t", np.float64), ("total_charge", n
                        ("field_energy", np.float64), ("kinetic_energy", np.float64),
                        ("probe_E", np.float64, 3), ("probe_B", np.float64, 3),
                        ("lost", np.int64), ("nonfinite", np.int32),
-                       ("has_mesh_terms", np.int32)])
+                       ("has_mesh_terms", np.int32), ("bunching", np.float64, 3)])
 assert DIAG_DTYPE.itemsize == ctypes.sizeof(DiagRow)
 
 
@@ -258,6 +259,9 @@ def make_mesh(n, d, origin, courant=0.9, nsfd_A=-1.0, substeps=1, space_charge=1
 
 def make_undulator(lambda_u, K, gamma_beam, z_entrance) -> Undulator:
     return Undulator(float(lambda_u), float(K), float(gamma_beam), float(z_entrance))
+
+
+assert DIAG_DTYPE.itemsize == ctypes.sizeof(DiagRow)
 
 
 def _rows_to_array(rows, n):

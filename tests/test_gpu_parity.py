@@ -94,6 +94,7 @@ def compare_diag(gd, od, tol, what=""):
     errs = {k: rel_l2(gd[k], od[:, c]) for k, c in cols.items()}
     errs["probe_E"] = rel_l2(gd["probe_E"], od[:, 7:10])
     errs["probe_B"] = rel_l2(gd["probe_B"], od[:, 10:13])
+    errs["bunching"] = rel_l2(gd["bunching"], od[:, 16:19])
     bad = {k: v for k, v in errs.items() if not v <= tol}
     say(what, "diag", errs)
     assert not bad, (what, bad)
@@ -317,6 +318,36 @@ def test_mid_config_full_size_f64():
     sim, orc = run_pair(w, 3, every=1)
     compare_state(sim, orc, TOL64, "mid-full")
     compare_diag(sim.get_diag(), orc.diag(), TOL64, "mid-full")
+
+
+def _prebunched(w, ka=0.3):
+    """Particles shifted along z by a sin(K z) (K = 2 gamma0 k_u), which
+    gives a bunching factor near J_1(K a), far above the shot noise."""
+    g0 = w.gamma_beam / math.sqrt(1.0 + w.K ** 2 / 2.0)
+    kb = 2.0 * g0 * 2.0 * math.pi / w.lambda_u
+    x = w.x.copy()
+    x[:, 2] += (ka / kb) * np.sin(kb * x[:, 2])
+    w.x = x
+    return w
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_bunching_factor_matches_oracle(precision):
+    """Bunching factor at harmonics 1..3 along 40 steps of a pre-bunched tiny
+    bunch; FP64 with mesh terms every 4th step (the rows between hold 0)."""
+    w = _prebunched(W.config(0, steps=40))
+    every = 4 if precision == "f64" else 1
+    tol = TOL64 if precision == "f64" else 1e-4
+    sim, orc = run_pair(w, 40, precision=precision, every=every)
+    gd, od = sim.get_diag(), orc.diag()
+    has = gd["has_mesh_terms"] == 1
+    assert has.sum() == 40 // every
+    assert np.all(gd["bunching"][~has] == 0.0)
+    err = rel_l2(gd["bunching"][has], od[has][:, 16:19])
+    say("bunching", precision, "b1 first/last", gd["bunching"][has][0, 0],
+        gd["bunching"][has][-1, 0], "rel-L2", err)
+    assert gd["bunching"][has][0, 0] > 0.1
+    assert err <= tol, err
 
 
 # ---------------------------------------------------------------------------
