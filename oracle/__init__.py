@@ -20,11 +20,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mithra_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-NDIAG = 20
+NDIAG = 24
 DIAG_COLUMNS = ("step", "t", "total_charge", "continuity_residual", "power",
                 "field_energy", "kinetic_energy", "Ex", "Ey", "Ez", "Bx", "By",
                 "Bz", "lost", "nonfinite", "spare", "bunching1", "bunching2",
-                "bunching3", "spare2")
+                "bunching3", "spare2", "power_h1", "power_h2", "power_h3", "spare3")
 
 _lib = None
 

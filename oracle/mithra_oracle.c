@@ -70,7 +70,7 @@
 #define ORC_MU0 (1.0 / (ORC_EPS0 * ORC_C * ORC_C))
 #define ORC_PI 3.14159265358979323846
 
-#define ORC_NDIAG 20
+#define ORC_NDIAG 24
 
 typedef struct orc_sim {
     int n[3];
@@ -103,6 +103,10 @@ typedef struct orc_sim {
     int probe[3], kp;
     double *diag;
     long ndiag, cap;
+    /* running DFT of Ex, Ey, Bx, By on the power plane at h omega_1 (h = 1..3):
+       per plane point 3 x 4 complex sums (reading R22) */
+    double *spec;
+    long nspec;
 } orc_sim;
 
 /* ---- indexing ---------------------------------------------------------- */
@@ -229,6 +233,8 @@ orc_sim *orc_create(const int n[3], const double d[3], const double origin[3],
     s->kp = n[2] / 2;
     s->cap = 1024;
     s->diag = (double *)malloc(sizeof(double) * ORC_NDIAG * s->cap);
+    s->spec = (double *)calloc((size_t)n[0] * n[1] * 24, sizeof(double));
+    s->nspec = 0;
     return s;
 }
 
@@ -250,6 +256,7 @@ void orc_destroy(orc_sim *s)
     free(s->x_old);
     free(s->alive);
     free(s->diag);
+    free(s->spec);
     free(s);
 }
 
@@ -813,13 +820,67 @@ void orc_deposit(orc_sim *s)
 /* ---- O10: diagnostics, one row per step ------------------------------------
    row: step, t, total charge, continuity residual, radiated power through the
    plane k = kp, field energy, kinetic energy, probe E (3), probe B (3), lost,
-   non-finite flag, spare, bunching factor at harmonics 1..3, spare.
+   non-finite flag, spare, bunching factor at harmonics 1..3, spare, power at
+   the harmonics 1..3 through the plane k = kp, spare.
 
    Bunching factor (the quantity <exp(j k z)> of section "Bunching factor",
    reading R21): b_h = |(1/N) sum_p exp(i h K z_p)| over the N live particles,
    z_p the rest-frame longitudinal position and K = 2 gamma0 k_u, the wave
    number of the ponderomotive phase in the frame of the undulator-averaged
    bunch (k_u = 2 pi / lambda_u in the lab). */
+
+/* Power at the harmonics h omega_1 (h = 1, 2, 3) of the rest-frame resonant
+   frequency omega_1 = gamma0 beta0 c k_u through the power plane (reading
+   R22).  Each step adds the sample at t = (s + 1/2) dt to the running DFT
+   F(omega) = sum_n f(t_n) exp(-i omega t_n) dt of Ex, Ey, Bx, By at every
+   plane point; after T = (number of samples) dt the mean power carried at
+   omega is (2 / T^2) sum_plane Re(F_Ex conj(F_By) - F_Ey conj(F_Bx)) / mu0 dx dy,
+   which for a field that is a pure tone over whole periods equals the time
+   mean of the instantaneous Poynting flux. */
+
+static double omega1(const orc_sim *s)
+{
+    return s->gamma0 * s->beta0 * ORC_C * (2.0 * ORC_PI / s->lambda_u);
+}
+
+void orc_spectrum_sample(orc_sim *s)
+{
+    int lo[2], hi[2];
+    for (int a = 0; a < 2; a++) interior(s, a, &lo[a], &hi[a]);
+    const double t = (s->step + 0.5) * s->dt;
+    for (int h = 1; h <= 3; h++) {
+        const double w = h * omega1(s);
+        const double cs = cos(w * t), sn = sin(w * t);
+        for (int j = lo[1]; j <= hi[1]; j++)
+            for (int i = lo[0]; i <= hi[0]; i++) {
+                long p = IX(s, i, j, s->kp);
+                const double f[4] = {s->E[0][p], s->E[1][p], s->B[0][p], s->B[1][p]};
+                double *acc = &s->spec[((long)j * s->n[0] + i) * 24 + (h - 1) * 8];
+                for (int c = 0; c < 4; c++) {
+                    acc[2 * c] += f[c] * cs * s->dt;
+                    acc[2 * c + 1] -= f[c] * sn * s->dt;
+                }
+            }
+    }
+    s->nspec++;
+}
+
+static void harmonic_power(const orc_sim *s, double *P)
+{
+    int lo[2], hi[2];
+    for (int a = 0; a < 2; a++) interior(s, a, &lo[a], &hi[a]);
+    const double T = s->nspec * s->dt;
+    for (int h = 1; h <= 3; h++) {
+        double sum = 0.0;
+        for (int j = lo[1]; j <= hi[1]; j++)
+            for (int i = lo[0]; i <= hi[0]; i++) {
+                const double *a = &s->spec[((long)j * s->n[0] + i) * 24 + (h - 1) * 8];
+                /* a[0..1] Ex, a[2..3] Ey, a[4..5] Bx, a[6..7] By (re, im) */
+                sum += (a[0] * a[6] + a[1] * a[7]) - (a[2] * a[4] + a[3] * a[5]);
+            }
+        P[h - 1] = s->nspec > 0 ? 2.0 / (T * T) * sum / ORC_MU0 * s->d[0] * s->d[1] : 0.0;
+    }
+}
 
 static void bunching(const orc_sim *s, double *b)
 {
@@ -898,6 +959,8 @@ void orc_diag_row(orc_sim *s, double *row)
     row[15] = 0.0;
     bunching(s, &row[16]);
     row[19] = 0.0;
+    harmonic_power(s, &row[20]);
+    row[23] = 0.0;
 }
 
 /* ---- O11: rotate the time levels ------------------------------------------ */
@@ -919,6 +982,7 @@ void orc_step(orc_sim *s, long nsteps)
         orc_vertex_fields(s); /* E, B at n+1/2 */
         orc_push(s);          /* gather, undulator, Boris, loss */
         orc_deposit(s);       /* rho^{n+3/2}, J^{n+1} */
+        orc_spectrum_sample(s);
         if (s->ndiag == s->cap) {
             s->cap *= 2;
             s->diag = (double *)realloc(s->diag, sizeof(double) * ORC_NDIAG * s->cap);

@@ -1000,6 +1000,42 @@ def test_bunching_counts_live_particles_only():
     assert np.allclose(b, 1.0, rtol=0, atol=1e-13), b
 
 
+# ---------------------------------------------------------------------------
+# Power at the harmonics of the resonant frequency through the power plane
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("h", [1, 2, 3])
+def test_harmonic_power_of_a_pure_tone_is_its_mean_poynting_flux(h):
+    """At c dt = dz a transversely uniform wave in a periodic box moves one
+    cell per step, so the plane sees an exact discrete tone: m = 6 periods in
+    n_z = 64 steps.  With lambda_u chosen so that h omega_1 is that tone, the
+    spectral power at harmonic h after the 64 steps equals the time mean of the
+    instantaneous Poynting flux (Parseval for one tone over whole periods),
+    and the other two harmonics, whole numbers of periods apart, carry none."""
+    n = (8, 8, 64)
+    d, origin = _mesh(n)
+    m, gamma = 6, 50.0
+    g0 = gamma  # K = 0
+    b0 = math.sqrt(1.0 - 1.0 / (g0 * g0))
+    # omega_1 dt = 2 pi m / (h n_z), with dt = dz / c
+    lambda_u = h * g0 * b0 * n[2] * d[2] / m
+    sim = oracle.OracleSim(n, d, origin, courant=1.0, bc=(1, 1, 1), K=0.0, gamma_beam=gamma,
+                           lambda_u=lambda_u)
+    _empty(sim)
+    kk = np.arange(n[2])
+    f = lambda z: 3.0e-9 * np.cos(2.0 * math.pi * m * z / n[2] + 0.4)
+    sim.pot(0, "cur")[:] = f(kk)[:, None, None]
+    sim.pot(0, "prev")[:] = f(kk + 1)[:, None, None]
+    sim.step(n[2])
+    dg = sim.diag()
+    mean_power = dg[:, 4].mean()
+    assert mean_power > 0.0
+    P = dg[-1, 20:23]
+    assert abs(P[h - 1] / mean_power - 1.0) < 1e-12, (P, mean_power)
+    others = [P[k] for k in range(3) if k != h - 1]
+    assert max(abs(v) for v in others) < 1e-12 * mean_power, (P, mean_power)
+
+
 def _golden_rows():
     rows = []
     with open(os.path.join(GOLDEN, "resonance_wavelengths.txt")) as f:
