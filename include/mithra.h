@@ -173,6 +173,12 @@ typedef struct {
                                    the push; z the rest-frame longitudinal position,
                                    K = 2 gamma0 k_u the ponderomotive wave number in
                                    this frame (section "Bunching factor")  (mesh term) */
+    double power_harmonic[3];   /* mean power [W] carried through plane k at h omega_1,
+                                   h = 1, 2, 3, omega_1 = gamma0 beta0 c k_u the rest-frame
+                                   resonant frequency, since the state was committed:
+                                   (2/T^2) sum Re(F_Ex F_By* - F_Ey F_Bx*)/mu0 dx dy with
+                                   F(omega) = sum_n f(t_n) exp(-i omega t_n) dt the running
+                                   DFT of the plane's vertex fields and T = (s+1) dt */
 } mithra_diag_row;
 
 /* Derived constants and bookkeeping of a simulation. */
@@ -250,9 +256,11 @@ mithra_status mithra_get_diag(mithra_sim *sim, mithra_diag_row *rows, int64_t ca
 
 mithra_status mithra_get_info(mithra_sim *sim, mithra_info *info);
 
-/* Checkpoint: all potentials (3 levels), J, rho (2), particles, step and
-   lost count.  blob NULL: *bytes receives the size.  EINVAL if *bytes is too
-   small or the blob belongs to another mesh or precision. */
+/* Checkpoint: all potentials (3 levels), J, rho (2), particles, step, lost
+   count and the running DFT of the power plane.  blob NULL: *bytes receives
+   the size.  EINVAL if *bytes is too small or the blob belongs to another
+   mesh or precision.  Blobs of the earlier layout without the plane spectrum
+   are still accepted (the spectrum then starts from zero). */
 mithra_status mithra_get_state(mithra_sim *sim, void *blob, size_t *bytes);
 mithra_status mithra_set_state(mithra_sim *sim, const void *blob, size_t bytes);
 

@@ -1591,22 +1591,46 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Arena ar, long long np)
 template <typename R>
 __device__ __forceinline__ void diag_plane(const SimDev *__restrict__ sims, int2 it, Arena &ar)
 {
+    // Per block of plane points: the Poynting flux, and the running DFT of
+    // Ex, Ey, Bx, By at h omega_1 (h = 1, 2, 3) advanced by this step's sample
+    // at t = (s + 1/2) dt, with each point's Re(F_Ex F_By* - F_Ey F_Bx*).
     const SimDev &S = sims[it.x];
     const long long step = *ar.d_step;
     const FieldPtrs<R> f = field_ptrs<R>(S, ar, step % 3, (step + 1) % 3, (int)(step % 3));
     const int e = it.y * BLOCK + threadIdx.x;
-    double pw = 0.0;
+    double t[PLANE_TERMS] = {0.0, 0.0, 0.0, 0.0};
     if (e < S.n[0] * S.n[1]) {
         const int i = e % S.n[0], j = e / S.n[0];
         if (vertex_valid(S, i, j, S.kp)) {
             R E[3], B[3];
             vertex_EB<R>(S, f, i, j, S.kp, E, B);
-            pw = (double)E[0] * (double)B[1] - (double)E[1] * (double)B[0];
+            t[0] = (double)E[0] * (double)B[1] - (double)E[1] * (double)B[0];
+            const double fv[4] = {(double)E[0], (double)E[1], (double)B[0], (double)B[1]};
+            const double tm = ((double)step + 0.5) * S.dt;
+            double *acc = ar.spec + S.spec0 + (long long)e * SPEC_PER_POINT;
+#pragma unroll
+            for (int h = 1; h <= 3; ++h) {
+                double sn, cs;
+                sincos((double)h * S.omega1 * tm, &sn, &cs);
+                double a[8];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    a[2 * c] = acc[(h - 1) * 8 + 2 * c] + fv[c] * cs * S.dt;
+                    a[2 * c + 1] = acc[(h - 1) * 8 + 2 * c + 1] - fv[c] * sn * S.dt;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[(h - 1) * 8 + q] = a[q];
+                // (re, im) pairs: Ex a[0..1], Ey a[2..3], Bx a[4..5], By a[6..7]
+                t[h] = (a[0] * a[6] + a[1] * a[7]) - (a[2] * a[4] + a[3] * a[5]);
+            }
         }
     }
     __shared__ double sh[BLOCK];
-    const double tot = block_sum(pw, sh);
-    if (threadIdx.x == 0) ar.partial[S.part_plane0 + it.y] = tot;
+#pragma unroll
+    for (int q = 0; q < PLANE_TERMS; ++q) {
+        const double tot = block_sum(t[q], sh);
+        if (threadIdx.x == 0) ar.partial[S.part_plane0 + (long long)PLANE_TERMS * it.y + q] = tot;
+    }
 }
 
 template <typename R>
@@ -1715,9 +1739,15 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
     const long long step = *ar.d_step;
     const bool mesh = S.mesh_every > 0 && ((step + 1) % S.mesh_every) == 0;
     __shared__ double sh[BLOCK];
-    double pw = 0.0;
-    for (int b = threadIdx.x; b < S.nb_plane; b += BLOCK) pw += ar.partial[S.part_plane0 + b];
-    pw = block_sum(pw, sh);
+    double pt[PLANE_TERMS] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < S.nb_plane; b += BLOCK) {
+        const double *o = ar.partial + S.part_plane0 + (long long)PLANE_TERMS * b;
+#pragma unroll
+        for (int q = 0; q < PLANE_TERMS; ++q) pt[q] += o[q];
+    }
+#pragma unroll
+    for (int q = 0; q < PLANE_TERMS; ++q) pt[q] = block_sum(pt[q], sh);
+    const double pw = pt[0];
     double q = 0.0, wf = 0.0, rmax = 0.0, res = 0.0, kt[KIN_TERMS];
 #pragma unroll
     for (int t = 0; t < KIN_TERMS; ++t) kt[t] = 0.0;
@@ -1774,6 +1804,9 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
                               ? sqrt(kt[2 + 2 * h] * kt[2 + 2 * h] + kt[3 + 2 * h] * kt[3 + 2 * h]) / live
                               : 0.0;
         row[19] = 0.0;
+        const double T = ((double)step + 1.0) * S.dt;
+        for (int h = 0; h < 3; ++h) row[20 + h] = 2.0 / (T * T) * pt[1 + h] * S.dxdy_mu0;
+        row[23] = 0.0;
         // every block has read the step counter before it counts itself done
         if (atomicAdd(ar.fin_ctr, 1) == (int)gridDim.x - 1) {
             *ar.fin_ctr = 0;

@@ -15,12 +15,14 @@ constexpr int TILE = 8;
 constexpr int TILE_CELLS = TILE * TILE * TILE;
 constexpr int TILE_VERT = TILE + 1;  // vertices per axis a tile's cells touch
 constexpr int NKINDS = 7;            // kernel kinds for timing
-constexpr int NDIAG = 20;            // doubles per diagnostic row
+constexpr int NDIAG = 24;            // doubles per diagnostic row
 constexpr int BLOCK = 256;
 constexpr int SCAN_PER_THREAD = 16;
 constexpr int SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
 constexpr int MESH_DIAG_PER_THREAD = 8;
 constexpr int KIN_PER_THREAD = 8;
+constexpr int SPEC_PER_POINT = 24;  // per power-plane point: 3 harmonics x (Ex, Ey, Bx, By) x (re, im)
+constexpr int PLANE_TERMS = 4;      // per plane block: power and the 3 harmonic terms
 constexpr int KIN_TERMS = 8;         // per kinetic block: sum (gamma - 1), live count,
                                      // cos and sin sums of h K z for h = 1, 2, 3
 constexpr int OKEY_LOST = 1 << 9;
@@ -72,6 +74,8 @@ struct SimDev {
     // diagnostics (SI)
     double dV, mc2, dxdy_mu0, eps0_half, inv_2mu0;
     double kbunch;      // 2 gamma0 k_u: wave number of the bunching factor
+    double omega1;      // gamma0 beta0 c k_u: rest-frame resonant frequency
+    long long spec0;    // first double of this simulation in the plane-spectrum arena
     // seed plane wave along +z (TF/SF planes k = 2 and 3)
     int seed_on, seed_sig;
     double seed_a0, seed_p[2], seed_f, seed_t0, seed_tau, seed_cep, seed_zref;
@@ -95,6 +99,7 @@ struct Arena {
     double *ke;         // (gamma - 1) by particle id, for the kinetic-energy sum
     double *zr;         // rest-frame z by particle id (NaN once lost), for the bunching factor
     double *partial;    // diagnostic partial sums
+    double *spec;       // running DFT of the power-plane fields at the harmonics (reset at commit)
     double *ring;       // diagnostic rows
     int *flags;         // per simulation: a non-finite value was produced
     int *tact;          // per tile: a particle in the 27-tile neighbourhood at the start of

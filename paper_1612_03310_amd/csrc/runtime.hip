@@ -79,6 +79,7 @@ struct Batch {
     std::vector<HostSim> hs;
     std::vector<SimDev> sd;
     long long total_cells = 0, total_keys = 0, total_particles = 0;
+    long long total_spec = 0;  // doubles of the plane-spectrum arena
     Arena ar{};
     SimDev *d_sims = nullptr;
     // work tables
@@ -343,6 +344,7 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     S.eps0_half = 0.5 * EPS0;
     S.inv_2mu0 = 0.5 / MU0;
     S.kbunch = 2.0 * h.gamma0 * h.ku;
+    S.omega1 = h.gamma0 * h.beta0 * C_LIGHT * h.ku;
     S.probe[0] = h.diag.probe[0];
     S.probe[1] = h.diag.probe[1];
     S.probe[2] = h.diag.probe[2];
@@ -513,7 +515,7 @@ static mithra_status build_tables(Batch &b)
         S.nb_kin = S.mesh_every > 0 ? (int)((S.np + BLOCK * KIN_PER_THREAD - 1) / (BLOCK * KIN_PER_THREAD))
                                     : 0;
         S.part_plane0 = slot;
-        slot += S.nb_plane;
+        slot += PLANE_TERMS * S.nb_plane;
         S.part_mesh0 = slot;
         slot += 4 * S.nb_mesh;
         S.part_kin0 = slot;
@@ -606,7 +608,7 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     }
     b->hs.resize(nsim);
     b->sd.resize(nsim);
-    long long cells = 0, keys = 0, ring = 0;
+    long long cells = 0, keys = 0, ring = 0, plate = 0;
     for (int s = 0; s < nsim; ++s) {
         HostSim &h = b->hs[s];
         h.mesh = meshes[s];
@@ -624,6 +626,8 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
         S.cell0 = cells;
         S.key0 = keys;
         S.ring0 = ring;
+        S.spec0 = plate;
+        plate += (long long)S.n[0] * S.n[1] * SPEC_PER_POINT;
         cells += (long long)S.n[0] * S.n[1] * S.n[2];
         keys += (long long)S.nkeys + 1;
         ring += S.ring_cap;
@@ -634,6 +638,7 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     }
     b->total_cells = cells;
     b->total_keys = keys;
+    b->total_spec = plate;
     // default stencil shape, clamped to the meshes
     int maxn[3] = {0, 0, 0};
     for (int s = 0; s < nsim; ++s)
@@ -654,6 +659,7 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     ok &= (b->ar.counts = (int *)A(sizeof(int) * keys)) != nullptr;
     for (int r = 0; r < 2; ++r) ok &= (b->ar.offs[r] = (int *)A(sizeof(int) * (keys + 1))) != nullptr;
     ok &= (b->ar.ring = (double *)A(sizeof(double) * NDIAG * ring)) != nullptr;
+    ok &= (b->ar.spec = (double *)A(sizeof(double) * plate)) != nullptr;
     ok &= (b->ar.flags = (int *)A(sizeof(int) * nsim)) != nullptr;
     ok &= (b->ar.d_step = (long long *)A(sizeof(long long))) != nullptr;
     ok &= (b->ar.fin_ctr = (int *)A(sizeof(int))) != nullptr;
@@ -672,6 +678,7 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     for (int r = 0; r < 2 && e == hipSuccess; ++r)
         e = hipMemsetAsync(b->ar.offs[r], 0, sizeof(int) * (keys + 1), b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.ring, 0, sizeof(double) * NDIAG * ring, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->ar.spec, 0, sizeof(double) * plate, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.flags, 0, sizeof(int) * nsim, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.d_step, 0, sizeof(long long), b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.fin_ctr, 0, sizeof(int), b->stream);
@@ -795,13 +802,15 @@ static mithra_status commit_impl(Batch &b)
         S.part0 = N;
         S.np = (int)b.hs[s].alive.size();
         N += S.np;
-        const long long keep0 = S.cell0, keep1 = S.key0, keep2 = S.ring0, keep3 = S.part0;
+        const long long keep0 = S.cell0, keep1 = S.key0, keep2 = S.ring0, keep3 = S.part0,
+                        keep4 = S.spec0;
         const int np = S.np;
         fill_simdev(b.hs[s], S);
         S.cell0 = keep0;
         S.key0 = keep1;
         S.ring0 = keep2;
         S.part0 = keep3;
+        S.spec0 = keep4;
         S.np = np;
     }
     b.total_particles = N;
@@ -839,6 +848,8 @@ static mithra_status commit_impl(Batch &b)
                            hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemsetAsync(b.ar.counts, 0, sizeof(int) * b.total_keys, st));
     HIP_TRY(hipMemsetAsync(b.ar.ke, 0, sizeof(double) * std::max(N, 1LL), st));
+    // the plane spectrum starts with the committed state
+    HIP_TRY(hipMemsetAsync(b.ar.spec, 0, sizeof(double) * b.total_spec, st));
     // all-ones bytes are a NaN: no position until a live particle's first
     // diagnostic push, and none ever for a particle lost at loading
     HIP_TRY(hipMemsetAsync(b.ar.zr, 0xff, sizeof(double) * std::max(N, 1LL), st));
@@ -1186,6 +1197,7 @@ static mithra_status get_diag(Batch &b, int s, mithra_diag_row *rows, int64_t ca
         o.nonfinite = (int32_t)v[14];
         o.has_mesh_terms = (int32_t)v[15];
         for (int h = 0; h < 3; ++h) o.bunching[h] = v[16 + h];
+        for (int h = 0; h < 3; ++h) o.power_harmonic[h] = v[20 + h];
     }
     h.read_step = first + n;
     *nrows = n;
@@ -1387,9 +1399,11 @@ static mithra_status get_state_impl(Batch &b, void *blob, size_t *bytes)
     const long long np = S.np;
     const size_t mesh_bytes = (size_t)ncell * sizeof(R);
     // potentials at levels s-1 and s, J (3), rho (2), particles in id order:
-    // alive (1 byte), cell (3 int), offset (3 R), u (3 R)
-    const size_t need = sizeof(StateHeader) + mesh_bytes * (8 + 3 + 2) +
-                        (size_t)np * (1 + 3 * sizeof(int) + 6 * sizeof(R));
+    // alive (1 byte), cell (3 int), offset (3 R), u (3 R); then (version 2)
+    // the running DFT of the power plane, SPEC_PER_POINT doubles per point
+    const size_t spec_bytes = sizeof(double) * (size_t)S.n[0] * S.n[1] * SPEC_PER_POINT;
+    const size_t part_bytes = (size_t)np * (1 + 3 * sizeof(int) + 6 * sizeof(R));
+    const size_t need = sizeof(StateHeader) + mesh_bytes * (8 + 3 + 2) + part_bytes + spec_bytes;
     if (!blob) {
         *bytes = need;
         return MITHRA_OK;
@@ -1401,7 +1415,7 @@ static mithra_status get_state_impl(Batch &b, void *blob, size_t *bytes)
     StateHeader hd;
     std::memset(&hd, 0, sizeof hd);
     std::memcpy(hd.magic, "MITHRA1", 8);
-    hd.version = 1;
+    hd.version = 2;
     hd.prec = b.prec;
     for (int a = 0; a < 3; ++a) hd.n[a] = S.n[a];
     hd.step = b.step;
@@ -1463,6 +1477,7 @@ static mithra_status get_state_impl(Batch &b, void *blob, size_t *bytes)
             mo[3 * p + a] = uu[a][i];
         }
     }
+    HIP_TRY(hipMemcpy(w + part_bytes, b.ar.spec + S.spec0, spec_bytes, hipMemcpyDeviceToHost));
     *bytes = need;
     return MITHRA_OK;
 }
@@ -1475,7 +1490,7 @@ static mithra_status set_state_impl(Batch &b, const void *blob, size_t bytes)
     if (bytes < sizeof(StateHeader)) return fail(MITHRA_EINVAL, "blob too small");
     StateHeader hd;
     std::memcpy(&hd, blob, sizeof hd);
-    if (std::memcmp(hd.magic, "MITHRA1", 8) != 0 || hd.version != 1)
+    if (std::memcmp(hd.magic, "MITHRA1", 8) != 0 || (hd.version != 1 && hd.version != 2))
         return fail(MITHRA_EINVAL, "not a state blob of this library");
     if (hd.prec != b.prec || hd.n[0] != S0.n[0] || hd.n[1] != S0.n[1] || hd.n[2] != S0.n[2])
         return fail(MITHRA_EINVAL, "state belongs to another mesh or precision");
@@ -1483,7 +1498,11 @@ static mithra_status set_state_impl(Batch &b, const void *blob, size_t bytes)
         return fail(MITHRA_ESTATE, "load particles once (any) before restoring a state: q and m come from that call");
     const long long np = hd.np;
     const size_t mesh_bytes = (size_t)ncell * sizeof(R);
-    const size_t need = sizeof(StateHeader) + mesh_bytes * 13 + (size_t)np * (1 + 3 * sizeof(int) + 6 * sizeof(R));
+    // version 1 has no plane spectrum: it starts again from zero
+    const size_t spec_bytes =
+        hd.version >= 2 ? sizeof(double) * (size_t)S0.n[0] * S0.n[1] * SPEC_PER_POINT : 0;
+    const size_t part_bytes = (size_t)np * (1 + 3 * sizeof(int) + 6 * sizeof(R));
+    const size_t need = sizeof(StateHeader) + mesh_bytes * 13 + part_bytes + spec_bytes;
     if (bytes < need) return fail(MITHRA_EINVAL, "blob truncated");
     HIP_TRY(hipStreamSynchronize(b.stream));
     // particles first (commit re-lays the arenas at the restored step)
@@ -1521,6 +1540,10 @@ static mithra_status set_state_impl(Batch &b, const void *blob, size_t bytes)
     HIP_TRY(hipMemcpy((char *)b.ar.rho[s & 1] + off, w, mesh_bytes, hipMemcpyHostToDevice));
     w += mesh_bytes;
     HIP_TRY(hipMemcpy((char *)b.ar.rho[(s + 1) & 1] + off, w, mesh_bytes, hipMemcpyHostToDevice));
+    if (spec_bytes)
+        HIP_TRY(hipMemcpy(b.ar.spec + S0.spec0,
+                          (const char *)blob + sizeof hd + mesh_bytes * 13 + part_bytes, spec_bytes,
+                          hipMemcpyHostToDevice));
     HIP_TRY(mark_sources_dirty(b));
     HIP_TRY(hipStreamSynchronize(b.stream));
     h.read_step = s;

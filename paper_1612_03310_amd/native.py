@@ -87,7 +87,7 @@ class DiagRow(ctypes.Structure):
                 ("kinetic_energy", ctypes.c_double), ("probe_E", ctypes.c_double * 3),
                 ("probe_B", ctypes.c_double * 3), ("lost", ctypes.c_int64),
                 ("nonfinite", ctypes.c_int32), ("has_mesh_terms", ctypes.c_int32),
-                ("bunching", ctypes.c_double * 3)]
+                ("bunching", ctypes.c_double * 3), ("power_harmonic", ctypes.c_double * 3)]
 
 
 class Info(ctypes.Structure):
@@ -103,7 +103,8 @@ DIAG_DTYPE = np.dtype([("step", np.int64), ("t", np.float64), ("total_charge", n
                        ("field_energy", np.float64), ("kinetic_energy", np.float64),
                        ("probe_E", np.float64, 3), ("probe_B", np.float64, 3),
                        ("lost", np.int64), ("nonfinite", np.int32),
-                       ("has_mesh_terms", np.int32), ("bunching", np.float64, 3)])
+                       ("has_mesh_terms", np.int32), ("bunching", np.float64, 3),
+                       ("power_harmonic", np.float64, 3)])
 assert DIAG_DTYPE.itemsize == ctypes.sizeof(DiagRow)
 
 

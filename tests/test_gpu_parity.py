@@ -95,6 +95,7 @@ def compare_diag(gd, od, tol, what=""):
     errs["probe_E"] = rel_l2(gd["probe_E"], od[:, 7:10])
     errs["probe_B"] = rel_l2(gd["probe_B"], od[:, 10:13])
     errs["bunching"] = rel_l2(gd["bunching"], od[:, 16:19])
+    errs["power_harmonic"] = rel_l2(gd["power_harmonic"], od[:, 20:23])
     bad = {k: v for k, v in errs.items() if not v <= tol}
     say(what, "diag", errs)
     assert not bad, (what, bad)
@@ -350,6 +351,46 @@ def test_bunching_factor_matches_oracle(precision):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_harmonic_power_of_a_pure_tone(precision):
+    """At c dt = dz a transversely uniform wave in a periodic box is an exact
+    tone at the power plane (6 periods in 64 steps), and lambda_u puts the
+    second harmonic of the resonant frequency on it.  Every row matches the
+    oracle; after the 64 steps the second harmonic carries the mean Poynting
+    flux and the first and third carry none."""
+    n = (8, 8, 64)
+    dz = 1e-6
+    d = (4 * dz, 4 * dz, dz)
+    origin = tuple(-(n[a] - 1) / 2.0 * d[a] for a in range(3))
+    m, gamma, h = 6, 50.0, 2
+    lambda_u = h * gamma * math.sqrt(1.0 - 1.0 / gamma ** 2) * n[2] * d[2] / m
+    kw = dict(courant=1.0, bc=(1, 1, 1), K=0.0, gamma_beam=gamma, lambda_u=lambda_u)
+    orc = oracle.OracleSim(n, d, origin, **kw)
+    orc.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+    sim = native.Sim(n, d, origin, precision=precision, **kw)
+    sim.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+    kk = np.arange(n[2])
+    f = lambda z: 3.0e-9 * np.cos(2.0 * math.pi * m * z / n[2] + 0.4)
+    cur = np.broadcast_to(f(kk)[:, None, None], (n[2], n[1], n[0]))
+    prev = np.broadcast_to(f(kk + 1)[:, None, None], (n[2], n[1], n[0]))
+    orc.pot(0, "cur")[:] = cur
+    orc.pot(0, "prev")[:] = prev
+    sim.set_field("Ax", cur)
+    sim.set_field("Ax_prev", prev)
+    orc.step(n[2])
+    sim.run(n[2])
+    sim.sync()
+    gd, od = sim.get_diag(), orc.diag()
+    tol = TOL64 if precision == "f64" else 1e-5
+    err = rel_l2(gd["power_harmonic"], od[:, 20:23])
+    mean = gd["power"].mean()
+    P = gd["power_harmonic"][-1]
+    say("pure tone", precision, "P", P, "mean power", mean, "rel-L2 vs oracle", err)
+    assert err <= tol, err
+    assert abs(P[h - 1] / mean - 1.0) <= tol
+    assert abs(P[0]) <= tol * mean and abs(P[2]) <= tol * mean
+
+
 # ---------------------------------------------------------------------------
 # float path with split positions
 # ---------------------------------------------------------------------------
@@ -398,6 +439,28 @@ def test_run_twice_is_bitwise_identical(precision):
         sim.run(50)
         sim.sync()
         outs.append(([sim.get_field(f) for f in ("Ax", "Az", "phi", "Jx", "rho", "Ex")],
+                     sim.get_particles(), sim.get_diag()))
+        sim.close()
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b, equal_nan=True)
+    assert outs[0][2].tobytes() == outs[1][2].tobytes()
+
+
+def test_graph_with_two_streams_equals_kernel_by_kernel_bitwise():
+    """The captured step runs the scan and scatter on a second stream beside
+    the deposit; kernel-by-kernel execution on one stream (timing mode) must
+    give the same bits (64x64x128 subcase, 30 steps, more steps than one
+    captured graph)."""
+    w = W.mid_subcase(steps=30)
+    outs = []
+    for timed in (False, True):
+        sim = native.sim_from_workload(w, precision="f32")
+        sim.set_timing(timed)
+        sim.run(30)
+        sim.sync()
+        outs.append(([sim.get_field(f) for f in ("Ax", "Ay", "phi", "Jx", "Jz", "rho")],
                      sim.get_particles(), sim.get_diag()))
         sim.close()
     for a, b in zip(outs[0][0], outs[1][0]):
@@ -487,6 +550,8 @@ def test_checkpoint_resume_is_bitwise():
     got = [sim2.get_field(f) for f in ("Ax", "phi", "Jy", "rho", "Bz")] + list(sim2.get_particles())
     for a, b in zip(ref, got):
         assert np.array_equal(a, b, equal_nan=True)
+    # the rows after the restart too, the plane spectrum included
+    assert sim.get_diag()[10:].tobytes() == sim2.get_diag().tobytes()
 
 
 # ---------------------------------------------------------------------------
