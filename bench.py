@@ -121,6 +121,69 @@ def traffic_from_profile(kind, workload):
         return None
 
 
+def gain_length(power, dz_step, smooth=60, lo=0.02, hi=0.4):
+    """Power gain length from a per-step power series: the power is smoothed
+    over `smooth` steps (about one rest-frame radiation period), and ln P is
+    fitted by a line over the samples before the saturation peak whose power
+    lies between lo and hi of the peak.  Returns (gain length [m], undulator
+    distance of the peak [m], peak power, first and last fitted step)."""
+    Ps = np.convolve(power, np.ones(smooth) / smooth, mode="valid")
+    i_sat = int(np.argmax(Ps))
+    peak = float(Ps[i_sat])
+    sel = np.nonzero((Ps[:i_sat] > lo * peak) & (Ps[:i_sat] < hi * peak))[0]
+    if len(sel) < 2:
+        return None, (i_sat + smooth // 2) * dz_step, peak, None, None
+    slope = np.polyfit(sel, np.log(Ps[sel]), 1)[0]
+    return dz_step / slope, (i_sat + smooth // 2) * dz_step, peak, int(sel[0]), int(sel[-1])
+
+
+def fel_theory(gamma, K, lambda_u, sigma_x, current, sigma_delta):
+    """One-dimensional FEL parameter and power gain length of a round Gaussian
+    beam (peak current, rms radius), and the three-dimensional gain length
+    from M. Xie's published fit (zero emittance).  Not from the paper: a
+    textbook yardstick for the example's growth."""
+    from scipy.special import j0, j1
+    ia = 17045.0  # Alfven current [A]
+    xi = K * K / (4 + 2 * K * K)
+    jj = j0(xi) - j1(xi)
+    ku = 2 * np.pi / lambda_u
+    rho = ((current / ia) * (K * jj) ** 2 / (16 * gamma ** 3 * sigma_x ** 2 * ku ** 2)) ** (1 / 3)
+    l1 = lambda_u / (4 * np.pi * np.sqrt(3) * rho)
+    kr = 2 * np.pi / (lambda_u * (1 + K * K / 2) / (2 * gamma ** 2))
+    ed, eg = l1 / (2 * kr * sigma_x ** 2), 4 * np.pi * (l1 / lambda_u) * sigma_delta
+    # the terms of the fit without emittance: diffraction, energy spread, both
+    lam = 0.45 * ed ** 0.57 + 3 * eg ** 2 + 51 * ed ** 0.95 * eg ** 3
+    return float(rho), float(l1), float(l1 * (1 + lam))
+
+
+def example1_run(steps, torch, native, W):
+    """The paper's infrared FEL example (job-file reading), run to saturation;
+    returns timing, the fitted gain length and the yardsticks."""
+    w = W.example1(steps=steps)
+    sim = native.sim_from_workload(w, precision="f64", every=100, capacity=steps + 8)
+    sim.run(8)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps - 8)
+    sim.sync()
+    dt = time.perf_counter() - t0
+    dg = sim.get_diag()
+    info = sim.info()
+    sim.close()
+    dz_step = info["gamma0"] * info["beta0"] * 299792458.0 * info["dt"]
+    lg, z_sat, p_sat, a, b = gain_length(dg["power"], dz_step)
+    rho, l1, l3 = fel_theory(w.gamma_beam, w.K, w.lambda_u, 260e-6, 88.5, 1e-4)
+    return {"workload": w.name, "particles": w.np, "steps": steps,
+            "ms_per_step": round(dt * 1e3 / (steps - 8), 5),
+            "gain_length_m": None if lg is None else round(lg, 4),
+            "fit_steps": [a, b], "saturation_at_m": round(z_sat, 3),
+            "peak_power_rest_frame_W": round(p_sat, 2), "lost": int(dg["lost"][-1]),
+            "bunching_max": round(float(dg["bunching"][:, 0].max()), 4),
+            "rho_1d": round(rho, 5), "gain_length_1d_m": round(l1, 4),
+            "gain_length_3d_xie_m": round(l3, 4), "gain_length_paper_m": 0.22}
+
+
 def timed_run(sim, steps, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -212,6 +275,9 @@ def main():
                     help="skip the second-order Mur leg (mid configuration, bc code 2)")
     ap.add_argument("--no-seed", action="store_true",
                     help="skip the seeded leg (mid configuration with a TF/SF plane-wave seed)")
+    ap.add_argument("--no-example1", action="store_true",
+                    help="skip the paper's infrared FEL example (64x64x2800, 131072 "
+                         "particles, run to saturation, gain length fitted)")
     ap.add_argument("--workload", choices=("mid", "large"), default="mid",
                     help="headline workload: mid (128x128x512, 1M particles, f64, the "
                          "default) or large (256x256x2048, 16.8M particles, f32 split)")
@@ -302,6 +368,14 @@ def main():
             "cell_updates_per_s": w.ncell * k3 / dt3, "stencil_ms": round(per3["stencil"], 5),
             "probe_Ex_max": float(np.max(np.abs(dg3["probe_E"][:, 0]))) if len(dg3) else None}
         log("  %.4f ms/step, stencil %.4f ms" % (dt3 * 1e3 / k3, per3["stencil"]))
+    if args.workload == "mid" and not args.no_example1:
+        log("infrared FEL example: 64x64x2800, 131072 particles, 6000 steps")
+        ex = example1_run(6000, torch, native, W)
+        out_extra["example1"] = ex
+        log("  %.4f ms/step, gain length %s m (1D %.3f, 3D fit %.3f, paper 0.22), "
+            "saturation at %.2f m" % (ex["ms_per_step"], ex["gain_length_m"],
+                                       ex["gain_length_1d_m"], ex["gain_length_3d_xie_m"],
+                                       ex["saturation_at_m"]))
     wl = None if args.skip_large else W.config(3)
     kl = max(20, min(200, K // 10))
     if wl is not None:

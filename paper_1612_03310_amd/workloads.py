@@ -123,6 +123,121 @@ def make_workload(name: str, n, n_particles: int, gamma: float, K: float, lambda
                     probe=probe, kp=kp, steps=steps)
 
 
+def halton(index: np.ndarray, base: int) -> np.ndarray:
+    """Radical inverse of the integers ``index`` in ``base`` (Halton sequence)."""
+    index = np.asarray(index, dtype=np.int64).copy()
+    out = np.zeros(index.shape)
+    f = 1.0 / base
+    while np.any(index > 0):
+        out += f * (index % base)
+        index //= base
+        f /= base
+    return out
+
+
+def _tapered_flat_top(u: np.ndarray, length: float, sigma: float) -> np.ndarray:
+    """Inverse cumulative distribution of a flat top of the given length with
+    half-Gaussian edges of width sigma at the same peak density (the two
+    halves of a small Gaussian bunch moved to tail and head), for u in (0, 1)."""
+    from scipy.special import ndtri
+    m_t = math.sqrt(math.pi / 2.0) * sigma  # mass of one edge at unit density
+    total = length + 2.0 * m_t
+    w = np.asarray(u) * total
+    z = np.empty_like(w)
+    lo = w < m_t
+    hi = w >= m_t + length
+    mid = ~lo & ~hi
+    z[lo] = -length / 2.0 + sigma * ndtri(w[lo] / m_t / 2.0)
+    z[mid] = -length / 2.0 + (w[mid] - m_t)
+    z[hi] = length / 2.0 + sigma * ndtri(0.5 + (w[hi] - m_t - length) / m_t / 2.0)
+    return z
+
+
+def example1(*, n=(64, 64, 2800), n_particles: int = 131072, steps: int = 17900,
+             seed: int = BASE_SEED + 10, bunching: float = 0.01,
+             substeps: int = 2, transverse: str = "gaussian") -> Workload:
+    """The paper's infrared FEL example (section "Example 1: Infrared FEL"),
+    lab parameters from its table and job file, taken into the rest frame.
+
+    Lab frame: gamma = 100.41, sigma_delta = 1e-4, charge 29.5 pC; undulator
+    lambda_u = 3 cm, K = 1.417; mesh 3200 x 3200 x 280 um at 50 x 50 x 0.1 um
+    (64 x 64 x 2800 cells); transverse Gaussian of sigma 260 um cut at
+    1040 um; a flat top of 100.5 um with Gaussian edges of one radiation
+    wavelength (3 um); initial bunching factor 0.01; second-order Mur, no
+    space charge.  Rest frame: dz = gamma0 * 0.1 um, c dt = dz, two particle
+    sub-steps per field step (the job's bunch time step 1.6 ps in the lab is
+    below the field step).  The matched momenta belong to the leapfrog's
+    time level of u, half a sub-step before the positions at dt/2.
+
+    Loading (quiet start, as the paper's Halton filling): z from the Halton
+    sequence of base 2 through the inverse distribution of the tapered flat
+    top, the transverse Gaussian by Box-Muller from bases 3 and 5; then
+    z -> gamma0 z, the bunching modulation z -> z + (2 b / K_b) sin(K_b z)
+    with K_b = 2 gamma0 k_u (which gives the bunching factor J_1(2 b) = b to
+    first order), and momenta matched to the undulator as in make_workload.
+    The bunch starts inside the undulator (entrance one cell behind the mesh).
+    The power plane sits 110 um (lab) ahead of the bunch centre.
+    ``transverse="uniform"`` loads the table's reading instead: a uniform
+    260 x 260 um square (the printed electron density 2.72e13 cm^-3).
+    """
+    n = tuple(int(v) for v in n)
+    gamma, K, lambda_u, sigma_delta = 100.41, 1.417, 0.03, 1e-4
+    gamma0 = gamma / math.sqrt(1.0 + K * K / 2.0)
+    beta0 = math.sqrt(1.0 - 1.0 / (gamma0 * gamma0))
+    ku = 2.0 * math.pi / lambda_u
+    lam_r = lambda_u / (2.0 * gamma0 * gamma0)  # lab radiation wavelength
+    d = (50e-6, 50e-6, 0.1e-6 * gamma0)
+    origin = tuple(-(n[a] - 1) / 2.0 * d[a] for a in range(3))
+    z_e = origin[2] - d[2]
+    # quiet start: Halton points, indices from 1; keep the first n_particles
+    # whose transverse radius is inside the 4-sigma cut
+    sig_t, cut = 260e-6, 1040e-6
+    idx = np.arange(1, int(n_particles * 1.01) + 64)
+    r = sig_t * np.sqrt(-2.0 * np.log(halton(idx, 3)))
+    keep = r <= cut
+    idx = idx[keep][:n_particles]
+    r = r[keep][:n_particles]
+    th = 2.0 * math.pi * halton(idx, 5)
+    zl = _tapered_flat_top(halton(idx, 2), 100.5e-6, lam_r)
+    x = np.empty((n_particles, 3))
+    if transverse == "uniform":
+        x[:, 0] = (halton(idx, 3) - 0.5) * sig_t
+        x[:, 1] = (halton(idx, 5) - 0.5) * sig_t
+    else:
+        x[:, 0] = r * np.cos(th)
+        x[:, 1] = r * np.sin(th)
+    kb = 2.0 * gamma0 * ku
+    zr = gamma0 * zl
+    x[:, 2] = zr + (2.0 * bunching / kb) * np.sin(kb * zr)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gp = gamma * (1.0 + sigma_delta * rng.standard_normal(n_particles))
+    # matched start in the leapfrog's time levels: the input positions belong
+    # to t = dt/2 and the momenta to half a particle sub-step before, so the
+    # lab phase of u is taken at that time and at the particle's position then
+    dt = 1.0 * d[2] / C_LIGHT
+    t_u = 0.5 * dt - 0.5 * dt / substeps
+    zu = x[:, 2].copy()
+    for _ in range(8):
+        zlab = gamma0 * (zu - z_e + beta0 * C_LIGHT * t_u)
+        uxp = -K * np.cos(ku * zlab)
+        uzp = np.sqrt(gp * gp - 1.0 - uxp * uxp)
+        uz = gamma0 * (uzp - beta0 * gp)
+        gr = np.sqrt(1.0 + uxp * uxp + uz * uz)
+        zu = x[:, 2] - (0.5 * dt - t_u) * C_LIGHT * uz / gr
+    zx = gamma0 * (x[:, 2] - z_e + beta0 * C_LIGHT * 0.5 * dt)
+    x[:, 0] -= K / (gamma0 * ku * math.sqrt(1.0 + K * K / 2.0)) * np.sin(ku * zx)
+    u = np.zeros((n_particles, 3))
+    u[:, 0] = uxp
+    u[:, 2] = uz
+    q = -BUNCH_CHARGE / n_particles
+    m = M_E * (BUNCH_CHARGE / Q_E) / n_particles
+    kp = min(n[2] // 2 + int(round(gamma0 * 110e-6 / d[2])), n[2] - 3)
+    return Workload(name="example1-%dx%dx%d" % n, n=n, d=d, origin=origin, courant=1.0,
+                    nsfd_A=-1.0, substeps=substeps, space_charge=0, bc=(2, 2, 2),
+                    lambda_u=lambda_u, K=K, gamma_beam=gamma, z_e=z_e, x=x, u=u, q=q, m=m,
+                    probe=(n[0] // 2, n[1] // 2, kp), kp=kp, steps=steps)
+
+
 # The published configurations, in order (index 0..4), plus the parity subcase.
 def config(index: int, *, n_particles: Optional[int] = None, steps: Optional[int] = None,
            seed: Optional[int] = None) -> Workload:
