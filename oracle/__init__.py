@@ -60,6 +60,7 @@ def _load():
     lib.orc_set_particles.restype = I
     lib.orc_set_background.argtypes = [P, dp]
     lib.orc_set_seed.argtypes = [P, I, D, D, D, D, D, D, D, I, D]
+    lib.orc_set_optical.argtypes = [P, I, D, D, D, D, D, D, D, I, D]
     lib.orc_seed_signal.argtypes = [P, D]
     lib.orc_seed_signal.restype = D
     lib.orc_config_diag.argtypes = [P, I, I, I, I]
@@ -147,6 +148,14 @@ class OracleSim:
 
     def seed_signal(self, t):
         return float(self._lib.orc_seed_signal(self._h, float(t)))
+
+    def set_optical_undulator(self, amplitude, polarization=(1.0, 0.0), frequency=0.0, t0=0.0,
+                              tau=1.0, cep=0.0, signal="gaussian", z_ref=0.0, on=True):
+        """Plane wave towards -z in place of the static undulator (rest frame)."""
+        self._lib.orc_set_optical(self._h, int(on), float(amplitude), float(polarization[0]),
+                                  float(polarization[1]), float(frequency), float(t0),
+                                  float(tau), float(cep), int(self.SIGNALS[signal]),
+                                  float(z_ref))
 
     def config_diag(self, probe, kp):
         self._lib.orc_config_diag(self._h, int(probe[0]), int(probe[1]), int(probe[2]), int(kp))

@@ -81,6 +81,10 @@ typedef struct orc_sim {
     /* seed plane wave (reading R20) */
     int seed_on, seed_sig;
     double seed_a0, seed_p[2], seed_f, seed_t0, seed_tau, seed_cep, seed_zref;
+    /* optical undulator (reading R24): a plane wave towards -z in place of the
+       static undulator, same signal shapes as the seed */
+    int opt_on, opt_sig;
+    double opt_a, opt_p[2], opt_f, opt_t0, opt_tau, opt_cep, opt_zref;
     double lambda_u, K, gamma_beam, z_e;
     /* derived constants */
     double dt, dtb, a1, a2, a4, a6, a8;
@@ -720,11 +724,63 @@ void orc_gather(const orc_sim *s, const double *x, double *E, double *B)
 
 /* ---- O6: static planar undulator seen in the rest frame ------------------ */
 
-/* eqs. (undulatorField), fringe field for z' < 0, and the boost of reading R8 */
+/* Time derivative of the signal shapes of section "Seed Field" (the same
+   four shapes as orc_seed_signal, amplitude a), differentiated by hand:
+   carrier C = cos(w x + cep), envelope g = exp(-2 ln2 x^2 / tau^2). */
+static double signal_rate(int sig, double a, double f, double t0, double tau, double cep, double t)
+{
+    double x = t - t0, ln2 = log(2.0), w = 2.0 * ORC_PI * f;
+    double C = cos(w * x + cep), S = sin(w * x + cep);
+    double g = exp(-2.0 * ln2 * x * x / (tau * tau));
+    double g1 = -4.0 * ln2 * x / (tau * tau) * g;           /* g' */
+    double g2 = -4.0 * ln2 / (tau * tau) * (g + x * g1);    /* g'' */
+    switch (sig) {
+    case 0: /* s = a C g' */
+        return a * (-w * S * g1 + C * g2);
+    case 1: /* s = a C g */
+        return a * (-w * S * g + C * g1);
+    case 2: { /* s = a C sech(x / tau) */
+        double sech = 1.0 / cosh(x / tau);
+        return a * (-w * S * sech - C * sech * tanh(x / tau) / tau);
+    }
+    default: /* Gaussian rise, then the bare carrier */
+        return x <= 0.0 ? a * (-w * S * g + C * g1) : -a * w * S;
+    }
+}
+
+void orc_set_optical(orc_sim *s, int on, double a, double px, double py, double freq, double t0,
+                     double tau, double cep, int signal, double z_ref)
+{
+    s->opt_on = on;
+    s->opt_a = a;
+    s->opt_p[0] = px;
+    s->opt_p[1] = py;
+    s->opt_f = freq;
+    s->opt_t0 = t0;
+    s->opt_tau = tau;
+    s->opt_cep = cep;
+    s->opt_sig = signal;
+    s->opt_zref = z_ref;
+}
+
+/* eqs. (undulatorField), fringe field for z' < 0, and the boost of reading R8;
+   with the optical undulator on, the rest-frame plane wave
+   A_perp = a p s(t + (z - z_ref)/c): E = -a p s', B = (-a p_y s'/c, a p_x s'/c, 0) */
 void orc_undulator(const orc_sim *s, double x, double y, double z, double t, double *E,
                    double *B)
 {
     (void)x;
+    if (s->opt_on) {
+        double ds = signal_rate(s->opt_sig, s->opt_a, s->opt_f, s->opt_t0, s->opt_tau, s->opt_cep,
+                                t + (z - s->opt_zref) / ORC_C);
+        E[0] = -s->opt_p[0] * ds;
+        E[1] = -s->opt_p[1] * ds;
+        E[2] = 0.0;
+        B[0] = -s->opt_p[1] * ds / ORC_C;
+        B[1] = s->opt_p[0] * ds / ORC_C;
+        B[2] = 0.0;
+        return;
+    }
     double zp = s->gamma0 * (z - s->z_e + s->beta0 * ORC_C * t); /* lab z' */
     double ph = s->ku * zp, by, bz;
     if (zp >= 0.0) {

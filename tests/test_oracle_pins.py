@@ -1036,6 +1036,107 @@ def test_harmonic_power_of_a_pure_tone_is_its_mean_poynting_flux(h):
     assert max(abs(v) for v in others) < 1e-12 * mean_power, (P, mean_power)
 
 
+# ---------------------------------------------------------------------------
+# Optical undulator: a plane wave towards -z in place of the static undulator
+# ---------------------------------------------------------------------------
+
+def _optical_run(courant, substeps=1, a0=0.5, periods=4.0):
+    """Test electrons (q/m = -e/m_e, negligible charge) at rest in the mesh,
+    passed by a Gaussian-enveloped plane wave A = a p s(t + (z - z_ref)/c)
+    travelling towards -z.  Returns the largest departures, over every step,
+    from the two exact invariants of motion in a plane wave: gamma + u_z and
+    u_perp + q A_perp / (m c) (both zero-change for a start at rest)."""
+    n = (16, 16, 96)
+    d, origin = _mesh(n)
+    sim = oracle.OracleSim(n, d, origin, courant=courant, substeps=substeps, space_charge=0,
+                           K=1.0)
+    lam = 32 * d[2]
+    f = C / lam
+    tau = periods / f
+    amp = a0 * ME * C / QE
+    z0 = origin[2] + 30 * d[2]
+    pol = (0.6, 0.8)
+    sim.set_optical_undulator(amp, polarization=pol, frequency=f, t0=3 * tau, tau=tau,
+                              signal="gaussian", z_ref=z0)
+    rng = np.random.default_rng(5)
+    x = np.zeros((6, 3))
+    x[:, 0] = rng.uniform(-2, 2, 6) * d[0]
+    x[:, 1] = rng.uniform(-2, 2, 6) * d[1]
+    x[:, 2] = z0 + rng.uniform(-3, 3, 6) * d[2]
+    qm = 1e-30
+    sim.set_particles(x, np.zeros_like(x), -qm, ME * qm / QE)
+    dt = sim.const["dt"]
+    ln2 = math.log(2.0)
+
+    def A(t, z):  # the Gaussian signal of section "Seed Field", amplitude amp
+        xx = t + (z - z0) / C - 3 * tau
+        return amp * np.cos(2 * math.pi * f * xx) * np.exp(-2 * ln2 * xx * xx / tau ** 2)
+
+    worst_g, worst_p = 0.0, 0.0
+    steps = int(6 * tau / dt)
+    zprev = sim.x[:, 2].copy()
+    dtb = dt / substeps
+    for k in range(steps):
+        sim.step(1)
+        # leapfrog levels: positions at (k + 3/2) dt after the step, u half a
+        # particle sub-step before them; positions interpolated to that time
+        t = (k + 1.5) * dt - 0.5 * dtb
+        zc = sim.x[:, 2] - (sim.x[:, 2] - zprev) * (0.5 * dtb / dt)
+        zprev = sim.x[:, 2].copy()
+        u = sim.u
+        g = np.sqrt(1.0 + (u * u).sum(1))
+        worst_g = max(worst_g, float(np.max(np.abs(g + u[:, 2] - 1.0))))
+        a = A(t, zc)
+        for c in range(2):
+            inv = u[:, c] - QE * pol[c] * a / (ME * C)
+            worst_p = max(worst_p, float(np.max(np.abs(inv))))
+    assert sim.lost == 0
+    return worst_g, worst_p
+
+
+def test_optical_undulator_keeps_the_plane_wave_invariants_to_second_order():
+    """A charge in a plane wave travelling towards -z keeps gamma + u_z and
+    u_perp + q A_perp/(m c) (the exact solution of the Lorentz equation in a
+    plane wave); the Boris scheme keeps them to second order in the particle
+    step (halving the field step here, the particles being test charges).
+    With a0 = 0.5 the electrons swing to |u_perp| ~ 0.5.  Particle sub-steps
+    keep gamma + u_z to second order in the sub-step as well."""
+    g1, p1 = _optical_run(0.9)
+    g2, p2 = _optical_run(0.45)
+    assert g1 < 2e-3 and p1 < 1e-2, (g1, p1)
+    assert 3.0 < g1 / g2 < 5.0 and 3.0 < p1 / p2 < 5.0, (g1, g2, p1, p2)
+    g3, _ = _optical_run(0.9, substeps=2)
+    assert 3.0 < g1 / g3 < 5.0, (g1, g3)
+
+
+def test_optical_undulator_field_is_a_plane_wave_towards_minus_z():
+    """B = -(1/c) z-hat x E (a wave towards -z) with E parallel to the
+    polarization, and E = -dA/dt against a finite difference of the signal."""
+    n = (8, 8, 8)
+    d, origin = _mesh(n)
+    sim = oracle.OracleSim(n, d, origin)
+    f, tau, amp = 3e13, 1e-13, 2.0e-6
+    for sig in ("neumann", "gaussian", "secant", "flat-top"):
+        sim.set_optical_undulator(amp, polarization=(0.6, 0.8), frequency=f, t0=2e-13, tau=tau,
+                                  signal=sig, z_ref=1e-6)
+        sim.set_seed(amp, polarization=(0.6, 0.8), frequency=f, t0=2e-13, tau=tau, signal=sig,
+                     z_ref=0.0)
+        ex, want = [], []
+        for t in (1.3e-13, 1.7e-13, 2.0e-13, 2.4e-13, 2.9e-13):
+            z = 4e-6
+            E, B = sim.undulator(0.0, 0.0, z, t)
+            assert abs(E[2]) == 0 and abs(B[2]) == 0
+            assert np.allclose(E[:2], [-C * B[1], C * B[0]], rtol=1e-14, atol=0)
+            assert abs(E[0] * 0.8 - E[1] * 0.6) < 1e-12 * abs(E).max()
+            # the seed's signal is the same shape: s(phi) with phi = t + (z - z_ref)/c
+            phi = t + (z - 1e-6) / C
+            h = 2e-18
+            ex.append(E[0])
+            want.append(-0.6 * (sim.seed_signal(phi + h) - sim.seed_signal(phi - h)) / (2 * h))
+        want = np.array(want)
+        assert np.allclose(ex, want, rtol=1e-5, atol=1e-6 * np.abs(want).max()), (sig, ex, want)
+
+
 def _golden_rows():
     rows = []
     with open(os.path.join(GOLDEN, "resonance_wavelengths.txt")) as f:
