@@ -229,6 +229,19 @@ mithra_status mithra_config_diag(mithra_sim *sim, const mithra_diag_cfg *cfg);
    than 8 planes along z. */
 mithra_status mithra_set_seed(mithra_sim *sim, const mithra_seed *seed);
 
+/* Optical undulator (section "UNDULATOR", undulator-type optical, beam-type
+   plane wave): replace the static undulator's field acting on the particles
+   by a plane wave travelling towards -z, given in the rest frame in the form
+   of the seed: A_perp(t, z) = amplitude * polarization * s(t + (z - z_ref)/c),
+   s one of the four seed signals, so E = -amplitude * polarization * s',
+   B = (-p_y, p_x) * amplitude * s' / c.  The frame (gamma0) stays the one the
+   undulator struct of mithra_create defined; give it K = a0 of the wave and
+   lambda_u = half the laser wavelength to put the frame on the bunch's mean
+   velocity.  Amplitude 0 or wave == NULL switches back to the static
+   undulator.  Acts from the next step.  EINVAL for non-finite values,
+   tau <= 0, f < 0 or an unknown signal. */
+mithra_status mithra_set_optical_undulator(mithra_sim *sim, const mithra_seed *wave);
+
 /* Enqueue nsteps steps on the simulation's stream (asynchronous).  ESTATE if
    no particles were loaded (np = 0 is a valid load). */
 mithra_status mithra_run(mithra_sim *sim, int64_t nsteps);
@@ -292,6 +305,8 @@ mithra_status mithra_batch_set_particles(mithra_batch *b, int32_t sim, int64_t n
                                          double m_macro);
 mithra_status mithra_batch_config_diag(mithra_batch *b, int32_t sim, const mithra_diag_cfg *cfg);
 mithra_status mithra_batch_set_seed(mithra_batch *b, int32_t sim, const mithra_seed *seed);
+mithra_status mithra_batch_set_optical_undulator(mithra_batch *b, int32_t sim,
+                                                 const mithra_seed *wave);
 /* Autotuner of the batch (see mithra_tune): one tile shape for all
    simulations, chosen by timing the whole batched launch. */
 mithra_status mithra_batch_tune(mithra_batch *b, int32_t trial_steps);

@@ -66,6 +66,32 @@ __device__ double seed_signal(const SimDev &S, double t)
     }
 }
 
+// Rate ds/dt of the optical undulator's signal (the seed's four shapes with
+// the undulator's parameters): carrier C = cos(w x + cep), envelope
+// g = exp(-2 ln2 x^2 / tau^2), x = t - t0.
+__device__ double optical_rate(const SimDev &S, double t)
+{
+    const double x = t - S.opt_t0, ln2 = 0.69314718055994530942;
+    const double w = 2.0 * 3.14159265358979323846 * S.opt_f, it2 = 1.0 / (S.opt_tau * S.opt_tau);
+    double sn, cs;
+    sincos(w * x + S.opt_cep, &sn, &cs);
+    const double g = exp(-2.0 * ln2 * x * x * it2);
+    const double dg = -4.0 * ln2 * x * it2 * g;                 // g'
+    switch (S.opt_sig) {
+    case 0: {                                                   // a C g'
+        const double ddg = -4.0 * ln2 * it2 * (g + x * dg);     // g''
+        return S.opt_a * (cs * ddg - w * sn * dg);
+    }
+    case 1: return S.opt_a * (cs * dg - w * sn * g);            // a C g
+    case 2: {                                                   // a C sech(x / tau)
+        const double q = x / S.opt_tau, sech = 1.0 / cosh(q);
+        return -S.opt_a * sech * (w * sn + cs * tanh(q) / S.opt_tau);
+    }
+    default:                                                    // Gaussian rise, then C
+        return x <= 0.0 ? S.opt_a * (cs * dg - w * sn * g) : -S.opt_a * w * sn;
+    }
+}
+
 __device__ __forceinline__ int comp_extent(const SimDev &S, int c, int a)
 {
     return (c == a && !S.bc[a]) ? S.n[a] - 1 : S.n[a];
@@ -1000,10 +1026,21 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
             for (int sub = 0; sub < S.nsub; ++sub) {
                 const double ts = t0 + sub * S.dtb;
                 const double y = S.origin[1] + ((double)c[1] + (double)f[1]) * S.d[1];
-                R Eu, Buy, Buz;
-                undulator_kick<R>(S, ph_cell0 + S.phase_rate * ts, f[2], y, Eu, Buy, Buz);
-                const R e0 = F[0] + Eu, e1 = F[1], e2 = F[2];
-                const R b0 = F[3], b1 = F[4] + Buy, b2 = F[5] + Buz;
+                R Eu, Buy, Buz, Euy = 0, Bux = 0;
+                if (S.opt_on) {
+                    // optical undulator: E = -a p s', B = (-a p_y s', a p_x s') / c
+                    const double z = S.origin[2] + ((double)c[2] + (double)f[2]) * S.d[2];
+                    const double ds = optical_rate(S, ts + (z - S.opt_zref) / C_LIGHT_D);
+                    Eu = (R)(-S.kE * S.opt_p[0] * ds);
+                    Euy = (R)(-S.kE * S.opt_p[1] * ds);
+                    Bux = (R)(-S.kB * S.opt_p[1] * ds / C_LIGHT_D);
+                    Buy = (R)(S.kB * S.opt_p[0] * ds / C_LIGHT_D);
+                    Buz = 0;
+                } else {
+                    undulator_kick<R>(S, ph_cell0 + S.phase_rate * ts, f[2], y, Eu, Buy, Buz);
+                }
+                const R e0 = F[0] + Eu, e1 = F[1] + Euy, e2 = F[2];
+                const R b0 = F[3] + Bux, b1 = F[4] + Buy, b2 = F[5] + Buz;
                 // Boris: half kick, rotation, half kick
                 const R t1x = u[0] + e0, t1y = u[1] + e1, t1z = u[2] + e2;
                 const R ig = (R)1 / sqrt((R)1 + t1x * t1x + t1y * t1y + t1z * t1z);

@@ -79,6 +79,10 @@ struct SimDev {
     // seed plane wave along +z (TF/SF planes k = 2 and 3)
     int seed_on, seed_sig;
     double seed_a0, seed_p[2], seed_f, seed_t0, seed_tau, seed_cep, seed_zref;
+    // optical undulator: a plane wave towards -z, A = a p s(t + (z - z_ref)/c),
+    // in place of the static undulator (same signal shapes as the seed)
+    int opt_on, opt_sig;
+    double opt_a, opt_p[2], opt_f, opt_t0, opt_tau, opt_cep, opt_zref;
 };
 
 // Device buffers of a batch (one arena per quantity, simulations concatenated).

@@ -55,6 +55,7 @@ struct HostSim {
     mithra_undulator und;
     mithra_diag_cfg diag;
     mithra_seed seed{};  // amplitude 0: none
+    mithra_seed optical{};  // optical undulator (wave towards -z); amplitude 0: static undulator
     double dt, dtb, A, gamma0, beta0, B0, ku;
     bool loaded = false;
     double q = 0.0, m = 0.0;
@@ -276,6 +277,20 @@ static void fill_seed(const HostSim &h, SimDev &S)
     S.seed_zref = h.seed.z_ref;
 }
 
+static void fill_optical(const HostSim &h, SimDev &S)
+{
+    S.opt_on = h.optical.amplitude != 0.0 ? 1 : 0;
+    S.opt_sig = h.optical.signal;
+    S.opt_a = h.optical.amplitude;
+    S.opt_p[0] = h.optical.polarization[0];
+    S.opt_p[1] = h.optical.polarization[1];
+    S.opt_f = h.optical.frequency;
+    S.opt_t0 = h.optical.t0;
+    S.opt_tau = h.optical.tau > 0.0 ? h.optical.tau : 1.0;
+    S.opt_cep = h.optical.cep;
+    S.opt_zref = h.optical.z_ref;
+}
+
 // fill the per-simulation constants (offsets are set by the layout)
 static void fill_simdev(const HostSim &h, SimDev &S)
 {
@@ -339,6 +354,7 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     for (int a = 0; a < 3; ++a) S.J_unit[a] = -q * m.d[a] / (dV * h.dt);
     S.dV = dV;
     fill_seed(h, S);
+    fill_optical(h, S);
     S.mc2 = mm * C_LIGHT * C_LIGHT;
     S.dxdy_mu0 = m.d[0] * m.d[1] / MU0;
     S.eps0_half = 0.5 * EPS0;
@@ -1247,20 +1263,28 @@ static mithra_status config_diag(Batch &b, int s, const mithra_diag_cfg *cfg)
     return build_tables(b);
 }
 
+// checks of a wave's parameters (the seed and the optical undulator)
+static mithra_status check_wave(const mithra_seed *w, const char *what)
+{
+    const double v[] = {w->amplitude, w->polarization[0], w->polarization[1], w->frequency,
+                        w->t0, w->tau, w->cep, w->z_ref};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(MITHRA_EINVAL, "%s: non-finite value", what);
+    if (!(w->tau > 0.0)) return fail(MITHRA_EINVAL, "%s: tau must be > 0", what);
+    if (w->frequency < 0.0) return fail(MITHRA_EINVAL, "%s: frequency must be >= 0", what);
+    if (w->signal < MITHRA_SIGNAL_NEUMANN || w->signal > MITHRA_SIGNAL_FLAT_TOP)
+        return fail(MITHRA_EINVAL, "%s: unknown signal %d", what, w->signal);
+    return MITHRA_OK;
+}
+
 static mithra_status set_seed(Batch &b, int s, const mithra_seed *seed)
 {
     if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
     HostSim &h = b.hs[s];
     mithra_seed z{};
     if (seed && seed->amplitude != 0.0) {
-        const double v[] = {seed->amplitude, seed->polarization[0], seed->polarization[1],
-                            seed->frequency, seed->t0, seed->tau, seed->cep, seed->z_ref};
-        for (double x : v)
-            if (!std::isfinite(x)) return fail(MITHRA_EINVAL, "seed: non-finite value");
-        if (!(seed->tau > 0.0)) return fail(MITHRA_EINVAL, "seed: tau must be > 0");
-        if (seed->frequency < 0.0) return fail(MITHRA_EINVAL, "seed: frequency must be >= 0");
-        if (seed->signal < MITHRA_SIGNAL_NEUMANN || seed->signal > MITHRA_SIGNAL_FLAT_TOP)
-            return fail(MITHRA_EINVAL, "seed: unknown signal %d", seed->signal);
+        mithra_status st = check_wave(seed, "seed");
+        if (st) return st;
         if (h.mesh.bc[2] == MITHRA_BC_PERIODIC)
             return fail(MITHRA_EINVAL, "seed: the z axis must be absorbing (the wave enters at z_min)");
         z = *seed;
@@ -1269,6 +1293,24 @@ static mithra_status set_seed(Batch &b, int s, const mithra_seed *seed)
     h.seed = z;
     fill_seed(h, b.sd[s]);
     // the per-simulation block on the device is read at every launch
+    HIP_TRY(hipMemcpyAsync(b.d_sims + s, &b.sd[s], sizeof(SimDev), hipMemcpyHostToDevice, b.stream));
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    return MITHRA_OK;
+}
+
+static mithra_status set_optical(Batch &b, int s, const mithra_seed *wave)
+{
+    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
+    HostSim &h = b.hs[s];
+    mithra_seed z{};
+    if (wave && wave->amplitude != 0.0) {
+        mithra_status st = check_wave(wave, "optical undulator");
+        if (st) return st;
+        z = *wave;
+    }
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    h.optical = z;
+    fill_optical(h, b.sd[s]);
     HIP_TRY(hipMemcpyAsync(b.d_sims + s, &b.sd[s], sizeof(SimDev), hipMemcpyHostToDevice, b.stream));
     HIP_TRY(hipStreamSynchronize(b.stream));
     return MITHRA_OK;
@@ -1616,6 +1658,12 @@ mithra_status mithra_set_seed(mithra_sim *sim, const mithra_seed *seed)
     return set_seed(*sim->b, 0, seed);
 }
 
+mithra_status mithra_set_optical_undulator(mithra_sim *sim, const mithra_seed *wave)
+{
+    if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
+    return set_optical(*sim->b, 0, wave);
+}
+
 mithra_status mithra_run(mithra_sim *sim, int64_t nsteps)
 {
     if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
@@ -1756,6 +1804,13 @@ mithra_status mithra_batch_set_seed(mithra_batch *bb, int32_t sim, const mithra_
 {
     if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
     return set_seed(*bb->b, sim, seed);
+}
+
+mithra_status mithra_batch_set_optical_undulator(mithra_batch *bb, int32_t sim,
+                                                 const mithra_seed *wave)
+{
+    if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
+    return set_optical(*bb->b, sim, wave);
 }
 
 mithra_status mithra_batch_tune(mithra_batch *bb, int32_t trial_steps)

@@ -36,6 +36,7 @@ ABI_FUNCTIONS = (
     "mithra_batch_get_diag", "mithra_batch_get_field", "mithra_batch_get_particles",
     "mithra_batch_get_info", "mithra_batch_set_timing", "mithra_batch_get_timing",
     "mithra_batch_destroy", "mithra_set_seed", "mithra_batch_set_seed",
+    "mithra_set_optical_undulator", "mithra_batch_set_optical_undulator",
 )
 
 SIGNALS = {"neumann": 0, "gaussian": 1, "secant": 2, "flat-top": 3}
@@ -140,6 +141,8 @@ def load_library(path: str = LIB_PATH):
         "mithra_config_diag": [P, ctypes.POINTER(DiagCfg)],
         "mithra_set_seed": [P, ctypes.POINTER(Seed)],
         "mithra_batch_set_seed": [P, I32, ctypes.POINTER(Seed)],
+        "mithra_set_optical_undulator": [P, ctypes.POINTER(Seed)],
+        "mithra_batch_set_optical_undulator": [P, I32, ctypes.POINTER(Seed)],
         "mithra_run": [P, I64],
         "mithra_sync": [P],
         "mithra_get_field": [P, I32, dp],
@@ -320,6 +323,12 @@ class Sim:
         seed = make_seed(amplitude, **kw)
         _check(self._lib.mithra_set_seed(self._h, ctypes.byref(seed)))
 
+    def set_optical_undulator(self, amplitude, **kw):
+        """Plane wave towards -z in place of the static undulator (see
+        mithra_set_optical_undulator); amplitude 0 restores the static one."""
+        wave = make_seed(amplitude, **kw)
+        _check(self._lib.mithra_set_optical_undulator(self._h, ctypes.byref(wave)))
+
     def config_diag(self, probe, kp, every=1, capacity=4096):
         c = DiagCfg()
         for a in range(3):
@@ -436,6 +445,10 @@ class Batch:
     def set_seed(self, s, amplitude, **kw):
         seed = make_seed(amplitude, **kw)
         _check(self._lib.mithra_batch_set_seed(self._h, int(s), ctypes.byref(seed)))
+
+    def set_optical_undulator(self, s, amplitude, **kw):
+        wave = make_seed(amplitude, **kw)
+        _check(self._lib.mithra_batch_set_optical_undulator(self._h, int(s), ctypes.byref(wave)))
 
     def config_diag(self, s, probe, kp, every=1, capacity=4096):
         c = DiagCfg()

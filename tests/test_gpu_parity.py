@@ -238,6 +238,84 @@ def test_seeded_full_loop_f64():
     compare_diag(sim.get_diag(), orc.diag(), TOL64, "seeded")
 
 
+def _optical_wave(w, a0=0.5):
+    """A Gaussian-enveloped plane wave towards -z (rest frame), a0 = 0.5,
+    wavelength 32 cells, crossing the bunch during the run."""
+    tau = 64 * w.d[2] / C
+    return a0 * ME * C / QE, dict(polarization=(0.6, 0.8), frequency=C / (32 * w.d[2]),
+                                   t0=2 * tau, tau=tau, cep=0.2, signal="gaussian",
+                                   z_ref=w.origin[2] + (w.n[2] - 1) * w.d[2] / 2)
+
+
+def _bunch_at_rest(w):
+    """The bunch at rest in the central half of the mesh along z (momenta
+    matched to the static undulator would carry it out of the mesh once the
+    wave replaces that field)."""
+    zc = w.origin[2] + (w.n[2] - 1) * w.d[2] / 2
+    x = w.x.copy()
+    x[:, 2] = zc + 0.5 * (x[:, 2] - zc)
+    w.x = x
+    w.u = np.zeros_like(w.u)
+    return w
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_optical_undulator_full_loop_matches_oracle(precision):
+    """The tiny bunch driven by the optical undulator (a plane wave towards -z
+    in place of the static undulator) for 60 steps: the whole state and the
+    diagnostics against the oracle."""
+    w = _bunch_at_rest(W.config(0, steps=60))
+    amp, wave = _optical_wave(w)
+    say("case optical undulator", w.n, precision)
+    orc = oracle.from_workload(w)
+    orc.set_optical_undulator(amp, **wave)
+    sim = native.sim_from_workload(w, precision=precision, every=1)
+    sim.set_optical_undulator(amp, **wave)
+    sim.run(60)
+    sim.sync()
+    orc.step(60)
+    if precision == "f64":
+        compare_state(sim, orc, TOL64, "optical")
+        compare_diag(sim.get_diag(), orc.diag(), TOL64, "optical")
+    else:
+        pos, u, alive = sim.get_particles()
+        assert np.array_equal(alive, orc.alive)
+        err = rel_l2(u, orc.u)
+        say("optical f32 u rel-L2", err)
+        assert err < 1e-4, err
+    # the wave really drives the particles (they started at rest), none lost
+    assert np.max(np.abs(orc.u[:, 1])) > 0.05 and orc.lost == 0
+
+
+def test_optical_undulator_switched_off_is_the_static_one_bitwise():
+    w = W.config(0, steps=20)
+    amp, wave = _optical_wave(w)
+    outs = []
+    for toggle in (False, True):
+        sim = native.sim_from_workload(w, precision="f64")
+        if toggle:
+            sim.set_optical_undulator(amp, **wave)
+            sim.set_optical_undulator(0.0)
+        sim.run(20)
+        sim.sync()
+        outs.append(list(sim.get_particles()) + [sim.get_field("Ax"), sim.get_field("Ez")])
+        sim.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b, equal_nan=True)
+
+
+def test_optical_undulator_rejects_bad_waves():
+    w = W.config(0, steps=1)
+    sim = native.sim_from_workload(w, precision="f64")
+    amp, wave = _optical_wave(w)
+    for bad in (dict(tau=0.0), dict(tau=-1.0), dict(frequency=-1.0), dict(signal=7),
+                dict(cep=float("nan"))):
+        with pytest.raises(native.MithraError) as e:
+            sim.set_optical_undulator(amp, **{**wave, **bad})
+        assert e.value.status == native.EINVAL
+    sim.close()
+
+
 def test_plane_wave_dispersion_on_gpu():
     """Property at any size: a plane wave with the frequency of eq.
     (NSFDDispersionCD) stays an exact discrete solution on the GPU too."""
