@@ -160,7 +160,8 @@ def example1_run(steps, torch, native, W):
     """The paper's infrared FEL example (job-file reading), run to saturation;
     returns timing, the fitted gain length and the yardsticks."""
     w = W.example1(steps=steps)
-    sim = native.sim_from_workload(w, precision="f64", every=100, capacity=steps + 8)
+    sim = native.sim_from_workload(w, precision="f64", every=100, capacity=steps + 8,
+                                   spectrum=False)
     sim.run(8)
     sim.sync()
     torch.cuda.synchronize()
@@ -197,7 +198,7 @@ def measure(w, precision, steps, warmup, torch, native, tune=True, every=100, se
     """Graph-replayed timed region, then an event-timed region of the same
     length for the per-kernel durations."""
     t_setup = time.perf_counter()
-    sim = native.sim_from_workload(w, precision=precision, every=every)
+    sim = native.sim_from_workload(w, precision=precision, every=every, spectrum=False)
     if seed is not None:
         sim.set_seed(**seed)
     if tune:
@@ -384,7 +385,7 @@ def main():
     if args.extra:
         log("batched scan: 64 simulations")
         ws = W.batch_configs(64, steps=100)
-        b = native.batch_from_workloads(ws, precision="f32", every=100)
+        b = native.batch_from_workloads(ws, precision="f32", every=100, spectrum=False)
         b.tune(2)
         b.run(8)
         b.sync()
@@ -397,7 +398,7 @@ def main():
         b.close()
         seq = 0.0
         for i, wi in enumerate(ws):
-            s = native.sim_from_workload(wi, precision="f32", every=100)
+            s = native.sim_from_workload(wi, precision="f32", every=100, spectrum=False)
             s.run(8)
             s.sync()
             seq += timed_run(s, nb, torch)

@@ -153,6 +153,9 @@ typedef struct {
     int32_t power_plane_k;   /* z index of the plane of the power diagnostic */
     int32_t mesh_diag_every; /* mesh-wide terms every M steps (M >= 1), 0 = never */
     int32_t capacity;        /* rows kept in the device ring (>= 1) */
+    int32_t power_spectrum;  /* 1: sample the running DFT of the power plane each step for
+                                mithra_diag_row.power_harmonic (FEL output); 0 (default):
+                                off, power_harmonic = 0.  Changes only before the first step */
 } mithra_diag_cfg;
 
 /* One row per completed step s (fields at t = (s+1/2) dt). */
@@ -173,7 +176,8 @@ typedef struct {
                                    the push; z the rest-frame longitudinal position,
                                    K = 2 gamma0 k_u the ponderomotive wave number in
                                    this frame (section "Bunching factor")  (mesh term) */
-    double power_harmonic[3];   /* mean power [W] carried through plane k at h omega_1,
+    double power_harmonic[3];   /* (with power_spectrum on) mean power [W] carried through
+                                   plane k at h omega_1,
                                    h = 1, 2, 3, omega_1 = gamma0 beta0 c k_u the rest-frame
                                    resonant frequency, since the state was committed:
                                    (2/T^2) sum Re(F_Ex F_By* - F_Ey F_Bx*)/mu0 dx dy with

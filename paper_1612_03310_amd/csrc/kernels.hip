@@ -723,7 +723,9 @@ __device__ __forceinline__ void count_runs(int *counts, int key, bool active)
     }
 }
 
-template <typename R>
+// OPTICAL: the variant that also evaluates the optical undulator (its FP64
+// transcendentals would otherwise raise the register count of every launch)
+template <typename R, bool OPTICAL>
 __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
                                                  const int2 *__restrict__ items, int nitems,
                                                  int chunk, Arena ar)
@@ -1027,7 +1029,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
                 const double ts = t0 + sub * S.dtb;
                 const double y = S.origin[1] + ((double)c[1] + (double)f[1]) * S.d[1];
                 R Eu, Buy, Buz, Euy = 0, Bux = 0;
-                if (S.opt_on) {
+                if (OPTICAL && S.opt_on) {
                     // optical undulator: E = -a p s', B = (-a p_y s', a p_x s') / c
                     const double z = S.origin[2] + ((double)c[2] + (double)f[2]) * S.d[2];
                     const double ds = optical_rate(S, ts + (z - S.opt_zref) / C_LIGHT_D);
@@ -1635,8 +1637,9 @@ __device__ __forceinline__ void diag_plane(const SimDev *__restrict__ sims, int2
     const long long step = *ar.d_step;
     const FieldPtrs<R> f = field_ptrs<R>(S, ar, step % 3, (step + 1) % 3, (int)(step % 3));
     const int e = it.y * BLOCK + threadIdx.x;
+    const long long npl = (long long)S.n[0] * S.n[1];
     double t[PLANE_TERMS] = {0.0, 0.0, 0.0, 0.0};
-    if (e < S.n[0] * S.n[1]) {
+    if (e < npl) {
         const int i = e % S.n[0], j = e / S.n[0];
         if (vertex_valid(S, i, j, S.kp)) {
             R E[3], B[3];
@@ -1644,27 +1647,40 @@ __device__ __forceinline__ void diag_plane(const SimDev *__restrict__ sims, int2
             t[0] = (double)E[0] * (double)B[1] - (double)E[1] * (double)B[0];
             const double fv[4] = {(double)E[0], (double)E[1], (double)B[0], (double)B[1]};
             const double tm = ((double)step + 0.5) * S.dt;
-            double *acc = ar.spec + S.spec0 + (long long)e * SPEC_PER_POINT;
+            if (S.spec_on) {
+                // the sums are stored sum-major (sum q of point e at q * npl + e),
+                // so each access is one contiguous span per wavefront; one
+                // harmonic (8 sums) at a time keeps the register count of the
+                // launch, which all roles share, low
+                double *acc = ar.spec + S.spec0 + e;
+                // harmonics 2 and 3 of the phase by angle addition from the first
+                double s1, c1;
+                sincos(S.omega1 * tm, &s1, &c1);
+                double sn = 0.0, cs = 1.0;
+                for (int h = 1; h <= 3; ++h) {
+                    const double sn_next = sn * c1 + cs * s1;
+                    cs = cs * c1 - sn * s1;
+                    sn = sn_next;
+                    double *ah = acc + (long long)(h - 1) * 8 * npl;
+                    double a[8];
 #pragma unroll
-            for (int h = 1; h <= 3; ++h) {
-                double sn, cs;
-                sincos((double)h * S.omega1 * tm, &sn, &cs);
-                double a[8];
+                    for (int q = 0; q < 8; ++q) a[q] = ah[q * npl];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    a[2 * c] = acc[(h - 1) * 8 + 2 * c] + fv[c] * cs * S.dt;
-                    a[2 * c + 1] = acc[(h - 1) * 8 + 2 * c + 1] - fv[c] * sn * S.dt;
+                    for (int c = 0; c < 4; ++c) {
+                        a[2 * c] = a[2 * c] + fv[c] * cs * S.dt;
+                        a[2 * c + 1] = a[2 * c + 1] - fv[c] * sn * S.dt;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) ah[q * npl] = a[q];
+                    // (re, im) pairs: Ex a[0..1], Ey a[2..3], Bx a[4..5], By a[6..7]
+                    t[h] = (a[0] * a[6] + a[1] * a[7]) - (a[2] * a[4] + a[3] * a[5]);
                 }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) acc[(h - 1) * 8 + q] = a[q];
-                // (re, im) pairs: Ex a[0..1], Ey a[2..3], Bx a[4..5], By a[6..7]
-                t[h] = (a[0] * a[6] + a[1] * a[7]) - (a[2] * a[4] + a[3] * a[5]);
             }
         }
     }
     __shared__ double sh[BLOCK];
-#pragma unroll
-    for (int q = 0; q < PLANE_TERMS; ++q) {
+    const int nterms = S.spec_on ? PLANE_TERMS : 1;  // uniform over the block
+    for (int q = 0; q < nterms; ++q) {
         const double tot = block_sum(t[q], sh);
         if (threadIdx.x == 0) ar.partial[S.part_plane0 + (long long)PLANE_TERMS * it.y + q] = tot;
     }
@@ -1740,13 +1756,16 @@ __device__ __forceinline__ void diag_kin(const SimDev *__restrict__ sims, int2 i
         const double z = ar.zr[S.part0 + i];
         if (z == z) {
             t[1] += 1.0;
-#pragma unroll
-            for (int h = 1; h <= 3; ++h) {
-                double sn, cs;
-                sincos((double)h * S.kbunch * z, &sn, &cs);
-                t[2 * h] += cs;
-                t[2 * h + 1] += sn;
-            }
+            // harmonics 2 and 3 of the phase by angle addition from the first
+            double s1, c1;
+            sincos(S.kbunch * z, &s1, &c1);
+            const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * s1 * c1;
+            t[2] += c1;
+            t[3] += s1;
+            t[4] += c2;
+            t[5] += s2;
+            t[6] += c2 * c1 - s2 * s1;
+            t[7] += s2 * c1 + c2 * s1;
         }
     }
     __shared__ double sh[BLOCK];
@@ -1842,7 +1861,8 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
                               : 0.0;
         row[19] = 0.0;
         const double T = ((double)step + 1.0) * S.dt;
-        for (int h = 0; h < 3; ++h) row[20 + h] = 2.0 / (T * T) * pt[1 + h] * S.dxdy_mu0;
+        for (int h = 0; h < 3; ++h)
+            row[20 + h] = S.spec_on ? 2.0 / (T * T) * pt[1 + h] * S.dxdy_mu0 : 0.0;
         row[23] = 0.0;
         // every block has read the step counter before it counts itself done
         if (atomicAdd(ar.fin_ctr, 1) == (int)gridDim.x - 1) {
@@ -1937,11 +1957,15 @@ static int dealt_grid(int nitems, int chunk)
 
 template <typename R>
 void launch_push(hipStream_t st, const SimDev *sims, const int2 *items, int nitems, int chunk,
-                 const Arena &ar)
+                 const Arena &ar, int optical)
 {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL((k_push<R>), dim3(dealt_grid(nitems, chunk)), dim3(BLOCK), 0, st, sims,
-                       items, nitems, chunk, ar);
+    if (optical)
+        hipLaunchKernelGGL((k_push<R, true>), dim3(dealt_grid(nitems, chunk)), dim3(BLOCK), 0, st,
+                           sims, items, nitems, chunk, ar);
+    else
+        hipLaunchKernelGGL((k_push<R, false>), dim3(dealt_grid(nitems, chunk)), dim3(BLOCK), 0, st,
+                           sims, items, nitems, chunk, ar);
 }
 
 template <typename R>
@@ -1999,7 +2023,7 @@ void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long
     template void launch_mur2<R>(hipStream_t, const SimDev *, const BSeg *, int, long long,     \
                                  const Arena &);                                                \
     template void launch_push<R>(hipStream_t, const SimDev *, const int2 *, int, int,           \
-                                 const Arena &);                                                \
+                                 const Arena &, int);                                           \
     template void launch_deposit<R>(hipStream_t, const SimDev *, const int2 *, int, int,        \
                                     const Arena &, int);                                        \
     template void launch_scatter<R>(hipStream_t, const Arena &, long long);                     \

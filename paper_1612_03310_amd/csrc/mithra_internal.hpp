@@ -76,6 +76,7 @@ struct SimDev {
     double kbunch;      // 2 gamma0 k_u: wave number of the bunching factor
     double omega1;      // gamma0 beta0 c k_u: rest-frame resonant frequency
     long long spec0;    // first double of this simulation in the plane-spectrum arena
+    int spec_on;        // the plane spectrum is sampled
     // seed plane wave along +z (TF/SF planes k = 2 and 3)
     int seed_on, seed_sig;
     double seed_a0, seed_p[2], seed_f, seed_t0, seed_tau, seed_cep, seed_zref;
@@ -103,7 +104,8 @@ struct Arena {
     double *ke;         // (gamma - 1) by particle id, for the kinetic-energy sum
     double *zr;         // rest-frame z by particle id (NaN once lost), for the bunching factor
     double *partial;    // diagnostic partial sums
-    double *spec;       // running DFT of the power-plane fields at the harmonics (reset at commit)
+    double *spec;       // running DFT of the power-plane fields at the harmonics, per simulation
+                        // sum-major: sum q of plane point e at spec0 + q * nx * ny + e (reset at commit)
     double *ring;       // diagnostic rows
     int *flags;         // per simulation: a non-finite value was produced
     int *tact;          // per tile: a particle in the 27-tile neighbourhood at the start of
@@ -135,10 +137,10 @@ template <typename R>
 void launch_mur2(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg, long long total,
                  const Arena &ar);
 // push and deposit: the tile table is dealt to the XCDs in chunks of `chunk`
-// tiles
+// tiles; optical: some simulation has the optical undulator on
 template <typename R>
 void launch_push(hipStream_t st, const SimDev *sims, const int2 *items, int nitems, int chunk,
-                 const Arena &ar);
+                 const Arena &ar, int optical);
 template <typename R>
 void launch_deposit(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
                     int chunk, const Arena &ar, int init);

@@ -154,6 +154,14 @@ static void dev_free_all(Batch &b, std::vector<void *> &owner)
     owner.clear();
 }
 
+// some simulation has the optical undulator on (selects the push variant)
+static int any_optical(const Batch &b)
+{
+    for (int s = 0; s < b.nsim; ++s)
+        if (b.sd[s].opt_on) return 1;
+    return 0;
+}
+
 static void drop_graph(Batch &b)
 {
     if (b.gexec) (void)hipGraphExecDestroy(b.gexec);
@@ -367,6 +375,7 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     S.kp = h.diag.power_plane_k;
     S.mesh_every = h.diag.mesh_diag_every;
     S.ring_cap = h.diag.capacity;
+    S.spec_on = h.diag.power_spectrum ? 1 : 0;
 }
 
 static int tile_key_host(const SimDev &S, int ci, int cj, int ck)
@@ -925,7 +934,7 @@ static void enqueue_step(Batch &b, bool timed)
         launch_mur2<R>(st, b.d_sims, b.d_m2seg[stage], b.nm2seg[stage], b.nm2_total[stage], b.ar);
     mark(K_BOUNDARY, false);
     mark(K_PUSH, true);
-    launch_push<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar);
+    launch_push<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar, any_optical(b));
     mark(K_PUSH, false);
     if (timed) {
         // one stream, so that each kind's events bracket that kind alone
@@ -1235,6 +1244,10 @@ static mithra_status config_diag(Batch &b, int s, const mithra_diag_cfg *cfg)
         return fail(MITHRA_ESTATE, "the ring capacity can only change before the first step");
     if (cfg->capacity < 1 || cfg->capacity > (1 << 24))
         return fail(MITHRA_EINVAL, "capacity must be in [1, 2^24]");
+    if (cfg->power_spectrum != 0 && cfg->power_spectrum != 1)
+        return fail(MITHRA_EINVAL, "power_spectrum must be 0 or 1");
+    if (cfg->power_spectrum != h.diag.power_spectrum && b.step > 0)
+        return fail(MITHRA_ESTATE, "the power spectrum can only be switched before the first step");
     HIP_TRY(hipStreamSynchronize(b.stream));
     const int old_cap = h.diag.capacity;
     h.diag = *cfg;
@@ -1260,6 +1273,7 @@ static mithra_status config_diag(Batch &b, int s, const mithra_diag_cfg *cfg)
     S.kp = cfg->power_plane_k;
     S.mesh_every = cfg->mesh_diag_every;
     S.ring_cap = cfg->capacity;
+    S.spec_on = cfg->power_spectrum;
     return build_tables(b);
 }
 
@@ -1309,8 +1323,11 @@ static mithra_status set_optical(Batch &b, int s, const mithra_seed *wave)
         z = *wave;
     }
     HIP_TRY(hipStreamSynchronize(b.stream));
+    const int before = any_optical(b);
     h.optical = z;
     fill_optical(h, b.sd[s]);
+    // the captured step launches the push variant chosen at capture
+    if (any_optical(b) != before) drop_graph(b);
     HIP_TRY(hipMemcpyAsync(b.d_sims + s, &b.sd[s], sizeof(SimDev), hipMemcpyHostToDevice, b.stream));
     HIP_TRY(hipStreamSynchronize(b.stream));
     return MITHRA_OK;

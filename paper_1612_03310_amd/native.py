@@ -78,7 +78,8 @@ def make_seed(amplitude, polarization=(1.0, 0.0), frequency=0.0, t0=0.0, tau=1.0
 
 class DiagCfg(ctypes.Structure):
     _fields_ = [("probe", ctypes.c_int32 * 3), ("power_plane_k", ctypes.c_int32),
-                ("mesh_diag_every", ctypes.c_int32), ("capacity", ctypes.c_int32)]
+                ("mesh_diag_every", ctypes.c_int32), ("capacity", ctypes.c_int32),
+                ("power_spectrum", ctypes.c_int32)]
 
 
 class DiagRow(ctypes.Structure):
@@ -329,13 +330,14 @@ class Sim:
         wave = make_seed(amplitude, **kw)
         _check(self._lib.mithra_set_optical_undulator(self._h, ctypes.byref(wave)))
 
-    def config_diag(self, probe, kp, every=1, capacity=4096):
+    def config_diag(self, probe, kp, every=1, capacity=4096, spectrum=False):
         c = DiagCfg()
         for a in range(3):
             c.probe[a] = int(probe[a])
         c.power_plane_k = int(kp)
         c.mesh_diag_every = int(every)
         c.capacity = int(capacity)
+        c.power_spectrum = 1 if spectrum else 0
         _check(self._lib.mithra_config_diag(self._h, ctypes.byref(c)))
 
     def run(self, nsteps: int):
@@ -450,13 +452,14 @@ class Batch:
         wave = make_seed(amplitude, **kw)
         _check(self._lib.mithra_batch_set_optical_undulator(self._h, int(s), ctypes.byref(wave)))
 
-    def config_diag(self, s, probe, kp, every=1, capacity=4096):
+    def config_diag(self, s, probe, kp, every=1, capacity=4096, spectrum=False):
         c = DiagCfg()
         for a in range(3):
             c.probe[a] = int(probe[a])
         c.power_plane_k = int(kp)
         c.mesh_diag_every = int(every)
         c.capacity = int(capacity)
+        c.power_spectrum = 1 if spectrum else 0
         _check(self._lib.mithra_batch_config_diag(self._h, int(s), ctypes.byref(c)))
 
     def tune(self, trials: int = 5):
@@ -510,22 +513,23 @@ class Batch:
 
 
 def sim_from_workload(w, precision: str = "f64", every: int = 1, capacity: int = 4096,
-                      **kw) -> Sim:
-    """A simulation loaded with a workload from the seeded generator."""
+                      spectrum: bool = True, **kw) -> Sim:
+    """A simulation loaded with a workload from the seeded generator (every
+    diagnostic on, the plane spectrum included, unless told otherwise)."""
     s = Sim(w.n, w.d, w.origin, w.courant, w.nsfd_A, w.substeps, w.space_charge, w.bc,
             w.lambda_u, w.K, w.gamma_beam, w.z_e, precision=precision, **kw)
-    s.config_diag(w.probe, w.kp, every=every, capacity=capacity)
+    s.config_diag(w.probe, w.kp, every=every, capacity=capacity, spectrum=spectrum)
     s.set_particles(w.x, w.u, w.q, w.m)
     return s
 
 
 def batch_from_workloads(ws, precision: str = "f32", every: int = 1, capacity: int = 4096,
-                         **kw) -> Batch:
+                         spectrum: bool = True, **kw) -> Batch:
     meshes = [make_mesh(w.n, w.d, w.origin, w.courant, w.nsfd_A, w.substeps, w.space_charge,
                         w.bc) for w in ws]
     unds = [make_undulator(w.lambda_u, w.K, w.gamma_beam, w.z_e) for w in ws]
     b = Batch(meshes, unds, precision=precision, **kw)
     for s, w in enumerate(ws):
-        b.config_diag(s, w.probe, w.kp, every=every, capacity=capacity)
+        b.config_diag(s, w.probe, w.kp, every=every, capacity=capacity, spectrum=spectrum)
         b.set_particles(s, w.x, w.u, w.q, w.m)
     return b

@@ -446,6 +446,7 @@ def test_harmonic_power_of_a_pure_tone(precision):
     orc = oracle.OracleSim(n, d, origin, **kw)
     orc.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
     sim = native.Sim(n, d, origin, precision=precision, **kw)
+    sim.config_diag((n[0] // 2, n[1] // 2, n[2] // 2), n[2] // 2, spectrum=True)
     sim.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
     kk = np.arange(n[2])
     f = lambda z: 3.0e-9 * np.cos(2.0 * math.pi * m * z / n[2] + 0.4)
@@ -467,6 +468,19 @@ def test_harmonic_power_of_a_pure_tone(precision):
     assert err <= tol, err
     assert abs(P[h - 1] / mean - 1.0) <= tol
     assert abs(P[0]) <= tol * mean and abs(P[2]) <= tol * mean
+
+
+def test_power_spectrum_is_off_by_default_and_fixed_after_the_first_step():
+    w = W.config(0, steps=5)
+    sim = native.sim_from_workload(w, spectrum=False)
+    sim.run(5)
+    sim.sync()
+    dg = sim.get_diag()
+    assert np.all(dg["power_harmonic"] == 0.0) and np.any(dg["power"] != 0.0)
+    with pytest.raises(native.MithraError) as e:
+        sim.config_diag(w.probe, w.kp, spectrum=True)
+    assert e.value.status == native.ESTATE
+    sim.close()
 
 
 # ---------------------------------------------------------------------------
