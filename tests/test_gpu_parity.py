@@ -304,6 +304,53 @@ def test_optical_undulator_switched_off_is_the_static_one_bitwise():
         assert np.array_equal(a, b, equal_nan=True)
 
 
+def test_optical_undulator_switched_on_mid_run_matches_oracle():
+    """Steps replayed from a captured graph, then the wave switched on (the
+    batch launches another push variant, so the graph is captured again),
+    then more steps: the state against the oracle doing the same.  (A weak
+    static undulator, K = 0.01, keeps the bunch in place before the wave.)"""
+    w = _bunch_at_rest(W.make_workload("optical-switch", (32, 32, 64), 4096, 100.0, 0.01, 0.015,
+                                       1e-4, 58, 40))
+    amp, wave = _optical_wave(w)
+    orc = oracle.from_workload(w)
+    sim = native.sim_from_workload(w, precision="f64", every=1)
+    sim.run(20)
+    orc.step(20)
+    sim.set_optical_undulator(amp, **wave)
+    orc.set_optical_undulator(amp, **wave)
+    sim.run(20)
+    sim.sync()
+    orc.step(20)
+    compare_state(sim, orc, TOL64, "optical mid-run")
+    compare_diag(sim.get_diag(), orc.diag(), TOL64, "optical mid-run")
+
+
+def test_batch_mixing_optical_and_static_undulators_equals_separate_runs():
+    """One simulation with the optical undulator, one with the static one, in
+    one batch (both through the optical push variant): each equals its own
+    separate run bit for bit."""
+    ws = [_bunch_at_rest(W.config(0, steps=30)),
+          W.make_workload("static", (32, 32, 96), 3000, 120.0, 1.2, 0.015, 1e-4, 77, 30)]
+    amp, wave = _optical_wave(ws[0])
+    b = native.batch_from_workloads(ws, precision="f64")
+    b.set_optical_undulator(0, amp, **wave)
+    b.run(30)
+    b.sync()
+    for s, w in enumerate(ws):
+        sim = native.sim_from_workload(w, precision="f64")
+        if s == 0:
+            sim.set_optical_undulator(amp, **wave)
+        sim.run(30)
+        sim.sync()
+        for name in ("Ax", "Ay", "phi", "rho", "Jx"):
+            assert np.array_equal(b.get_field(s, name), sim.get_field(name)), (s, name)
+        for x, y in zip(b.get_particles(s), sim.get_particles()):
+            assert np.array_equal(x, y, equal_nan=True), s
+        assert b.get_diag(s).tobytes() == sim.get_diag().tobytes(), s
+        sim.close()
+    b.close()
+
+
 def test_optical_undulator_rejects_bad_waves():
     w = W.config(0, steps=1)
     sim = native.sim_from_workload(w, precision="f64")
