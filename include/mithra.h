@@ -218,7 +218,8 @@ mithra_status mithra_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
 
 /* Load np macro-particles (section "Electron Bunch Generation" produces them;
    the caller supplies the result).  pos: [np][3] rest-frame positions [m] at
-   t = (s+1/2) dt; u: [np][3] gamma*beta at t = s dt; q_macro, m_macro: charge
+   t = (s+1/2) dt; u: [np][3] gamma*beta half a particle sub-step earlier, at
+   t = (s+1/2) dt - dtb/2 (= s dt with one sub-step); q_macro, m_macro: charge
    [C] (signed) and mass [kg] of one macro-particle.  Particles whose cell is
    outside [2, n-3] on an axis are counted as lost at once.  Deposits
    rho^{s+1/2}; sets J^s = 0.  EINVAL for np < 0, non-finite input or m <= 0. */
