@@ -29,8 +29,9 @@
  *   - Time levels: after s completed steps the newest potentials are A^s,
  *     phi^s (phi^s belongs to t = (s+1/2) dt, section "FDTD for Scalar
  *     Potential"); particle positions belong to t = (s+1/2) dt and momenta
- *     u = gamma*beta to t = s dt.  Input particles are taken as r^{1/2},
- *     u^0; the potentials start at zero and J^0 = 0.
+ *     u = gamma*beta half a particle sub-step earlier (t = s dt with one
+ *     sub-step).  Input particles are taken at s = 0; the potentials start
+ *     at zero and J^0 = 0.
  *   - Every call returns a mithra_status; nothing throws across the ABI.
  *     On error mithra_last_error() gives a message naming the violated
  *     condition (a thread-local string, valid until the next call on the

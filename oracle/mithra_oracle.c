@@ -31,7 +31,8 @@
  *   R8  rest-frame undulator field: E_x = -g0 b0 c B'_y, B_y = g0 B'_y,
  *       B_z = B'_z, phase k_u z' with z' = g0 (z - z_e + b0 c t);
  *   R10 start from zero potentials, J^0 = 0, rho^{1/2} from the input
- *       positions (taken as r^{1/2}; momenta as u^0);
+ *       positions (taken as r^{1/2}; momenta half a particle sub-step
+ *       earlier, u^0 with one sub-step);
  *   R16 first-order Mur on faces, then edges, then corners; a point on
  *       several faces uses the rule of its highest-priority axis
  *       (z > y > x);
@@ -55,7 +56,16 @@
  *       the standard signs, so that the total-field region carries +A; the
  *       printed signs would inject -A.  The printed "sinusoidal pulse" is
  *       the job file's "flat-top" signal;
- *   R17 a particle whose cell leaves [2, n_d - 3] on any axis is lost.
+ *   R17 a particle whose cell leaves [2, n_d - 3] on any axis is lost;
+ *   R21 bunching factor (section "Bunching factor"), a diagnostic here:
+ *       b_h = |<exp(i h K z)>| over live particles, K = 2 gamma0 k_u;
+ *   R22 power at the harmonics h omega_1 (omega_1 = gamma0 beta0 c k_u)
+ *       through the power plane from a running DFT of the plane's fields
+ *       (section "FEL-OUTPUT" names the output, not its transform);
+ *   R24 optical undulator (section "UNDULATOR"): a plane wave towards -z,
+ *       A_perp = a p s(t + (z - z_ref)/c) in the rest frame with the seed's
+ *       signal shapes, in place of the static undulator's field on the
+ *       particles.
  */
 #include <math.h>
 #include <stdint.h>
