@@ -19,7 +19,9 @@ examples and the published configuration list):
   cells, truncated at 3 sigma by re-drawing (numpy PCG64, seeded);
 * lab energy gamma' = gamma * (1 + sigma_delta * N(0, 1)); momenta matched to
   the undulator at the particle's lab phase, u'_x = -K cos(k_u z'),
-  u'_y = 0, u'_z from gamma', then boosted to the rest frame;
+  u'_y = 0, u'_z from gamma', then boosted to the rest frame, taken at the
+  leapfrog's time level of u (half a particle sub-step before the positions,
+  which belong to dt/2);
 * each particle sits at its guiding centre plus its wiggle offset,
   x = x_c - K / (gamma0 k_u sqrt(1 + K^2/2)) sin(k_u z'), so that its
   transverse oscillation is centred on x_c (a particle started at its
@@ -85,6 +87,32 @@ def _truncated_normal(rng: np.random.Generator, size: int, cut: float) -> np.nda
     return out
 
 
+def _matched(x, gp, gamma0, beta0, K, ku, z_e, dt, substeps):
+    """Momenta matched to the undulator, u'_x = -K cos(k_u z'), u'_y = 0,
+    u'_z from the lab energy gp, boosted to the rest frame, at the leapfrog's
+    time level of u: the positions x belong to t = dt/2 and the momenta to
+    half a particle sub-step before, so the lab phase is taken at that time
+    and at the particle's position then.  Also returns the x positions moved
+    by the wiggle offset at the positions' own phase, so that the transverse
+    oscillation is centred on the input x (a particle started at its centre
+    would swing up to twice the amplitude to one side)."""
+    t_u = 0.5 * dt - 0.5 * dt / substeps
+    zu = x[:, 2].copy()
+    for _ in range(8):
+        zlab = gamma0 * (zu - z_e + beta0 * C_LIGHT * t_u)
+        uxp = -K * np.cos(ku * zlab)
+        uzp = np.sqrt(gp * gp - 1.0 - uxp * uxp)
+        uz = gamma0 * (uzp - beta0 * gp)  # boost of the 4-momentum along z
+        gr = np.sqrt(1.0 + uxp * uxp + uz * uz)
+        zu = x[:, 2] - (0.5 * dt - t_u) * C_LIGHT * uz / gr
+    zx = gamma0 * (x[:, 2] - z_e + beta0 * C_LIGHT * 0.5 * dt)
+    u = np.zeros((len(gp), 3))
+    u[:, 0] = uxp
+    u[:, 2] = uz
+    x0 = x[:, 0] - K / (gamma0 * ku * math.sqrt(1.0 + K * K / 2.0)) * np.sin(ku * zx)
+    return u, x0
+
+
 def make_workload(name: str, n, n_particles: int, gamma: float, K: float, lambda_u: float,
                   sigma_delta: float, seed: int, steps: int, *, n_lambda: int = 32,
                   aspect: float = 4.0, courant: float = 0.9, sigma_cells=None,
@@ -105,13 +133,7 @@ def make_workload(name: str, n, n_particles: int, gamma: float, K: float, lambda
         x[:, a] = _truncated_normal(rng, n_particles, cut) * sigma_cells[a] * d[a]
     ku = 2.0 * math.pi / lambda_u
     gp = gamma * (1.0 + sigma_delta * rng.standard_normal(n_particles))
-    zlab = gamma0 * (x[:, 2] - z_e)  # lab undulator coordinate at t = 0
-    uxp = -K * np.cos(ku * zlab)
-    x[:, 0] -= K / (gamma0 * ku * math.sqrt(1.0 + K * K / 2.0)) * np.sin(ku * zlab)
-    uzp = np.sqrt(gp * gp - 1.0 - uxp * uxp)
-    u = np.zeros((n_particles, 3))
-    u[:, 0] = uxp
-    u[:, 2] = gamma0 * (uzp - beta0 * gp)  # boost of the 4-momentum along z
+    u, x[:, 0] = _matched(x, gp, gamma0, beta0, K, ku, z_e, courant * d[2] / C_LIGHT, substeps)
     q = -charge / n_particles
     m = M_E * (charge / Q_E) / n_particles
     kp = int(round(0.893 * n[2]))
@@ -211,24 +233,7 @@ def example1(*, n=(64, 64, 2800), n_particles: int = 131072, steps: int = 17900,
     x[:, 2] = zr + (2.0 * bunching / kb) * np.sin(kb * zr)
     rng = np.random.Generator(np.random.PCG64(seed))
     gp = gamma * (1.0 + sigma_delta * rng.standard_normal(n_particles))
-    # matched start in the leapfrog's time levels: the input positions belong
-    # to t = dt/2 and the momenta to half a particle sub-step before, so the
-    # lab phase of u is taken at that time and at the particle's position then
-    dt = 1.0 * d[2] / C_LIGHT
-    t_u = 0.5 * dt - 0.5 * dt / substeps
-    zu = x[:, 2].copy()
-    for _ in range(8):
-        zlab = gamma0 * (zu - z_e + beta0 * C_LIGHT * t_u)
-        uxp = -K * np.cos(ku * zlab)
-        uzp = np.sqrt(gp * gp - 1.0 - uxp * uxp)
-        uz = gamma0 * (uzp - beta0 * gp)
-        gr = np.sqrt(1.0 + uxp * uxp + uz * uz)
-        zu = x[:, 2] - (0.5 * dt - t_u) * C_LIGHT * uz / gr
-    zx = gamma0 * (x[:, 2] - z_e + beta0 * C_LIGHT * 0.5 * dt)
-    x[:, 0] -= K / (gamma0 * ku * math.sqrt(1.0 + K * K / 2.0)) * np.sin(ku * zx)
-    u = np.zeros((n_particles, 3))
-    u[:, 0] = uxp
-    u[:, 2] = uz
+    u, x[:, 0] = _matched(x, gp, gamma0, beta0, K, ku, z_e, 1.0 * d[2] / C_LIGHT, substeps)
     q = -BUNCH_CHARGE / n_particles
     m = M_E * (BUNCH_CHARGE / Q_E) / n_particles
     kp = min(n[2] // 2 + int(round(gamma0 * 110e-6 / d[2])), n[2] - 3)
