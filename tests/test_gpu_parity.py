@@ -674,6 +674,48 @@ def test_batch_tuned_matches_oracle_f64():
         compare_diag(b.get_diag(s), orc.diag(), TOL64, "batch-f64-%d" % s)
 
 
+def test_batch_config_full_size_f32():
+    """The 64-simulation parameter scan at its full sizes (32x32x128 to
+    96x96x384, 16K-256K particles each), tuned and run as the benchmark runs
+    it, in float with split positions.  Every simulation: charge equal to the
+    live particles' charge, continuity to float round-off, finite values.
+    Three sampled simulations (fewest cells, most cells, the median) against
+    the oracle on the float bar."""
+    steps = 12
+    ws = W.batch_configs(64, steps=steps)
+    say("case full batch", len(ws), "cells", sum(w.ncell for w in ws),
+        "particles", sum(w.np for w in ws))
+    b = native.batch_from_workloads(ws, precision="f32", every=1, spectrum=False)
+    b.tune(2)
+    say("tuned", b.info(0)["stencil_tile"])
+    b.run(steps)
+    b.sync()
+    diag = [b.get_diag(s) for s in range(len(ws))]  # reading marks the rows read
+    for s, w in enumerate(ws):
+        gd = diag[s]
+        assert len(gd) == steps and not gd["nonfinite"].any(), s
+        live = w.np - gd["lost"]
+        assert np.all(np.abs(gd["total_charge"] - live * w.q) <= 1e-6 * abs(w.np * w.q)), s
+        steady = np.concatenate([[gd["lost"][0] == 0], np.diff(gd["lost"]) == 0])
+        assert np.max(gd["continuity_residual"][steady]) < 1e-5, s
+    order = sorted(range(len(ws)), key=lambda i: ws[i].ncell)
+    for s in (order[0], order[len(order) // 2], order[-1]):
+        w = ws[s]
+        say("oracle for simulation", s, w.n, w.np)
+        orc = oracle.from_workload(w)
+        orc.step(steps)
+        gd, od = diag[s], orc.diag()
+        assert np.array_equal(gd["lost"], od[:, 13].astype(np.int64)), s
+        errs = {"probe_Ex": rel_l2(gd["probe_E"][:, 0], od[:, 7]),
+                "power": rel_l2(gd["power"], od[:, 4]),
+                "charge": rel_l2(gd["total_charge"], od[:, 2])}
+        say("simulation", s, errs)
+        assert errs["probe_Ex"] <= 1e-3 and errs["power"] <= 1e-3 and errs["charge"] < 1e-6, errs
+        pos, u, alive = b.get_particles(s)
+        assert np.array_equal(alive, orc.alive), s
+    b.close()
+
+
 def test_checkpoint_resume_is_bitwise():
     w = W.config(0, steps=30)
     sim = native.sim_from_workload(w)
