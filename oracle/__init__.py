@@ -68,6 +68,7 @@ def _load():
                  "orc_rotate"):
         getattr(lib, name).argtypes = [P]
     lib.orc_step.argtypes = [P, L]
+    lib.orc_set_step.argtypes = [P, L]
     lib.orc_diag_row.argtypes = [P, dp]
     lib.orc_array.restype = dp
     lib.orc_array.argtypes = [P, I]
@@ -213,6 +214,10 @@ class OracleSim:
     @property
     def step_count(self):
         return int(self._lib.orc_info(self._h, 1))
+
+    def set_step(self, step):
+        """Step counter of the state loaded by hand (no arithmetic)."""
+        self._lib.orc_set_step(self._h, int(step))
 
     @property
     def lost(self):

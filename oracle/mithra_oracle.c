@@ -1095,6 +1095,10 @@ long orc_info(orc_sim *s, int which)
     }
 }
 
+/* Set the step counter (the time levels the next step uses: potentials at
+   n, particles at n + 1/2).  For checks that load a state taken elsewhere. */
+void orc_set_step(orc_sim *s, long step) { s->step = step; }
+
 /* derived constants: dt, dtb, A, a1, a2, a4, a6, a8, gamma0, beta0, B0, ku,
    mur-z beta0, beta1, mu0, eps0, c, e, me */
 void orc_constants(const orc_sim *s, double *out)

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+import subbox
 from paper_1612_03310_amd import native
 from paper_1612_03310_amd import workloads as W
 
@@ -858,6 +859,59 @@ def test_large_config_f32_properties():
     assert np.max(mesh["continuity_residual"]) < 1e-5
     assert dg["lost"][-1] == 0 and not dg["nonfinite"].any()
     assert np.all(np.isfinite(dg["power"]))
+
+
+def test_large_config_one_step_against_the_oracle_on_a_box():
+    """256x256x2048 with 16.8M particles in float with split positions, tuned
+    as the benchmark runs it: after a few steps, one more step of the whole
+    mesh against one oracle step of a 48x48x64-cell box at the bunch centre
+    (about 360K particles) loaded with the state before it.  Away from the
+    box faces the two compute the same quantities (the box cut is checked on
+    the CPU).  Both sides start from the same float state, so what differs is
+    the rounding of one step's float arithmetic, a few units of 2^-24: the bar
+    is 1e-6 relative L2 (16 units) for every field, the momenta and, in cells,
+    the positions."""
+    w = W.config(3)
+    say("case large box", w.n, w.np)
+    sim = native.sim_from_workload(w, precision="f32", every=100, spectrum=False)
+    sim.tune(3)
+    sim.run(4)
+    sim.sync()
+    step = sim.info()["step"]
+    lo, hi = (104, 104, 992), (152, 152, 1056)
+    sl = subbox.box_slices(lo, hi)
+    names = list(subbox.POT) + [n + "_prev" for n in subbox.POT] + list(subbox.SRC)
+    fields = {n: sim.get_field(n)[sl].copy() for n in names}
+    x0, u0, alive0 = sim.get_particles()
+    assert alive0.all()
+    box, sel = subbox.load_box(w, lo, hi, fields, x0, u0, alive0, step)
+    keep = subbox.compared_particles(w, lo, hi, x0, sel)
+    say("step", step, "loaded", int(sel.sum()), "compared", int(keep.sum()))
+    sim.run(1)
+    sim.sync()
+    box.step(1)
+    assert box.lost == 0
+    errs = {}
+    for c, name in enumerate(subbox.POT):
+        errs[name] = rel_l2(subbox.inner(sim.get_field(name)[sl], subbox.MARGIN_POT),
+                            subbox.inner(box.pot(c, "cur"), subbox.MARGIN_POT))
+    for v, get in (("E", box.E), ("B", box.B)):
+        g = np.stack([subbox.inner(sim.get_field(v + a)[sl], subbox.MARGIN_EB) for a in "xyz"])
+        o = np.stack([subbox.inner(get(c), subbox.MARGIN_EB) for c in range(3)])
+        errs[v] = rel_l2(g, o)
+    g = np.stack([subbox.inner(sim.get_field(n)[sl], subbox.MARGIN_SRC) for n in subbox.SRC[:3]])
+    o = np.stack([subbox.inner(box.J(c), subbox.MARGIN_SRC) for c in range(3)])
+    errs["J"] = rel_l2(g, o)
+    errs["rho"] = rel_l2(subbox.inner(sim.get_field("rho")[sl], subbox.MARGIN_SRC),
+                         subbox.inner(box.rho, subbox.MARGIN_SRC))
+    x1, u1, alive1 = sim.get_particles()
+    assert alive1.all()
+    errs["u"] = rel_l2(u1[sel][keep], box.u[keep])
+    errs["x_cells"] = float(np.max(np.abs(x1[sel][keep] - box.x[keep]) / np.asarray(w.d)))
+    say("large box", errs)
+    bad = {k: v for k, v in errs.items() if not v <= 1e-6}
+    assert not bad, (bad, errs)
+    sim.close()
 
 
 # ---------------------------------------------------------------------------
