@@ -223,7 +223,9 @@ mithra_status mithra_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
    t = (s+1/2) dt - dtb/2 (= s dt with one sub-step); q_macro, m_macro: charge
    [C] (signed) and mass [kg] of one macro-particle.  Particles whose cell is
    outside [2, n-3] on an axis are counted as lost at once.  Deposits
-   rho^{s+1/2}; sets J^s = 0.  EINVAL for np < 0, non-finite input or m <= 0. */
+   rho^{s+1/2}; sets J^s = 0.  EINVAL for np < 0, non-finite input, m <= 0
+   or more than 2^31 - 2^20 particles (32-bit bucket offsets; in a batch the
+   limit holds for all simulations together). */
 mithra_status mithra_set_particles(mithra_sim *sim, int64_t np, const double *pos,
                                    const double *u, double q_macro, double m_macro);
 

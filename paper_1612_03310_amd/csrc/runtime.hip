@@ -724,12 +724,18 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
 // particles
 // ---------------------------------------------------------------------------
 
+// Bucket offsets and particle indices are 32-bit; the margin keeps the index
+// arithmetic of a block running past the last particle inside int range.
+constexpr long long MAX_PARTICLES = (1LL << 31) - (1LL << 20);
+
 static mithra_status stage_particles(HostSim &h, int s, int64_t np, const double *pos,
                                      const double *u, double q, double m)
 {
     if (np < 0) return fail(MITHRA_EINVAL, "sim %d: np < 0", s);
     if (np > 0 && (!pos || !u)) return fail(MITHRA_EINVAL, "sim %d: pos and u must not be NULL", s);
-    if (np >= (1LL << 31) - 1) return fail(MITHRA_EINVAL, "sim %d: too many particles", s);
+    if (np > MAX_PARTICLES)
+        return fail(MITHRA_EINVAL, "sim %d: %lld particles, at most %lld", s, (long long)np,
+                    MAX_PARTICLES);
     if (!std::isfinite(q) || !(m > 0.0) || !std::isfinite(m))
         return fail(MITHRA_EINVAL, "sim %d: q must be finite and m positive", s);
     h.cell.assign(3 * np, 0);
@@ -822,6 +828,10 @@ static mithra_status commit_impl(Batch &b)
     drop_graph(b);
     dev_free_all(b, b.mem_part);
     long long N = 0;
+    for (int s = 0; s < b.nsim; ++s) N += (long long)b.hs[s].alive.size();
+    if (N > MAX_PARTICLES)
+        return fail(MITHRA_EINVAL, "%lld particles in the batch, at most %lld", N, MAX_PARTICLES);
+    N = 0;
     for (int s = 0; s < b.nsim; ++s) {
         SimDev &S = b.sd[s];
         S.part0 = N;
@@ -1805,6 +1815,12 @@ mithra_status mithra_batch_set_particles(mithra_batch *bb, int32_t sim, int64_t 
     if (sim < 0 || sim >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", sim);
     if (b.step > 0)
         return fail(MITHRA_ESTATE, "batch particles can only be loaded before the first step");
+    long long others = 0;
+    for (int s = 0; s < b.nsim; ++s)
+        if (s != sim) others += (long long)b.hs[s].alive.size();
+    if (np > 0 && others + np > MAX_PARTICLES)
+        return fail(MITHRA_EINVAL, "%lld particles in the batch, at most %lld",
+                    others + (long long)np, MAX_PARTICLES);
     mithra_status st = stage_particles(b.hs[sim], sim, np, pos, u, q_macro, m_macro);
     if (st) return st;
     b.committed = false;

@@ -824,6 +824,21 @@ def test_run_before_particles_is_a_state_error():
     assert e.value.status == native.ESTATE
 
 
+def test_particle_count_beyond_32_bit_offsets_is_rejected():
+    """More particles than 32-bit bucket offsets hold are refused before any
+    array is read (the count alone decides; the arrays passed are short)."""
+    sim = native.Sim((16, 16, 16), (4e-6, 4e-6, 1e-6), (0, 0, 0))
+    pos = np.zeros((1, 3))
+    too_many = (1 << 31) - (1 << 20) + 1
+    st = sim._lib.mithra_set_particles(sim._h, too_many, native._dptr(pos), native._dptr(pos),
+                                       -QE, ME)
+    assert st == native.EINVAL
+    assert b"at most" in sim._lib.mithra_last_error()
+    sim.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)  # still usable
+    sim.run(1)
+    sim.sync()
+
+
 def test_overflowing_field_is_reported_as_numeric_error():
     """A potential that overflows the float range makes the momenta non-finite;
     the particle is counted lost and sync reports ENUMERIC."""
