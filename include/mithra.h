@@ -277,11 +277,15 @@ mithra_status mithra_get_diag(mithra_sim *sim, mithra_diag_row *rows, int64_t ca
 
 mithra_status mithra_get_info(mithra_sim *sim, mithra_info *info);
 
-/* Checkpoint: all potentials (3 levels), J, rho (2), particles, step, lost
-   count and the running DFT of the power plane.  blob NULL: *bytes receives
+/* Checkpoint: the potentials at the two levels the next step reads, J, rho
+   (both buffers), particles, step, lost count and the running DFT of the
+   power plane.  blob NULL: *bytes receives
    the size.  EINVAL if *bytes is too small or the blob belongs to another
-   mesh or precision.  Blobs of the earlier layout without the plane spectrum
-   are still accepted (the spectrum then starts from zero). */
+   mesh or precision, and for a corrupt blob (negative step or particle
+   count, a live particle outside the cells [2, n-3], an offset outside
+   [0, 1], non-finite momenta); a refused blob changes nothing.  Blobs of
+   the earlier layout without the plane spectrum are still accepted (the
+   spectrum then starts from zero). */
 mithra_status mithra_get_state(mithra_sim *sim, void *blob, size_t *bytes);
 mithra_status mithra_set_state(mithra_sim *sim, const void *blob, size_t bytes);
 

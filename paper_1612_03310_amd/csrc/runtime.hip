@@ -1566,6 +1566,9 @@ static mithra_status set_state_impl(Batch &b, const void *blob, size_t bytes)
     if (!b.hs[0].loaded)
         return fail(MITHRA_ESTATE, "load particles once (any) before restoring a state: q and m come from that call");
     const long long np = hd.np;
+    if (hd.step < 0 || np < 0 || np > MAX_PARTICLES)
+        return fail(MITHRA_EINVAL, "corrupt state blob (step %lld, %lld particles)",
+                    (long long)hd.step, np);
     const size_t mesh_bytes = (size_t)ncell * sizeof(R);
     // version 1 has no plane spectrum: it starts again from zero
     const size_t spec_bytes =
@@ -1573,14 +1576,26 @@ static mithra_status set_state_impl(Batch &b, const void *blob, size_t bytes)
     const size_t part_bytes = (size_t)np * (1 + 3 * sizeof(int) + 6 * sizeof(R));
     const size_t need = sizeof(StateHeader) + mesh_bytes * 13 + part_bytes + spec_bytes;
     if (bytes < need) return fail(MITHRA_EINVAL, "blob truncated");
-    HIP_TRY(hipStreamSynchronize(b.stream));
-    // particles first (commit re-lays the arenas at the restored step)
-    HostSim &h = b.hs[0];
     const char *r = (const char *)blob + sizeof hd + mesh_bytes * 13;
     const unsigned char *al = (const unsigned char *)r;
     const int *cell = (const int *)(r + np);
     const R *fr = (const R *)(r + np + 3 * sizeof(int) * np);
     const R *mo = fr + 3 * np;
+    // a live particle's cell indexes the bins and the mesh: check every one
+    // before anything changes
+    for (long long i = 0; i < np; ++i) {
+        if (al[i] > 1) return fail(MITHRA_EINVAL, "corrupt state blob (particle %lld)", i);
+        if (!al[i]) continue;
+        for (int a = 0; a < 3; ++a) {
+            const double f = (double)fr[3 * i + a], m = (double)mo[3 * i + a];
+            if (cell[3 * i + a] < 2 || cell[3 * i + a] > S0.n[a] - 3 || !(f >= 0.0 && f <= 1.0) ||
+                !std::isfinite(m))
+                return fail(MITHRA_EINVAL, "corrupt state blob (particle %lld)", i);
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    // particles first (commit re-lays the arenas at the restored step)
+    HostSim &h = b.hs[0];
     h.alive.assign(al, al + np);
     h.cell.assign(cell, cell + 3 * np);
     h.frac.resize(3 * np);

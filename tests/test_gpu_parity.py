@@ -736,6 +736,52 @@ def test_checkpoint_resume_is_bitwise():
     assert sim.get_diag()[10:].tobytes() == sim2.get_diag().tobytes()
 
 
+def test_corrupt_checkpoints_are_rejected_and_change_nothing():
+    """A blob with a negative step or particle count, a live particle outside
+    the safe interior, an offset outside [0, 1] or non-finite momenta, or one
+    cut short, is refused before anything changes: the simulation then runs
+    exactly as one that was never given it."""
+    w = W.config(0, steps=10)
+    src = native.sim_from_workload(w)
+    src.run(3)
+    blob = bytearray(src.get_state())
+    head = 56                               # magic, 6 int32, step, np, ncell
+    ncell, npart = w.ncell, w.np
+    parts = head + 13 * ncell * 8           # after 13 FP64 mesh arrays
+    alive = np.frombuffer(bytes(blob[parts:parts + npart]), dtype=np.uint8)
+    p = int(np.argmax(alive == 1))
+    cell_at = parts + npart + 12 * p        # int32 cell of particle p, x
+    off_at = parts + npart + 12 * npart + 24 * p
+    mom_at = parts + npart + 12 * npart + 24 * npart + 24 * p
+
+    def patched(at, fmt, value):
+        b = bytearray(blob)
+        b[at:at + np.dtype(fmt).itemsize] = np.array([value], dtype=fmt).tobytes()
+        return bytes(b)
+
+    bad = {"negative step": patched(32, np.int64, -1),
+           "negative count": patched(40, np.int64, -5),
+           "cell far outside": patched(cell_at, np.int32, 1 << 20),
+           "cell in the lost margin": patched(cell_at, np.int32, 1),
+           "offset above one": patched(off_at, np.float64, 2.0),
+           "momentum not finite": patched(mom_at, np.float64, np.inf),
+           "cut short": bytes(blob[:-8])}
+    sim = native.sim_from_workload(w)
+    ref = native.sim_from_workload(w)
+    for what, b in bad.items():
+        say("case corrupt blob:", what)
+        with pytest.raises(native.MithraError) as e:
+            sim.set_state(b)
+        assert e.value.status == native.EINVAL, what
+    for s in (sim, ref):
+        s.run(5)
+        s.sync()
+    for f in ("Ax", "phi", "Jz", "rho"):
+        assert np.array_equal(sim.get_field(f), ref.get_field(f)), f
+    assert sim.get_diag().tobytes() == ref.get_diag().tobytes()
+    sim.set_state(bytes(blob))  # the intact blob is still accepted
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
