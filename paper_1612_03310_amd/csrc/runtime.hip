@@ -120,7 +120,13 @@ struct Batch {
     void *(*alloc_fn)(size_t, void *) = nullptr;
     void (*free_fn)(void *, void *) = nullptr;
     void *alloc_ctx = nullptr;
-    std::vector<void *> mem_fixed, mem_part, mem_tab;
+    // device blocks by lifetime: the batch, the particle arrays, the launch
+    // tables, the diagnostic ring (re-laid when a ring capacity changes)
+    struct Block {
+        void *p;
+        size_t bytes;
+    };
+    std::vector<Block> mem_fixed, mem_part, mem_tab, mem_ring;
     size_t bytes = 0;
 };
 
@@ -128,7 +134,7 @@ struct Batch {
 // memory
 // ---------------------------------------------------------------------------
 
-static void *dev_alloc(Batch &b, size_t bytes, std::vector<void *> &owner)
+static void *dev_alloc(Batch &b, size_t bytes, std::vector<Batch::Block> &owner)
 {
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~(size_t)255;
@@ -139,17 +145,18 @@ static void *dev_alloc(Batch &b, size_t bytes, std::vector<void *> &owner)
         p = nullptr;
     }
     if (p) {
-        owner.push_back(p);
+        owner.push_back({p, bytes});
         b.bytes += bytes;
     }
     return p;
 }
 
-static void dev_free_all(Batch &b, std::vector<void *> &owner)
+static void dev_free_all(Batch &b, std::vector<Batch::Block> &owner)
 {
-    for (void *p : owner) {
-        if (b.free_fn) b.free_fn(p, b.alloc_ctx);
-        else (void)hipFree(p);
+    for (const Batch::Block &m : owner) {
+        if (b.free_fn) b.free_fn(m.p, b.alloc_ctx);
+        else (void)hipFree(m.p);
+        b.bytes -= m.bytes;
     }
     owner.clear();
 }
@@ -186,6 +193,7 @@ static void destroy_batch(Batch *b)
     }
     dev_free_all(*b, b->mem_tab);
     dev_free_all(*b, b->mem_part);
+    dev_free_all(*b, b->mem_ring);
     dev_free_all(*b, b->mem_fixed);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -683,7 +691,8 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     for (int r = 0; r < 2; ++r) ok &= (b->ar.rho[r] = A(mb)) != nullptr;
     ok &= (b->ar.counts = (int *)A(sizeof(int) * keys)) != nullptr;
     for (int r = 0; r < 2; ++r) ok &= (b->ar.offs[r] = (int *)A(sizeof(int) * (keys + 1))) != nullptr;
-    ok &= (b->ar.ring = (double *)A(sizeof(double) * NDIAG * ring)) != nullptr;
+    ok &= (b->ar.ring = (double *)dev_alloc(*b, sizeof(double) * NDIAG * ring, b->mem_ring)) !=
+          nullptr;
     ok &= (b->ar.spec = (double *)A(sizeof(double) * plate)) != nullptr;
     ok &= (b->ar.flags = (int *)A(sizeof(int) * nsim)) != nullptr;
     ok &= (b->ar.d_step = (long long *)A(sizeof(long long))) != nullptr;
@@ -1259,23 +1268,30 @@ static mithra_status config_diag(Batch &b, int s, const mithra_diag_cfg *cfg)
     if (cfg->power_spectrum != h.diag.power_spectrum && b.step > 0)
         return fail(MITHRA_ESTATE, "the power spectrum can only be switched before the first step");
     HIP_TRY(hipStreamSynchronize(b.stream));
-    const int old_cap = h.diag.capacity;
-    h.diag = *cfg;
-    if (cfg->capacity != old_cap) {
-        // re-lay the ring arena
+    if (cfg->capacity != h.diag.capacity) {
+        // re-lay the ring arena (no rows exist before the first step); the
+        // new ring is in place before anything else changes
         long long ring = 0;
+        for (int i = 0; i < b.nsim; ++i) ring += i == s ? cfg->capacity : b.hs[i].diag.capacity;
+        std::vector<Batch::Block> fresh;
+        double *nr = (double *)dev_alloc(b, sizeof(double) * NDIAG * ring, fresh);
+        if (!nr) return fail(MITHRA_ENOMEM, "device allocation of the diagnostic ring failed");
+        if (hipMemset(nr, 0, sizeof(double) * NDIAG * ring) != hipSuccess) {
+            dev_free_all(b, fresh);
+            return fail(MITHRA_EDEVICE, "clearing the diagnostic ring failed");
+        }
+        drop_graph(b);
+        dev_free_all(b, b.mem_ring);
+        b.mem_ring = fresh;
+        b.ar.ring = nr;
+        ring = 0;
         for (int i = 0; i < b.nsim; ++i) {
             b.sd[i].ring0 = ring;
-            b.sd[i].ring_cap = b.hs[i].diag.capacity;
+            b.sd[i].ring_cap = i == s ? cfg->capacity : b.hs[i].diag.capacity;
             ring += b.sd[i].ring_cap;
         }
-        void *old = b.ar.ring;
-        b.ar.ring = (double *)dev_alloc(b, sizeof(double) * NDIAG * ring, b.mem_fixed);
-        if (!b.ar.ring) return fail(MITHRA_ENOMEM, "device allocation of the diagnostic ring failed");
-        HIP_TRY(hipMemset(b.ar.ring, 0, sizeof(double) * NDIAG * ring));
-        // the old ring stays allocated until destroy (kept in mem_fixed)
-        (void)old;
     }
+    h.diag = *cfg;
     SimDev &S = b.sd[s];
     S.probe[0] = cfg->probe[0];
     S.probe[1] = cfg->probe[1];
@@ -1388,7 +1404,7 @@ static mithra_status tune_impl(Batch &b, int trials)
     };
     std::vector<Cand> cands;
     std::vector<int4> items;
-    std::vector<void *> scratch;
+    std::vector<Batch::Block> scratch;
     for (auto &sh : shapes) {
         if (sh[0] > 2 * maxn[0] && sh[0] > 16) continue;
         for (int kz : kzs) {
@@ -1429,10 +1445,7 @@ static mithra_status tune_impl(Batch &b, int trials)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_TRY(hipStreamSynchronize(b.stream));
-    for (void *p : scratch) {
-        if (b.free_fn) b.free_fn(p, b.alloc_ctx);
-        else (void)hipFree(p);
-    }
+    dev_free_all(b, scratch);
     b.tile_x = bx;
     b.tile_y = by;
     b.kz = bk;

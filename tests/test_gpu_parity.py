@@ -870,6 +870,31 @@ def test_run_before_particles_is_a_state_error():
     assert e.value.status == native.ESTATE
 
 
+def test_device_bytes_follow_reallocations():
+    """device_bytes is what the simulation holds: a re-laid diagnostic ring
+    replaces the old one, and re-loading particles leaves no blocks behind."""
+    w = W.config(0, steps=4)
+    sim = native.sim_from_workload(w)  # ring of 4096 rows of 24 doubles
+    b0 = sim.info()["device_bytes"]
+    sim.config_diag(w.probe, w.kp, capacity=100)
+    b1 = sim.info()["device_bytes"]
+    assert b0 - b1 == 4096 * 24 * 8 - 100 * 24 * 8
+    sim.config_diag(w.probe, w.kp, capacity=4096)
+    assert sim.info()["device_bytes"] == b0
+    sim.set_particles(w.x, w.u, w.q, w.m)
+    assert sim.info()["device_bytes"] == b0
+    sim.run(1)
+    sim.sync()
+    b2 = sim.info()["device_bytes"]
+    with pytest.raises(native.MithraError) as e:  # fixed once stepping began
+        sim.config_diag(w.probe, w.kp, capacity=100)
+    assert e.value.status == native.ESTATE
+    assert sim.info()["device_bytes"] == b2
+    sim.run(3)
+    sim.sync()
+    assert len(sim.get_diag()) == 4
+
+
 def test_particle_count_beyond_32_bit_offsets_is_rejected():
     """More particles than 32-bit bucket offsets hold are refused before any
     array is read (the count alone decides; the arrays passed are short)."""
