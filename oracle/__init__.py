@@ -61,6 +61,7 @@ def _load():
     lib.orc_set_background.argtypes = [P, dp]
     lib.orc_set_seed.argtypes = [P, I, D, D, D, D, D, D, D, I, D]
     lib.orc_set_optical.argtypes = [P, I, D, D, D, D, D, D, D, I, D]
+    lib.orc_set_optical_beam.argtypes = [P, I, D, D, D, D, D]
     lib.orc_seed_signal.argtypes = [P, D]
     lib.orc_seed_signal.restype = D
     lib.orc_config_diag.argtypes = [P, I, I, I, I]
@@ -157,6 +158,14 @@ class OracleSim:
                                   float(polarization[1]), float(frequency), float(t0),
                                   float(tau), float(cep), int(self.SIGNALS[signal]),
                                   float(z_ref))
+
+    def set_optical_beam(self, beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)):
+        """Beam of the optical undulator: "plane" or "gaussian" with the
+        Rayleigh lengths along the polarization and across it [m] and the
+        focus (rest frame)."""
+        self._lib.orc_set_optical_beam(self._h, {"plane": 0, "gaussian": 1}[beam],
+                                       float(rayleigh[0]), float(rayleigh[1]), float(focus[0]),
+                                       float(focus[1]), float(focus[2]))
 
     def config_diag(self, probe, kp):
         self._lib.orc_config_diag(self._h, int(probe[0]), int(probe[1]), int(probe[2]), int(kp))

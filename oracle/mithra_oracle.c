@@ -65,9 +65,19 @@
  *   R24 optical undulator (section "UNDULATOR"): a plane wave towards -z,
  *       A_perp = a p s(t + (z - z_ref)/c) in the rest frame with the seed's
  *       signal shapes, in place of the static undulator's field on the
- *       particles.
+ *       particles;
+ *   R25 its Gaussian-beam type: the same wave with the paraxial envelope of
+ *       an astigmatic Gaussian beam focused at r_f, Rayleigh lengths z_par
+ *       (along p) and z_perp (along z x p), carrier wave number k = 2 pi f/c:
+ *       A_perp = a p Re{U S(t + (z - z_ref)/c)}, S the analytic signal of s
+ *       (envelope times exp(i(w x + cep))), U = u(xi, z_par) u(eta, z_perp),
+ *       u(v, zr) = sqrt(i zr / q) exp(-i k v^2 / (2 q)), q = zeta + i zr,
+ *       zeta = z_f - z; fields E = -dA/dt, B = curl A (no scalar potential).
  */
+#include <complex.h>
 #include <math.h>
+#undef I /* loops use I, J, K as vertex indices; the imaginary unit is ORC_J */
+#define ORC_J _Complex_I
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -95,6 +105,10 @@ typedef struct orc_sim {
        static undulator, same signal shapes as the seed */
     int opt_on, opt_sig;
     double opt_a, opt_p[2], opt_f, opt_t0, opt_tau, opt_cep, opt_zref;
+    /* its beam (reading R25): 0 plane wave, 1 Gaussian beam with Rayleigh
+       lengths along p and along z x p, focused at opt_focus */
+    int opt_beam;
+    double opt_zr[2], opt_focus[3];
     double lambda_u, K, gamma_beam, z_e;
     /* derived constants */
     double dt, dtb, a1, a2, a4, a6, a8;
@@ -758,6 +772,69 @@ static double signal_rate(int sig, double a, double f, double t0, double tau, do
     }
 }
 
+/* The shapes as analytic signals: S = a e(x) exp(i(w x + cep)) with the
+   envelope e of each shape, and dS/dt = a (e' + i w e) exp(i(w x + cep)).
+   Their real parts are the signal and signal_rate. */
+static double complex analytic_signal(int sig, double a, double f, double t0, double tau,
+                                      double cep, double t, double complex *rate)
+{
+    double x = t - t0, ln2 = log(2.0), w = 2.0 * ORC_PI * f;
+    double g = exp(-2.0 * ln2 * x * x / (tau * tau));
+    double g1 = -4.0 * ln2 * x / (tau * tau) * g;
+    double g2 = -4.0 * ln2 / (tau * tau) * (g + x * g1);
+    double e, e1;
+    switch (sig) {
+    case 0: e = g1; e1 = g2; break;
+    case 1: e = g; e1 = g1; break;
+    case 2: e = 1.0 / cosh(x / tau); e1 = -e * tanh(x / tau) / tau; break;
+    default: e = x <= 0.0 ? g : 1.0; e1 = x <= 0.0 ? g1 : 0.0; break;
+    }
+    double complex carrier = cexp(ORC_J * (w * x + cep));
+    *rate = a * (e1 + ORC_J * w * e) * carrier;
+    return a * e * carrier;
+}
+
+/* Gaussian-beam optical undulator (reading R25): E = -p dpsi/dt,
+   B = grad psi x p = (-p_y dpsi/dz, p_x dpsi/dz, -dpsi/deta) with
+   psi = Re{U S}; d/dz = (1/c) d/dt - d/dzeta. */
+static void gaussian_beam_field(const orc_sim *s, double x, double y, double z, double t,
+                                double *E, double *B)
+{
+    double k = 2.0 * ORC_PI * s->opt_f / ORC_C;
+    double px = s->opt_p[0], py = s->opt_p[1];
+    double X = x - s->opt_focus[0], Y = y - s->opt_focus[1], zeta = s->opt_focus[2] - z;
+    double xi = X * px + Y * py, eta = -X * py + Y * px;
+    double complex q1 = zeta + ORC_J * s->opt_zr[0], q2 = zeta + ORC_J * s->opt_zr[1];
+    double complex U = csqrt(ORC_J * s->opt_zr[0] / q1) * csqrt(ORC_J * s->opt_zr[1] / q2) *
+                       cexp(-ORC_J * k * xi * xi / (2.0 * q1) - ORC_J * k * eta * eta / (2.0 * q2));
+    double complex dU_deta = U * (-ORC_J * k * eta / q2);
+    double complex dU_dzeta = U * (-1.0 / (2.0 * q1) + ORC_J * k * xi * xi / (2.0 * q1 * q1) -
+                                   1.0 / (2.0 * q2) + ORC_J * k * eta * eta / (2.0 * q2 * q2));
+    double complex rate;
+    double complex S = analytic_signal(s->opt_sig, s->opt_a, s->opt_f, s->opt_t0, s->opt_tau,
+                                       s->opt_cep, t + (z - s->opt_zref) / ORC_C, &rate);
+    double dpsi_dt = creal(U * rate);
+    double dpsi_dz = dpsi_dt / ORC_C - creal(dU_dzeta * S);
+    double dpsi_deta = creal(dU_deta * S);
+    E[0] = -px * dpsi_dt;
+    E[1] = -py * dpsi_dt;
+    E[2] = 0.0;
+    B[0] = -py * dpsi_dz;
+    B[1] = px * dpsi_dz;
+    B[2] = -dpsi_deta;
+}
+
+void orc_set_optical_beam(orc_sim *s, int beam, double zr_par, double zr_perp, double xf,
+                          double yf, double zf)
+{
+    s->opt_beam = beam;
+    s->opt_zr[0] = zr_par;
+    s->opt_zr[1] = zr_perp;
+    s->opt_focus[0] = xf;
+    s->opt_focus[1] = yf;
+    s->opt_focus[2] = zf;
+}
+
 void orc_set_optical(orc_sim *s, int on, double a, double px, double py, double freq, double t0,
                      double tau, double cep, int signal, double z_ref)
 {
@@ -779,7 +856,10 @@ void orc_set_optical(orc_sim *s, int on, double a, double px, double py, double 
 void orc_undulator(const orc_sim *s, double x, double y, double z, double t, double *E,
                    double *B)
 {
-    (void)x;
+    if (s->opt_on && s->opt_beam == 1) {
+        gaussian_beam_field(s, x, y, z, t, E, B);
+        return;
+    }
     if (s->opt_on) {
         double ds = signal_rate(s->opt_sig, s->opt_a, s->opt_f, s->opt_t0, s->opt_tau, s->opt_cep,
                                 t + (z - s->opt_zref) / ORC_C);

@@ -1156,3 +1156,135 @@ def test_rest_frame_matches_printed_radiation_wavelengths(row):
     g0, b0 = sim.const["gamma0"], sim.const["beta0"]
     lam = float(lam_u) / (g0 * g0 * b0 * (1.0 + b0))
     assert abs(lam / float(lam_printed) - 1.0) < float(tol)
+
+
+# ---- Gaussian-beam optical undulator (reading R25) ---------------------------
+
+LAM_G = 1e-6                      # carrier wavelength
+F_G = C / LAM_G
+K_G = 2 * np.pi / LAM_G
+ZR_G = 1000.0 / K_G               # k z_R = 1000: paraxial terms of order 1e-6
+FOCUS_G = (1e-6, -2e-6, 5e-6)
+POL_G = (0.6, 0.8)
+
+
+def _gauss_sim(zr=(ZR_G, 0.5 * ZR_G), signal="gaussian", cep=0.3, beam="gaussian"):
+    n = (8, 8, 8)
+    d, origin = _mesh(n)
+    sim = oracle.OracleSim(n, d, origin)
+    tau = 20 * LAM_G / C
+    sim.set_optical_undulator(2e-6, polarization=POL_G, frequency=F_G, t0=3 * tau, tau=tau,
+                              cep=cep, signal=signal, z_ref=0.0)
+    sim.set_optical_beam(beam, rayleigh=zr, focus=FOCUS_G)
+    return sim, tau
+
+
+def _at(xi, eta, zeta):
+    """Rest-frame point at (xi along p, eta along z x p) from the axis, zeta
+    past the focus (towards -z)."""
+    px, py = POL_G
+    return (FOCUS_G[0] + xi * px - eta * py, FOCUS_G[1] + xi * py + eta * px, FOCUS_G[2] - zeta)
+
+
+def test_gaussian_beam_reduces_to_the_plane_wave_for_long_rayleigh_lengths():
+    for sig in ("neumann", "gaussian", "secant", "flat-top"):
+        g, tau = _gauss_sim(zr=(1e9, 1e9), signal=sig)
+        p, _ = _gauss_sim(signal=sig, beam="plane")
+        for t in (2.0 * tau, 2.9 * tau, 3.3 * tau):
+            for pt in (_at(3e-6, -2e-6, 0.0), _at(-5e-6, 4e-6, 20e-6)):
+                Eg, Bg = g.undulator(*pt, t)
+                Ep, Bp = p.undulator(*pt, t)
+                assert np.abs(Eg - Ep).max() <= 1e-9 * np.abs(Ep).max(), sig
+                assert np.abs(Bg - Bp).max() <= 1e-9 * np.abs(Bp).max(), sig
+
+
+def test_gaussian_beam_waists_at_the_focus():
+    """At the focus the profile is exp(-xi^2/w_par^2 - eta^2/w_perp^2) with
+    w^2 = 2 z_R / k along each axis, and the phase is flat."""
+    zr = (ZR_G, 0.5 * ZR_G)
+    g, tau = _gauss_sim(zr=zr, signal="flat-top")
+    w = [np.sqrt(2 * z / K_G) for z in zr]
+    t = 3 * tau + 0.13 * LAM_G / C     # bare carrier, away from its zeros
+    E0, _ = g.undulator(*_at(0, 0, 0), t)
+    for xi, eta in ((w[0], 0.0), (0.0, w[1]), (0.7 * w[0], -1.3 * w[1])):
+        E, _ = g.undulator(*_at(xi, eta, 0.0), t)
+        want = np.exp(-(xi / w[0]) ** 2 - (eta / w[1]) ** 2)
+        assert abs(E[0] / E0[0] - want) < 1e-12, (xi, eta)
+
+
+def test_gaussian_beam_gouy_phase_on_axis():
+    """One Rayleigh length past the focus the on-axis field is the plane wave
+    advanced by pi/8 per axis (the Gouy phase) with amplitude 2^(-1/4) per
+    axis: pi/4 and 1/sqrt(2) for a round beam, pi/8 and 2^(-1/4) when the
+    other axis is collimated."""
+    for zr, phase, amp in (((ZR_G, ZR_G), np.pi / 4, 2 ** -0.5),
+                           ((ZR_G, 1e12), np.pi / 8, 2 ** -0.25)):
+        g, tau = _gauss_sim(zr=zr, signal="flat-top", cep=0.3)
+        p, _ = _gauss_sim(signal="flat-top", cep=0.3 + phase, beam="plane")
+        for dt in (0.0, 0.21, 0.55):
+            t = 3 * tau + 2 * ZR_G / C + dt * LAM_G / C
+            pt = _at(0.0, 0.0, ZR_G)
+            Eg, _ = g.undulator(*pt, t)
+            Ep, _ = p.undulator(*pt, t)
+            assert np.allclose(Eg[:2], amp * Ep[:2], rtol=0, atol=1e-12 * np.abs(Ep).max()), zr
+
+
+def _d1(f, h):
+    """Fourth-order central first derivative of f at 0."""
+    return (-f(2 * h) + 8 * f(h) - 8 * f(-h) + f(-2 * h)) / (12 * h)
+
+
+def _d2(f, h):
+    """Fourth-order central second derivative of f at 0."""
+    return (-f(2 * h) + 16 * f(h) - 30 * f(0.0) + 16 * f(-h) - f(-2 * h)) / (12 * h * h)
+
+
+def test_gaussian_beam_fields_obey_faraday_and_gauss_for_b():
+    """E = -dA/dt and B = curl A: dB/dt = -curl E and div B = 0, checked by
+    finite differences (fourth order, step lambda/100) inside the pulse."""
+    g, tau = _gauss_sim()
+    h = LAM_G / 100
+    for pt, t in ((_at(2e-6, -3e-6, 0.3 * ZR_G), 3 * tau + 2e-15),
+                  (_at(-4e-6, 1e-6, -0.8 * ZR_G), 2.6 * tau),
+                  (_at(1e-6, 5e-6, 1.5 * ZR_G), 3.4 * tau)):
+        x, y, z = pt
+
+        def E(dx=0, dy=0, dz=0, dt=0):
+            return g.undulator(x + dx, y + dy, z + dz, t + dt)[0]
+
+        def B(dx=0, dy=0, dz=0, dt=0):
+            return g.undulator(x + dx, y + dy, z + dz, t + dt)[1]
+
+        dBdt = _d1(lambda s: B(dt=s / C), h) * C
+        dEdx = _d1(lambda s: E(dx=s), h)
+        dEdy = _d1(lambda s: E(dy=s), h)
+        dEdz = _d1(lambda s: E(dz=s), h)
+        curlE = np.array([dEdy[2] - dEdz[1], dEdz[0] - dEdx[2], dEdx[1] - dEdy[0]])
+        scale = np.abs(dBdt).max()
+        assert np.abs(dBdt + curlE).max() < 1e-6 * scale, (pt, dBdt, curlE)
+        divB = _d1(lambda s: B(dx=s), h)[0] + _d1(lambda s: B(dy=s), h)[1] + \
+            _d1(lambda s: B(dz=s), h)[2]
+        assert abs(divB) < 1e-6 * K_G * np.abs(B()).max()
+
+
+@pytest.mark.parametrize("signal,x_env,bound", [("flat-top", 2.0, 1e-5), ("gaussian", 0.3, 1e-4)])
+def test_gaussian_beam_is_a_vacuum_wave_to_paraxial_order(signal, x_env, bound):
+    """The envelope solves the paraxial equation in the convention of the
+    carrier: on the bare carrier the wave operator on E leaves a residual of
+    order 1/(k z_R)^2 = 1e-6 of k^2 |E|; inside a pulse (0.3 tau after its
+    peak) the envelope's rate adds 2 |e'/e| / (c k^2 z_R), about 1.3e-5.
+    The opposite phase convention would leave 4/(k z_R) = 4e-3."""
+    g, tau = _gauss_sim(signal=signal)
+    h = LAM_G / 50
+    for pt in (_at(3e-6, -2e-6, 0.4 * ZR_G), _at(-2e-6, 4e-6, -0.9 * ZR_G)):
+        x, y, z = pt
+        t = 3 * tau + x_env * tau - z / C   # the pulse variable t + z/c - t0 is x_env tau
+
+        def Ex(dx=0.0, dy=0.0, dz=0.0, dt=0.0):
+            return g.undulator(x + dx, y + dy, z + dz, t + dt)[0][0]
+
+        lap = _d2(lambda s: Ex(dx=s), h) + _d2(lambda s: Ex(dy=s), h) + \
+            _d2(lambda s: Ex(dz=s), h)
+        tt = _d2(lambda s: Ex(dt=s / C), h)
+        peak = max(abs(Ex(dt=s * LAM_G / C / 8)) for s in range(8))
+        assert abs(lap - tt) < bound * K_G ** 2 * peak, (lap, tt, K_G ** 2 * peak)
