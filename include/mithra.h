@@ -250,6 +250,31 @@ mithra_status mithra_set_seed(mithra_sim *sim, const mithra_seed *seed);
    tau <= 0, f < 0 or an unknown signal. */
 mithra_status mithra_set_optical_undulator(mithra_sim *sim, const mithra_seed *wave);
 
+/* Beam of the optical undulator (section "UNDULATOR": beam types plane wave
+   and Gaussian beam, Rayleigh radii parallel and perpendicular to the
+   polarization, position = focus).  The paper gives no field; the library's
+   reading: the wave above times the paraxial envelope of an astigmatic
+   Gaussian beam, A_perp = amplitude * p * Re{U S(t + (z - z_ref)/c)} with S
+   the analytic signal (envelope times exp(i(2 pi f x + cep))),
+   U = u(xi, z_par) u(eta, z_perp), u(v, z_R) = sqrt(i z_R / q)
+   exp(-i k v^2 / (2 q)), q = (z_f - z) + i z_R, k = 2 pi f / c, xi and eta
+   the distances from the axis along p and along z x p; E = -dA/dt,
+   B = curl A (no scalar potential; Gauss's and Ampere's laws then hold to
+   the paraxial order 1/(k z_R)).  Waist radius sqrt(2 z_R / k) at the
+   focus.  Type 0 is the plane wave (default).  Kept when the wave itself
+   changes; acts from the next step.  EINVAL for an unknown type, Rayleigh
+   lengths that are not finite and positive, or a focus that is not finite. */
+typedef enum { MITHRA_BEAM_PLANE = 0, MITHRA_BEAM_GAUSSIAN = 1 } mithra_beam_type;
+
+typedef struct {
+    int32_t type;          /* mithra_beam_type */
+    int32_t pad;
+    double rayleigh[2];    /* Rayleigh lengths along p and along z x p [m] (Gaussian) */
+    double focus[3];       /* focus, rest frame [m] (Gaussian) */
+} mithra_beam;
+
+mithra_status mithra_set_optical_beam(mithra_sim *sim, const mithra_beam *beam);
+
 /* Enqueue nsteps steps on the simulation's stream (asynchronous).  ESTATE if
    no particles were loaded (np = 0 is a valid load). */
 mithra_status mithra_run(mithra_sim *sim, int64_t nsteps);
@@ -319,6 +344,7 @@ mithra_status mithra_batch_config_diag(mithra_batch *b, int32_t sim, const mithr
 mithra_status mithra_batch_set_seed(mithra_batch *b, int32_t sim, const mithra_seed *seed);
 mithra_status mithra_batch_set_optical_undulator(mithra_batch *b, int32_t sim,
                                                  const mithra_seed *wave);
+mithra_status mithra_batch_set_optical_beam(mithra_batch *b, int32_t sim, const mithra_beam *beam);
 /* Autotuner of the batch (see mithra_tune): one tile shape for all
    simulations, chosen by timing the whole batched launch. */
 mithra_status mithra_batch_tune(mithra_batch *b, int32_t trial_steps);

@@ -92,6 +92,70 @@ __device__ double optical_rate(const SimDev &S, double t)
     }
 }
 
+// Envelope e and its rate e' of the optical undulator's signal at x = t - t0
+// (the signal is a e(x) cos(w x + cep)).
+__device__ void optical_envelope(const SimDev &S, double x, double *e, double *e1)
+{
+    const double ln2 = 0.69314718055994530942, it2 = 1.0 / (S.opt_tau * S.opt_tau);
+    const double g = exp(-2.0 * ln2 * x * x * it2);
+    const double dg = -4.0 * ln2 * x * it2 * g;
+    switch (S.opt_sig) {
+    case 0: *e = dg; *e1 = -4.0 * ln2 * it2 * (g + x * dg); break;
+    case 1: *e = g; *e1 = dg; break;
+    case 2: {
+        const double q = x / S.opt_tau, sech = 1.0 / cosh(q);
+        *e = sech;
+        *e1 = -sech * tanh(q) / S.opt_tau;
+        break;
+    }
+    default: *e = x <= 0.0 ? g : 1.0; *e1 = x <= 0.0 ? dg : 0.0; break;
+    }
+}
+
+// Gaussian-beam optical undulator at (x, y, z, t): the plane wave's potential
+// a p e(x) cos(phase) times the paraxial envelope U = |U| exp(i theta) of an
+// astigmatic Gaussian beam travelling towards -z (per axis v = xi along p or
+// eta along z x p with Rayleigh length zr, zeta = z_f - z, m = zeta^2 + zr^2:
+// |u| = (zr^2/m)^(1/4) exp(-k v^2 zr / (2m)), arg u = atan(zeta/zr)/2
+// - k v^2 zeta / (2m)).  With psi = a |U| e cos(Theta), Theta = w x + cep +
+// theta: E = -p dpsi/dt, B = (-p_y, p_x) dpsi/dz and B_z = -dpsi/deta, where
+// the z and eta derivatives of U are U (alpha + i beta) with the real and
+// imaginary parts written out below.
+__device__ void optical_gaussian_beam(const SimDev &S, double t, double x, double y, double z,
+                                      double *E, double *B)
+{
+    const double px = S.opt_p[0], py = S.opt_p[1], k = S.opt_k;
+    const double X = x - S.opt_focus[0], Y = y - S.opt_focus[1], zeta = S.opt_focus[2] - z;
+    const double v[2] = {X * px + Y * py, -X * py + Y * px};
+    double amp = 1.0, theta = 0.0, a_z = 0.0, b_z = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const double zr = S.opt_zr[a], m = zeta * zeta + zr * zr, im = 1.0 / m;
+        const double kv2 = k * v[a] * v[a];
+        amp *= sqrt(zr * sqrt(im)) * exp(-0.5 * kv2 * zr * im);
+        theta += 0.5 * atan2(zeta, zr) - 0.5 * kv2 * zeta * im;
+        a_z += -0.5 * zeta * im + kv2 * zeta * zr * im * im;
+        b_z += 0.5 * zr * im + 0.5 * kv2 * (zeta * zeta - zr * zr) * im * im;
+    }
+    const double zr1 = S.opt_zr[1], im1 = 1.0 / (zeta * zeta + zr1 * zr1);
+    const double a_eta = -k * v[1] * zr1 * im1, b_eta = -k * v[1] * zeta * im1;
+    const double xs = t + (z - S.opt_zref) / C_LIGHT_D - S.opt_t0;
+    const double w = 2.0 * 3.14159265358979323846 * S.opt_f;
+    double e, e1, sn, cs;
+    optical_envelope(S, xs, &e, &e1);
+    sincos(w * xs + S.opt_cep + theta, &sn, &cs);
+    const double aU = S.opt_a * amp;
+    const double re = aU * e * cs, imv = aU * e * sn;   // a Re{U S}, a Im{U S}
+    const double dt_psi = aU * (e1 * cs - w * e * sn);  // a Re{U S'}
+    const double dz_psi = dt_psi / C_LIGHT_D - (a_z * re - b_z * imv);
+    const double deta_psi = a_eta * re - b_eta * imv;
+    E[0] = -px * dt_psi;
+    E[1] = -py * dt_psi;
+    B[0] = -py * dz_psi;
+    B[1] = px * dz_psi;
+    B[2] = -deta_psi;
+}
+
 __device__ __forceinline__ int comp_extent(const SimDev &S, int c, int a)
 {
     return (c == a && !S.bc[a]) ? S.n[a] - 1 : S.n[a];
@@ -1029,7 +1093,17 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
                 const double ts = t0 + sub * S.dtb;
                 const double y = S.origin[1] + ((double)c[1] + (double)f[1]) * S.d[1];
                 R Eu, Buy, Buz, Euy = 0, Bux = 0;
-                if (OPTICAL && S.opt_on) {
+                if (OPTICAL && S.opt_on && S.opt_beam == 1) {
+                    const double x = S.origin[0] + ((double)c[0] + (double)f[0]) * S.d[0];
+                    const double z = S.origin[2] + ((double)c[2] + (double)f[2]) * S.d[2];
+                    double E[2], B[3];
+                    optical_gaussian_beam(S, ts, x, y, z, E, B);
+                    Eu = (R)(S.kE * E[0]);
+                    Euy = (R)(S.kE * E[1]);
+                    Bux = (R)(S.kB * B[0]);
+                    Buy = (R)(S.kB * B[1]);
+                    Buz = (R)(S.kB * B[2]);
+                } else if (OPTICAL && S.opt_on) {
                     // optical undulator: E = -a p s', B = (-a p_y s', a p_x s') / c
                     const double z = S.origin[2] + ((double)c[2] + (double)f[2]) * S.d[2];
                     const double ds = optical_rate(S, ts + (z - S.opt_zref) / C_LIGHT_D);

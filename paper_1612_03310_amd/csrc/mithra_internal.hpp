@@ -84,6 +84,10 @@ struct SimDev {
     // in place of the static undulator (same signal shapes as the seed)
     int opt_on, opt_sig;
     double opt_a, opt_p[2], opt_f, opt_t0, opt_tau, opt_cep, opt_zref;
+    // its beam: 0 plane wave, 1 Gaussian beam (Rayleigh lengths along p and
+    // along z x p, focus, carrier wave number 2 pi f / c)
+    int opt_beam;
+    double opt_zr[2], opt_focus[3], opt_k;
 };
 
 // Device buffers of a batch (one arena per quantity, simulations concatenated).

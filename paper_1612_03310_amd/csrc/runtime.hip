@@ -56,6 +56,7 @@ struct HostSim {
     mithra_diag_cfg diag;
     mithra_seed seed{};  // amplitude 0: none
     mithra_seed optical{};  // optical undulator (wave towards -z); amplitude 0: static undulator
+    mithra_beam beam{};     // its beam (type 0: plane wave)
     double dt, dtb, A, gamma0, beta0, B0, ku;
     bool loaded = false;
     double q = 0.0, m = 0.0;
@@ -305,6 +306,11 @@ static void fill_optical(const HostSim &h, SimDev &S)
     S.opt_tau = h.optical.tau > 0.0 ? h.optical.tau : 1.0;
     S.opt_cep = h.optical.cep;
     S.opt_zref = h.optical.z_ref;
+    S.opt_beam = h.beam.type;
+    S.opt_zr[0] = h.beam.rayleigh[0];
+    S.opt_zr[1] = h.beam.rayleigh[1];
+    for (int a = 0; a < 3; ++a) S.opt_focus[a] = h.beam.focus[a];
+    S.opt_k = 2.0 * PI * h.optical.frequency / C_LIGHT;
 }
 
 // fill the per-simulation constants (offsets are set by the layout)
@@ -1359,6 +1365,29 @@ static mithra_status set_optical(Batch &b, int s, const mithra_seed *wave)
     return MITHRA_OK;
 }
 
+static mithra_status set_optical_beam(Batch &b, int s, const mithra_beam *beam)
+{
+    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
+    if (!beam) return fail(MITHRA_EINVAL, "beam is NULL");
+    if (beam->type != MITHRA_BEAM_PLANE && beam->type != MITHRA_BEAM_GAUSSIAN)
+        return fail(MITHRA_EINVAL, "optical beam: unknown type %d", beam->type);
+    if (beam->type == MITHRA_BEAM_GAUSSIAN) {
+        for (int a = 0; a < 2; ++a)
+            if (!std::isfinite(beam->rayleigh[a]) || !(beam->rayleigh[a] > 0.0))
+                return fail(MITHRA_EINVAL, "optical beam: Rayleigh lengths must be finite and > 0");
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(beam->focus[a]))
+                return fail(MITHRA_EINVAL, "optical beam: the focus must be finite");
+    }
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    HostSim &h = b.hs[s];
+    h.beam = *beam;
+    fill_optical(h, b.sd[s]);
+    HIP_TRY(hipMemcpyAsync(b.d_sims + s, &b.sd[s], sizeof(SimDev), hipMemcpyHostToDevice, b.stream));
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    return MITHRA_OK;
+}
+
 static mithra_status get_info(Batch &b, int s, mithra_info *info)
 {
     if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
@@ -1719,6 +1748,12 @@ mithra_status mithra_set_optical_undulator(mithra_sim *sim, const mithra_seed *w
     return set_optical(*sim->b, 0, wave);
 }
 
+mithra_status mithra_set_optical_beam(mithra_sim *sim, const mithra_beam *beam)
+{
+    if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
+    return set_optical_beam(*sim->b, 0, beam);
+}
+
 mithra_status mithra_run(mithra_sim *sim, int64_t nsteps)
 {
     if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
@@ -1872,6 +1907,12 @@ mithra_status mithra_batch_set_optical_undulator(mithra_batch *bb, int32_t sim,
 {
     if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
     return set_optical(*bb->b, sim, wave);
+}
+
+mithra_status mithra_batch_set_optical_beam(mithra_batch *bb, int32_t sim, const mithra_beam *beam)
+{
+    if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
+    return set_optical_beam(*bb->b, sim, beam);
 }
 
 mithra_status mithra_batch_tune(mithra_batch *bb, int32_t trial_steps)

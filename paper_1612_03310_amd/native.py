@@ -37,6 +37,7 @@ ABI_FUNCTIONS = (
     "mithra_batch_get_info", "mithra_batch_set_timing", "mithra_batch_get_timing",
     "mithra_batch_destroy", "mithra_set_seed", "mithra_batch_set_seed",
     "mithra_set_optical_undulator", "mithra_batch_set_optical_undulator",
+    "mithra_set_optical_beam", "mithra_batch_set_optical_beam",
 )
 
 SIGNALS = {"neumann": 0, "gaussian": 1, "secant": 2, "flat-top": 3}
@@ -74,6 +75,24 @@ def make_seed(amplitude, polarization=(1.0, 0.0), frequency=0.0, t0=0.0, tau=1.0
     s.z_ref = float(z_ref)
     s.signal = SIGNALS[signal] if isinstance(signal, str) else int(signal)
     return s
+
+
+class Beam(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("rayleigh", ctypes.c_double * 2), ("focus", ctypes.c_double * 3)]
+
+
+BEAMS = {"plane": 0, "gaussian": 1}
+
+
+def make_beam(beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)) -> Beam:
+    b = Beam()
+    b.type = BEAMS[beam] if isinstance(beam, str) else int(beam)
+    for a in range(2):
+        b.rayleigh[a] = float(rayleigh[a])
+    for a in range(3):
+        b.focus[a] = float(focus[a])
+    return b
 
 
 class DiagCfg(ctypes.Structure):
@@ -144,6 +163,8 @@ def load_library(path: str = LIB_PATH):
         "mithra_batch_set_seed": [P, I32, ctypes.POINTER(Seed)],
         "mithra_set_optical_undulator": [P, ctypes.POINTER(Seed)],
         "mithra_batch_set_optical_undulator": [P, I32, ctypes.POINTER(Seed)],
+        "mithra_set_optical_beam": [P, ctypes.POINTER(Beam)],
+        "mithra_batch_set_optical_beam": [P, I32, ctypes.POINTER(Beam)],
         "mithra_run": [P, I64],
         "mithra_sync": [P],
         "mithra_get_field": [P, I32, dp],
@@ -330,6 +351,11 @@ class Sim:
         wave = make_seed(amplitude, **kw)
         _check(self._lib.mithra_set_optical_undulator(self._h, ctypes.byref(wave)))
 
+    def set_optical_beam(self, beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)):
+        """Beam of the optical undulator (see mithra_set_optical_beam)."""
+        b = make_beam(beam, rayleigh, focus)
+        _check(self._lib.mithra_set_optical_beam(self._h, ctypes.byref(b)))
+
     def config_diag(self, probe, kp, every=1, capacity=4096, spectrum=False):
         c = DiagCfg()
         for a in range(3):
@@ -451,6 +477,10 @@ class Batch:
     def set_optical_undulator(self, s, amplitude, **kw):
         wave = make_seed(amplitude, **kw)
         _check(self._lib.mithra_batch_set_optical_undulator(self._h, int(s), ctypes.byref(wave)))
+
+    def set_optical_beam(self, s, beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)):
+        b = make_beam(beam, rayleigh, focus)
+        _check(self._lib.mithra_batch_set_optical_beam(self._h, int(s), ctypes.byref(b)))
 
     def config_diag(self, s, probe, kp, every=1, capacity=4096, spectrum=False):
         c = DiagCfg()

@@ -288,6 +288,77 @@ def test_optical_undulator_full_loop_matches_oracle(precision):
     assert np.max(np.abs(orc.u[:, 1])) > 0.05 and orc.lost == 0
 
 
+def _gaussian_beam(w):
+    """An astigmatic Gaussian beam for the wave of _optical_wave: waist 6
+    cells along the polarization and 6/sqrt(2) across it, focused one cell
+    off the bunch axis and 10 cells ahead of its centre."""
+    k = 2 * np.pi / (32 * w.d[2])
+    w0 = 6 * w.d[0]
+    zr = k * w0 * w0 / 2
+    c = [w.origin[a] + (w.n[a] - 1) * w.d[a] / 2 for a in range(3)]
+    return dict(beam="gaussian", rayleigh=(zr, 0.5 * zr),
+                focus=(c[0] + w.d[0], c[1] - w.d[1], c[2] + 10 * w.d[2]))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_gaussian_beam_optical_undulator_full_loop_matches_oracle(precision):
+    """As the plane-wave case, with the wave shaped as an astigmatic Gaussian
+    beam whose waist is comparable to the bunch: the whole state and the
+    diagnostics against the oracle; the beam shape changes the momenta by
+    far more than the bar."""
+    w = _bunch_at_rest(W.config(0, steps=60))
+    amp, wave = _optical_wave(w)
+    beam = _gaussian_beam(w)
+    say("case Gaussian-beam optical undulator", w.n, precision, beam)
+    orc = oracle.from_workload(w)
+    orc.set_optical_undulator(amp, **wave)
+    orc.set_optical_beam(**beam)
+    plane = oracle.from_workload(w)
+    plane.set_optical_undulator(amp, **wave)
+    sim = native.sim_from_workload(w, precision=precision, every=1)
+    sim.set_optical_beam(**beam)        # kept when the wave is set afterwards
+    sim.set_optical_undulator(amp, **wave)
+    sim.run(60)
+    sim.sync()
+    orc.step(60)
+    plane.step(60)
+    if precision == "f64":
+        compare_state(sim, orc, TOL64, "gaussian beam")
+        compare_diag(sim.get_diag(), orc.diag(), TOL64, "gaussian beam")
+    else:
+        pos, u, alive = sim.get_particles()
+        assert np.array_equal(alive, orc.alive)
+        err = rel_l2(u, orc.u)
+        say("gaussian beam f32 u rel-L2", err)
+        assert err < 1e-4, err
+    shaped = rel_l2(orc.u, plane.u)
+    say("momenta, Gaussian beam against plane wave", shaped)
+    assert shaped > 1e-2 and orc.lost == 0
+
+
+def test_optical_beam_rejects_bad_parameters_and_plane_is_the_default():
+    w = W.config(0, steps=10)
+    amp, wave = _optical_wave(w)
+    sim = native.sim_from_workload(w, precision="f64")
+    for kw in (dict(beam=5), dict(beam="gaussian", rayleigh=(0.0, 1e-3)),
+               dict(beam="gaussian", rayleigh=(1e-3, float("inf"))),
+               dict(beam="gaussian", rayleigh=(1e-3, 1e-3), focus=(0.0, float("nan"), 0.0))):
+        with pytest.raises(native.MithraError) as e:
+            sim.set_optical_beam(**kw)
+        assert e.value.status == native.EINVAL, kw
+    outs = []
+    for explicit in (False, True):
+        s = native.sim_from_workload(_bunch_at_rest(W.config(0, steps=10)), precision="f64")
+        s.set_optical_undulator(amp, **wave)
+        if explicit:
+            s.set_optical_beam(**_gaussian_beam(w))
+            s.set_optical_beam("plane")
+        s.run(10)
+        s.sync()
+        outs.append(s.get_particles()[1])
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_optical_undulator_switched_off_is_the_static_one_bitwise():
     w = W.config(0, steps=20)
     amp, wave = _optical_wave(w)
@@ -327,20 +398,27 @@ def test_optical_undulator_switched_on_mid_run_matches_oracle():
 
 
 def test_batch_mixing_optical_and_static_undulators_equals_separate_runs():
-    """One simulation with the optical undulator, one with the static one, in
-    one batch (both through the optical push variant): each equals its own
-    separate run bit for bit."""
+    """One simulation with the optical undulator, one with the static one and
+    one with the optical undulator shaped as a Gaussian beam, in one batch
+    (all through the optical push variant): each equals its own separate run
+    bit for bit."""
     ws = [_bunch_at_rest(W.config(0, steps=30)),
-          W.make_workload("static", (32, 32, 96), 3000, 120.0, 1.2, 0.015, 1e-4, 77, 30)]
+          W.make_workload("static", (32, 32, 96), 3000, 120.0, 1.2, 0.015, 1e-4, 77, 30),
+          _bunch_at_rest(W.config(0, steps=30, seed=991))]
     amp, wave = _optical_wave(ws[0])
+    beam = _gaussian_beam(ws[2])
     b = native.batch_from_workloads(ws, precision="f64")
     b.set_optical_undulator(0, amp, **wave)
+    b.set_optical_undulator(2, amp, **wave)
+    b.set_optical_beam(2, **beam)
     b.run(30)
     b.sync()
     for s, w in enumerate(ws):
         sim = native.sim_from_workload(w, precision="f64")
-        if s == 0:
+        if s != 1:
             sim.set_optical_undulator(amp, **wave)
+        if s == 2:
+            sim.set_optical_beam(**beam)
         sim.run(30)
         sim.sync()
         for name in ("Ax", "Ay", "phi", "rho", "Jx"):
