@@ -62,6 +62,9 @@ def _load():
     lib.orc_set_seed.argtypes = [P, I, D, D, D, D, D, D, D, I, D]
     lib.orc_set_optical.argtypes = [P, I, D, D, D, D, D, D, D, I, D]
     lib.orc_set_optical_beam.argtypes = [P, I, D, D, D, D, D]
+    lib.orc_set_seed_beam.argtypes = [P, I, D, D, D, D, D]
+    lib.orc_seed_incident.argtypes = [P, I, I, I, I, D]
+    lib.orc_seed_incident.restype = D
     lib.orc_seed_signal.argtypes = [P, D]
     lib.orc_seed_signal.restype = D
     lib.orc_config_diag.argtypes = [P, I, I, I, I]
@@ -158,6 +161,19 @@ class OracleSim:
                                   float(polarization[1]), float(frequency), float(t0),
                                   float(tau), float(cep), int(self.SIGNALS[signal]),
                                   float(z_ref))
+
+    def set_seed_beam(self, beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)):
+        """Beam of the seed: "plane" or "gaussian" (travelling towards +z) with
+        the Rayleigh lengths along the polarization and across it [m] and the
+        focus (rest frame)."""
+        self._lib.orc_set_seed_beam(self._h, {"plane": 0, "gaussian": 1}[beam],
+                                    float(rayleigh[0]), float(rayleigh[1]), float(focus[0]),
+                                    float(focus[1]), float(focus[2]))
+
+    def seed_incident(self, comp, i, j, k, t):
+        """Incident potential of the seed at grid point (i, j, k) of
+        component comp (0: A_x, 1: A_y) at time t."""
+        return self._lib.orc_seed_incident(self._h, int(comp), int(i), int(j), int(k), float(t))
 
     def set_optical_beam(self, beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)):
         """Beam of the optical undulator: "plane" or "gaussian" with the

@@ -101,6 +101,9 @@ typedef struct orc_sim {
     /* seed plane wave (reading R20) */
     int seed_on, seed_sig;
     double seed_a0, seed_p[2], seed_f, seed_t0, seed_tau, seed_cep, seed_zref;
+    /* its beam (reading R25): 0 plane wave, 1 Gaussian beam along +z */
+    int seed_beam;
+    double seed_zr[2], seed_focus[3];
     /* optical undulator (reading R24): a plane wave towards -z in place of the
        static undulator, same signal shapes as the seed */
     int opt_on, opt_sig;
@@ -509,11 +512,47 @@ void orc_set_seed(orc_sim *s, int on, double a0, double px, double py, double fr
     s->seed_zref = z_ref;
 }
 
-/* incident potential component c at grid plane k, time level n */
-static double seed_incident(const orc_sim *s, int c, int k, double t)
+static double complex analytic_signal(int sig, double a, double f, double t0, double tau,
+                                      double cep, double t, double complex *rate);
+
+void orc_set_seed_beam(orc_sim *s, int beam, double zr_par, double zr_perp, double xf, double yf,
+                       double zf)
+{
+    s->seed_beam = beam;
+    s->seed_zr[0] = zr_par;
+    s->seed_zr[1] = zr_perp;
+    s->seed_focus[0] = xf;
+    s->seed_focus[1] = yf;
+    s->seed_focus[2] = zf;
+}
+
+/* incident potential component c at the grid point (i, j, k) of that
+   component (A_x sits at x + dx/2, A_y at y + dy/2), time level n: the plane
+   wave, or for the Gaussian-beam seed (reading R25, travelling towards +z,
+   zeta = z - z_f) Re{U S} with the analytic signal S */
+static double seed_incident(const orc_sim *s, int c, int i, int j, int k, double t)
 {
     double z = s->o[2] + k * s->d[2];
-    return s->seed_p[c] * orc_seed_signal(s, t - (z - s->seed_zref) / ORC_C);
+    double tt = t - (z - s->seed_zref) / ORC_C;
+    if (s->seed_beam != 1) return s->seed_p[c] * orc_seed_signal(s, tt);
+    double x = s->o[0] + (i + (c == 0 ? 0.5 : 0.0)) * s->d[0];
+    double y = s->o[1] + (j + (c == 1 ? 0.5 : 0.0)) * s->d[1];
+    double k0 = 2.0 * ORC_PI * s->seed_f / ORC_C, px = s->seed_p[0], py = s->seed_p[1];
+    double pn = sqrt(px * px + py * py);
+    double X = x - s->seed_focus[0], Y = y - s->seed_focus[1], zeta = z - s->seed_focus[2];
+    double xi = (X * px + Y * py) / pn, eta = (-X * py + Y * px) / pn;
+    double complex q1 = zeta + ORC_J * s->seed_zr[0], q2 = zeta + ORC_J * s->seed_zr[1];
+    double complex U = csqrt(ORC_J * s->seed_zr[0] / q1) * csqrt(ORC_J * s->seed_zr[1] / q2) *
+                       cexp(-ORC_J * k0 * xi * xi / (2.0 * q1) - ORC_J * k0 * eta * eta / (2.0 * q2));
+    double complex rate;
+    double complex S = analytic_signal(s->seed_sig, s->seed_a0, s->seed_f, s->seed_t0, s->seed_tau,
+                                       s->seed_cep, tt, &rate);
+    return s->seed_p[c] * creal(U * S);
+}
+
+double orc_seed_incident(const orc_sim *s, int c, int i, int j, int k, double t)
+{
+    return seed_incident(s, c, i, j, k, t);
 }
 
 /* after the interior update of component c (A_x or A_y): the scattered-field
@@ -527,14 +566,16 @@ static void seed_tfsf(orc_sim *s, int c, const int lo[3], const int hi[3])
     const int ks = 2, kt = 3;
     for (int j = lo[1]; j <= hi[1]; j++)
         for (int i = lo[0]; i <= hi[0]; i++) {
-            /* the incident field is uniform across a plane; the neighbours are
-               written out as in eq. (updateEquation) */
-            double ft_ip = seed_incident(s, c, kt, t), ft_im = ft_ip, ft_jp = ft_ip, ft_jm = ft_ip;
-            double fs_ip = seed_incident(s, c, ks, t), fs_im = fs_ip, fs_jp = fs_ip, fs_jm = fs_ip;
+            /* the neighbours on the other plane, as in eq. (updateEquation)
+               (all equal for the plane wave) */
+            double ft_ip = seed_incident(s, c, i + 1, j, kt, t), ft_im = seed_incident(s, c, i - 1, j, kt, t);
+            double ft_jp = seed_incident(s, c, i, j + 1, kt, t), ft_jm = seed_incident(s, c, i, j - 1, kt, t);
+            double fs_ip = seed_incident(s, c, i + 1, j, ks, t), fs_im = seed_incident(s, c, i - 1, j, ks, t);
+            double fs_jp = seed_incident(s, c, i, j + 1, ks, t), fs_jm = seed_incident(s, c, i, j - 1, ks, t);
             R[IX(s, i, j, ks)] -= A * (s->a2 * ft_ip + s->a2 * ft_im + s->a4 * ft_jp + s->a4 * ft_jm) +
-                                  s->a6 * seed_incident(s, c, kt, t);
+                                  s->a6 * seed_incident(s, c, i, j, kt, t);
             R[IX(s, i, j, kt)] += A * (s->a2 * fs_ip + s->a2 * fs_im + s->a4 * fs_jp + s->a4 * fs_jm) +
-                                  s->a6 * seed_incident(s, c, ks, t);
+                                  s->a6 * seed_incident(s, c, i, j, ks, t);
         }
 }
 
@@ -795,15 +836,17 @@ static double complex analytic_signal(int sig, double a, double f, double t0, do
 }
 
 /* Gaussian-beam optical undulator (reading R25): E = -p dpsi/dt,
-   B = grad psi x p = (-p_y dpsi/dz, p_x dpsi/dz, -dpsi/deta) with
-   psi = Re{U S}; d/dz = (1/c) d/dt - d/dzeta. */
+   B = grad psi x p = (-p_y dpsi/dz, p_x dpsi/dz, -|p| dpsi/deta) with
+   psi = Re{U S}, xi and eta the distances along p/|p| and z x p/|p|;
+   d/dz = (1/c) d/dt - d/dzeta. */
 static void gaussian_beam_field(const orc_sim *s, double x, double y, double z, double t,
                                 double *E, double *B)
 {
     double k = 2.0 * ORC_PI * s->opt_f / ORC_C;
     double px = s->opt_p[0], py = s->opt_p[1];
+    double pn = sqrt(px * px + py * py);
     double X = x - s->opt_focus[0], Y = y - s->opt_focus[1], zeta = s->opt_focus[2] - z;
-    double xi = X * px + Y * py, eta = -X * py + Y * px;
+    double xi = (X * px + Y * py) / pn, eta = (-X * py + Y * px) / pn;
     double complex q1 = zeta + ORC_J * s->opt_zr[0], q2 = zeta + ORC_J * s->opt_zr[1];
     double complex U = csqrt(ORC_J * s->opt_zr[0] / q1) * csqrt(ORC_J * s->opt_zr[1] / q2) *
                        cexp(-ORC_J * k * xi * xi / (2.0 * q1) - ORC_J * k * eta * eta / (2.0 * q2));
@@ -821,7 +864,7 @@ static void gaussian_beam_field(const orc_sim *s, double x, double y, double z, 
     E[2] = 0.0;
     B[0] = -py * dpsi_dz;
     B[1] = px * dpsi_dz;
-    B[2] = -dpsi_deta;
+    B[2] = -pn * dpsi_deta;
 }
 
 void orc_set_optical_beam(orc_sim *s, int beam, double zr_par, double zr_perp, double xf,

@@ -1288,3 +1288,118 @@ def test_gaussian_beam_is_a_vacuum_wave_to_paraxial_order(signal, x_env, bound):
         tt = _d2(lambda s: Ex(dt=s / C), h)
         peak = max(abs(Ex(dt=s * LAM_G / C / 8)) for s in range(8))
         assert abs(lap - tt) < bound * K_G ** 2 * peak, (lap, tt, K_G ** 2 * peak)
+
+
+# ---- Gaussian-beam seed by TF/SF (reading R25) -------------------------------
+
+def test_gaussian_seed_reduces_to_the_plane_wave_seed_for_long_rayleigh_lengths():
+    """The per-point incident field (A_x at x + dx/2, A_y at y + dy/2) with
+    Rayleigh lengths of 1e9 m drives the mesh as the plane-wave seed does."""
+    runs = []
+    for beam in ("plane", "gaussian"):
+        dz = 1e-6
+        d, n = (2 * dz, 2 * dz, dz), (6, 6, 120)
+        sim = oracle.OracleSim(n, d, (0.0, 0.0, 0.0), courant=0.9, bc=(1, 1, 0), K=0.0)
+        _empty(sim)
+        tau = 15 * dz / C
+        sim.set_seed(1e-3, (0.6, 0.8), C / (20 * dz), 4 * tau, tau, 0.3, "gaussian", z_ref=0.0)
+        sim.set_seed_beam(beam, rayleigh=(1e9, 1e9), focus=(3e-6, 5e-6, 60e-6))
+        sim.step(100)
+        runs.append([sim.pot(c, "cur").copy() for c in range(2)])
+    for a, b in zip(*runs):
+        assert np.abs(a - b).max() <= 1e-9 * np.abs(b).max()
+
+
+def _gaussian_seeded(steps):
+    """A round, nearly collimated Gaussian beam (k z_R = 100, so the paraxial
+    envelope is a vacuum wave to about 1%; waist 5.6 cells across, 20 cells
+    per wavelength along z) injected at the TF/SF planes, focused 60 cells
+    into the box."""
+    dz = 1e-6
+    d, n = (8 * dz, 8 * dz, dz), (40, 40, 100)
+    origin = (-156 * dz, -156 * dz, 0.0)
+    sim = oracle.OracleSim(n, d, origin, courant=0.9, bc=(0, 0, 0), K=0.0)
+    _empty(sim)
+    lam, tau = 20 * dz, 15 * dz / C
+    k = 2 * np.pi / lam
+    zr = 100.0 / k
+    w0 = np.sqrt(2 * zr / k)
+    sim.set_seed(1e-3, (1.0, 0.0), C / lam, 4 * tau, tau, 0.3, "gaussian", z_ref=0.0)
+    sim.set_seed_beam("gaussian", rayleigh=(zr, zr), focus=(0.0, 0.0, 60 * dz))
+    sim.step(steps)
+    return sim, w0
+
+
+def test_gaussian_seed_keeps_the_scattered_region_empty():
+    """With a transverse profile the corrections use each point's own
+    neighbours on the other plane; what leaks behind the injection planes
+    stays far below the beam (a wrong sign or a missing neighbour leaks a
+    field of the beam's order)."""
+    sim, _ = _gaussian_seeded(90)
+    a = sim.pot(0, "cur")
+    peak = np.abs(a[3:]).max()
+    assert peak > 1e-4
+    assert np.abs(a[:2]).max() < 1e-2 * peak
+
+
+def test_gaussian_seed_reaches_its_waist_at_the_focus():
+    """After the pulse has propagated 60 cells through the mesh, the
+    transverse profile of A_x on the focal plane at its peak is a Gaussian
+    of the waist sqrt(2 z_R / k) (fitted across x and y, within 5%)."""
+    sim, w0 = _gaussian_seeded(0)
+    best, prof = 0.0, None
+    for _ in range(90):
+        sim.step(1)
+        plane = sim.pot(0, "cur")[60]
+        if np.abs(plane).max() > best:
+            best, prof = np.abs(plane).max(), plane.copy()
+    dz = 1e-6
+    xs = -156 * dz + (np.arange(40) + 0.5) * 8 * dz   # A_x sits half a cell along x
+    ys = -156 * dz + np.arange(40) * 8 * dz
+    j0 = int(np.argmin(np.abs(ys)))
+    i0 = int(np.argmin(np.abs(xs)))
+    for r, line in ((xs, prof[j0, :]), (ys, prof[:, i0])):
+        keep = np.abs(line) > 0.05 * np.abs(line).max()
+        # ln|A| = c - r^2 / w^2 across the beam
+        slope = np.polyfit(r[keep] ** 2, np.log(np.abs(line[keep])), 1)[0]
+        w_fit = np.sqrt(-1.0 / slope)
+        assert abs(w_fit / w0 - 1.0) < 0.05, (w_fit, w0)
+
+
+def test_gaussian_seed_corrections_are_the_update_of_the_incident_field():
+    """One update from an empty mesh: what the TF/SF corrections put on the
+    planes k = 2 and 3 is exactly what the plain update (eq. updateEquation,
+    pinned above) takes from the incident field on the other plane, point by
+    point with each point's own neighbours (a narrow, strongly focused beam,
+    so neighbours differ)."""
+    dz = 1e-6
+    n, d = (14, 12, 10), (3 * dz, 3 * dz, dz)
+    origin = (-20 * dz, -17 * dz, 0.0)
+    lam = 20 * dz
+    k = 2 * np.pi / lam
+
+    def make(seeded):
+        sim = oracle.OracleSim(n, d, origin, courant=0.9, bc=(0, 0, 0), K=0.0)
+        _empty(sim)
+        if seeded:
+            # bare carrier of the flat-top signal (x > 0 everywhere here)
+            sim.set_seed(1e-3, (0.6, 0.8), C / lam, -5e-13, 1e-14, 0.3, "flat-top", z_ref=0.0)
+            sim.set_seed_beam("gaussian", rayleigh=(k * (6 * dz) ** 2 / 2, k * (4 * dz) ** 2 / 2),
+                              focus=(1e-6, -2e-6, 5 * dz))
+        return sim
+
+    seeded = make(True)
+    seeded.set_step(7)
+    t = 7 * seeded.const["dt"]
+    seeded.field_update()
+    for comp in (0, 1):
+        for src, dst, sign in ((3, 2, -1.0), (2, 3, 1.0)):
+            plain = make(False)
+            inc = np.array([[seeded.seed_incident(comp, i, j, src, t) for i in range(n[0])]
+                            for j in range(n[1])])
+            assert np.abs(inc).max() > 1e-5
+            plain.pot(comp, "cur")[src] = inc
+            plain.field_update()
+            want = plain.pot(comp, "next")[dst, 1:-1, 1:-1]
+            got = seeded.pot(comp, "next")[dst, 1:-1, 1:-1]
+            assert np.allclose(sign * got, want, rtol=0, atol=1e-13 * np.abs(want).max()), comp
