@@ -275,6 +275,20 @@ typedef struct {
 
 mithra_status mithra_set_optical_beam(mithra_sim *sim, const mithra_beam *beam);
 
+/* Beam of the seed (section "FIELD", seed types plane wave and Gaussian
+   beam, same parameters): the seed's wave (mithra_set_seed) times the
+   paraxial envelope above for a beam travelling towards +z, with
+   zeta = z - z_f in q.  The TF/SF planes then inject, at every point of
+   A_x (at x + dx/2) and A_y (at y + dy/2), the incident field of that point,
+   and the corrections use each point's own neighbours on the other plane
+   (a kernel before each potential update writes them, 4 nx ny doubles of
+   device memory per simulation, allocated at the first Gaussian setting).
+   The beam should lie well inside the transverse boundaries.  Type 0 is
+   the plane wave (default).  Kept when the seed itself changes; acts from
+   the next step.  EINVAL as for the optical undulator's beam; ENOMEM if
+   the corrections cannot be allocated. */
+mithra_status mithra_set_seed_beam(mithra_sim *sim, const mithra_beam *beam);
+
 /* Enqueue nsteps steps on the simulation's stream (asynchronous).  ESTATE if
    no particles were loaded (np = 0 is a valid load). */
 mithra_status mithra_run(mithra_sim *sim, int64_t nsteps);
@@ -345,6 +359,7 @@ mithra_status mithra_batch_set_seed(mithra_batch *b, int32_t sim, const mithra_s
 mithra_status mithra_batch_set_optical_undulator(mithra_batch *b, int32_t sim,
                                                  const mithra_seed *wave);
 mithra_status mithra_batch_set_optical_beam(mithra_batch *b, int32_t sim, const mithra_beam *beam);
+mithra_status mithra_batch_set_seed_beam(mithra_batch *b, int32_t sim, const mithra_beam *beam);
 /* Autotuner of the batch (see mithra_tune): one tile shape for all
    simulations, chosen by timing the whole batched launch. */
 mithra_status mithra_batch_tune(mithra_batch *b, int32_t trial_steps);

@@ -73,6 +73,9 @@
  *       (envelope times exp(i(w x + cep))), U = u(xi, z_par) u(eta, z_perp),
  *       u(v, zr) = sqrt(i zr / q) exp(-i k v^2 / (2 q)), q = zeta + i zr,
  *       zeta = z_f - z; fields E = -dA/dt, B = curl A (no scalar potential).
+ *       The seed's Gaussian-beam type is the same beam towards +z
+ *       (zeta = z - z_f, argument t - (z - z_ref)/c) injected point by point
+ *       through the TF/SF planes.
  */
 #include <complex.h>
 #include <math.h>

@@ -66,6 +66,74 @@ __device__ double seed_signal(const SimDev &S, double t)
     }
 }
 
+// Envelope of the seed's signal at x = t - t0 (the signal is
+// a0 e(x) cos(w x + cep)).
+__device__ double seed_envelope(const SimDev &S, double x)
+{
+    const double ln2 = 0.69314718055994530942;
+    const double g = exp(-2.0 * ln2 * x * x / (S.seed_tau * S.seed_tau));
+    switch (S.seed_sig) {
+    case 0: return -4.0 * ln2 * x / (S.seed_tau * S.seed_tau) * g;
+    case 1: return g;
+    case 2: return 1.0 / cosh(x / S.seed_tau);
+    default: return x <= 0.0 ? g : 1.0;
+    }
+}
+
+// Incident potential of a Gaussian-beam seed (travelling towards +z) for
+// component comp at its grid point (i, j, k): A_x sits at x + dx/2, A_y at
+// y + dy/2.  a0 p_c |U| e(x) cos(w x + cep + theta) with the paraxial
+// envelope U = |U| exp(i theta) per axis v (xi along p/|p|, eta along
+// z x p/|p|), zeta = z - z_f, m = zeta^2 + zr^2:
+// |u| = (zr^2/m)^(1/4) exp(-k v^2 zr / (2m)), arg u = atan(zeta/zr)/2
+// - k v^2 zeta / (2m).
+__device__ double seed_beam_incident(const SimDev &S, int comp, int i, int j, int k, double t)
+{
+    const double x = S.origin[0] + ((double)i + (comp == 0 ? 0.5 : 0.0)) * S.d[0];
+    const double y = S.origin[1] + ((double)j + (comp == 1 ? 0.5 : 0.0)) * S.d[1];
+    const double z = S.origin[2] + (double)k * S.d[2];
+    const double px = S.seed_p[0], py = S.seed_p[1], ipn = 1.0 / sqrt(px * px + py * py);
+    const double X = x - S.seed_focus[0], Y = y - S.seed_focus[1], zeta = z - S.seed_focus[2];
+    const double v[2] = {(X * px + Y * py) * ipn, (-X * py + Y * px) * ipn};
+    double amp = 1.0, theta = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const double zr = S.seed_zr[a], im = 1.0 / (zeta * zeta + zr * zr);
+        const double kv2 = S.seed_k * v[a] * v[a];
+        amp *= sqrt(zr * sqrt(im)) * exp(-0.5 * kv2 * zr * im);
+        theta += 0.5 * atan2(zeta, zr) - 0.5 * kv2 * zeta * im;
+    }
+    const double xs = t - (z - S.seed_zref) / C_LIGHT_D - S.seed_t0;
+    const double w = 2.0 * 3.14159265358979323846 * S.seed_f;
+    return S.seed_a0 * S.seed_p[comp] * amp * seed_envelope(S, xs) *
+           cos(w * xs + S.seed_cep + theta);
+}
+
+// TF/SF corrections of a Gaussian-beam seed for one column and component:
+// plane 2 (scattered side) loses what its update takes from the incident
+// field on plane 3, plane 3 gains what its update misses on plane 2, each
+// point with its own neighbours on the other plane (in the regrouped
+// weights of the potential update: A (a_x, a_y) across, a_z along z).
+__global__ __launch_bounds__(BLOCK) void k_seed_beam(const SimDev *__restrict__ sims, int sim,
+                                                     int ncol, const long long *__restrict__ d_step)
+{
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= 2 * ncol) return;
+    const SimDev &S = sims[sim];
+    const int comp = e / ncol, col = e - comp * ncol;
+    const int i = col % S.n[0], j = col / S.n[0];
+    const double t = (double)(*d_step) * S.dt;
+    auto pull = [&](int k) {
+        return S.A * (S.ax * (seed_beam_incident(S, comp, i + 1, j, k, t) +
+                              seed_beam_incident(S, comp, i - 1, j, k, t)) +
+                      S.ay * (seed_beam_incident(S, comp, i, j + 1, k, t) +
+                              seed_beam_incident(S, comp, i, j - 1, k, t))) +
+               S.az * seed_beam_incident(S, comp, i, j, k, t);
+    };
+    S.seed_corr[(long long)(2 * comp) * ncol + col] = -pull(3);
+    S.seed_corr[(long long)(2 * comp + 1) * ncol + col] = pull(2);
+}
+
 // Rate ds/dt of the optical undulator's signal (the seed's four shapes with
 // the undulator's parameters): carrier C = cos(w x + cep), envelope
 // g = exp(-2 ln2 x^2 / tau^2), x = t - t0.
@@ -118,15 +186,17 @@ __device__ void optical_envelope(const SimDev &S, double x, double *e, double *e
 // eta along z x p with Rayleigh length zr, zeta = z_f - z, m = zeta^2 + zr^2:
 // |u| = (zr^2/m)^(1/4) exp(-k v^2 zr / (2m)), arg u = atan(zeta/zr)/2
 // - k v^2 zeta / (2m)).  With psi = a |U| e cos(Theta), Theta = w x + cep +
-// theta: E = -p dpsi/dt, B = (-p_y, p_x) dpsi/dz and B_z = -dpsi/deta, where
+// theta, xi and eta along p/|p| and z x p/|p|: E = -p dpsi/dt,
+// B = (-p_y, p_x) dpsi/dz and B_z = -|p| dpsi/deta, where
 // the z and eta derivatives of U are U (alpha + i beta) with the real and
 // imaginary parts written out below.
 __device__ void optical_gaussian_beam(const SimDev &S, double t, double x, double y, double z,
                                       double *E, double *B)
 {
     const double px = S.opt_p[0], py = S.opt_p[1], k = S.opt_k;
+    const double pn = sqrt(px * px + py * py), ipn = 1.0 / pn;
     const double X = x - S.opt_focus[0], Y = y - S.opt_focus[1], zeta = S.opt_focus[2] - z;
-    const double v[2] = {X * px + Y * py, -X * py + Y * px};
+    const double v[2] = {(X * px + Y * py) * ipn, (-X * py + Y * px) * ipn};
     double amp = 1.0, theta = 0.0, a_z = 0.0, b_z = 0.0;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -153,7 +223,7 @@ __device__ void optical_gaussian_beam(const SimDev &S, double t, double x, doubl
     E[1] = -py * dt_psi;
     B[0] = -py * dz_psi;
     B[1] = px * dz_psi;
-    B[2] = -deta_psi;
+    B[2] = -pn * deta_psi;
 }
 
 __device__ __forceinline__ int comp_extent(const SimDev &S, int c, int a)
@@ -373,7 +443,14 @@ __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ s
     // uniform over the plane
     const bool seeded = S.seed_on && comp < 2 && S.seed_p[comp < 2 ? comp : 0] != 0.0 && !S.bc[2];
     R corr_s = 0, corr_t = 0;
-    if (seeded) {
+    if (seeded && S.seed_beam) {
+        // a Gaussian beam: per-column corrections written before this launch
+        if (act && k0 <= 3) {
+            const long long cc = (long long)j * nx + i;
+            corr_s = (R)S.seed_corr[(2 * comp) * sxy + cc];
+            corr_t = (R)S.seed_corr[(2 * comp + 1) * sxy + cc];
+        }
+    } else if (seeded) {
         const double t = (double)step * S.dt;
         const double wgt = S.A * (2.0 * S.ax + 2.0 * S.ay) + S.az;  // weight of plane k +- 1
         const double p = S.seed_p[comp];
@@ -2079,6 +2156,13 @@ void launch_diag(hipStream_t st, const SimDev *sims, int nsim, const int2 *plane
         hipLaunchKernelGGL((k_diag_parts<R>), dim3(nparts), dim3(BLOCK), 0, st, sims, plane_items,
                            nplane, mesh_items, nmesh, kin_items, ar);
     hipLaunchKernelGGL((k_diag_final<R>), dim3(nsim), dim3(BLOCK), 0, st, sims, ar);
+}
+
+void launch_seed_beam(hipStream_t st, const SimDev *sims, int sim, int ncol,
+                      const long long *d_step)
+{
+    hipLaunchKernelGGL(k_seed_beam, dim3((unsigned)((2 * ncol + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       st, sims, sim, ncol, d_step);
 }
 
 template <typename R>

@@ -80,6 +80,12 @@ struct SimDev {
     // seed plane wave along +z (TF/SF planes k = 2 and 3)
     int seed_on, seed_sig;
     double seed_a0, seed_p[2], seed_f, seed_t0, seed_tau, seed_cep, seed_zref;
+    // its beam: 0 plane wave (uniform corrections), 1 Gaussian beam along +z,
+    // whose per-column corrections of A_x and A_y on planes 2 and 3 are
+    // written each step to seed_corr ([comp][plane][ny][nx])
+    int seed_beam;
+    double seed_zr[2], seed_focus[3], seed_k;
+    double *seed_corr;
     // optical undulator: a plane wave towards -z, A = a p s(t + (z - z_ref)/c),
     // in place of the static undulator (same signal shapes as the seed)
     int opt_on, opt_sig;
@@ -133,6 +139,10 @@ template <typename R>
 // fuse_x: the stencil pass also updates the x faces (first-order Mur)
 void launch_stencil(hipStream_t st, const SimDev *sims, const int4 *items, int nitems,
                     const Arena &ar, int tx, int ty, int kz, int fuse_x);
+// Gaussian-beam seed: the TF/SF corrections of simulation `sim` for this
+// step (ncol = nx * ny columns), before its potential update
+void launch_seed_beam(hipStream_t st, const SimDev *sims, int sim, int ncol,
+                      const long long *d_step);
 template <typename R>
 void launch_boundary(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg,
                      long long total, const Arena &ar);

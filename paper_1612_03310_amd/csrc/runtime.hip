@@ -57,6 +57,8 @@ struct HostSim {
     mithra_seed seed{};  // amplitude 0: none
     mithra_seed optical{};  // optical undulator (wave towards -z); amplitude 0: static undulator
     mithra_beam beam{};     // its beam (type 0: plane wave)
+    mithra_beam seed_beam{};        // the seed's beam (type 0: plane wave)
+    double *seed_corr = nullptr;    // device: Gaussian-beam seed corrections
     double dt, dtb, A, gamma0, beta0, B0, ku;
     bool loaded = false;
     double q = 0.0, m = 0.0;
@@ -292,6 +294,27 @@ static void fill_seed(const HostSim &h, SimDev &S)
     S.seed_tau = h.seed.tau > 0.0 ? h.seed.tau : 1.0;
     S.seed_cep = h.seed.cep;
     S.seed_zref = h.seed.z_ref;
+    S.seed_beam = h.seed_beam.type;
+    S.seed_zr[0] = h.seed_beam.rayleigh[0];
+    S.seed_zr[1] = h.seed_beam.rayleigh[1];
+    for (int a = 0; a < 3; ++a) S.seed_focus[a] = h.seed_beam.focus[a];
+    S.seed_k = 2.0 * PI * h.seed.frequency / C_LIGHT;
+    S.seed_corr = h.seed_corr;
+}
+
+// the simulation's step launches the Gaussian-beam seed kernel
+static bool seed_beam_active(const SimDev &S)
+{
+    return S.seed_on && S.seed_beam == MITHRA_BEAM_GAUSSIAN && S.seed_corr != nullptr;
+}
+
+// which simulations launch the seed kernel (part of a captured step)
+static std::vector<int> seed_beam_sims(const Batch &b)
+{
+    std::vector<int> v;
+    for (int s = 0; s < b.nsim; ++s)
+        if (seed_beam_active(b.sd[s])) v.push_back(s);
+    return v;
 }
 
 static void fill_optical(const HostSim &h, SimDev &S)
@@ -950,6 +973,8 @@ static void enqueue_step(Batch &b, bool timed)
         }
     };
     mark(K_STENCIL, true);
+    for (int s : seed_beam_sims(b))
+        launch_seed_beam(st, b.d_sims, s, b.sd[s].n[0] * b.sd[s].n[1], b.ar.d_step);
     launch_stencil<R>(st, b.d_sims, b.d_stencil, b.n_stencil, b.ar, b.tile_x, b.tile_y, b.kz,
                       b.fuse_x);
     mark(K_STENCIL, false);
@@ -1336,8 +1361,10 @@ static mithra_status set_seed(Batch &b, int s, const mithra_seed *seed)
         z = *seed;
     }
     HIP_TRY(hipStreamSynchronize(b.stream));
+    const std::vector<int> before = seed_beam_sims(b);
     h.seed = z;
     fill_seed(h, b.sd[s]);
+    if (seed_beam_sims(b) != before) drop_graph(b);
     // the per-simulation block on the device is read at every launch
     HIP_TRY(hipMemcpyAsync(b.d_sims + s, &b.sd[s], sizeof(SimDev), hipMemcpyHostToDevice, b.stream));
     HIP_TRY(hipStreamSynchronize(b.stream));
@@ -1365,24 +1392,53 @@ static mithra_status set_optical(Batch &b, int s, const mithra_seed *wave)
     return MITHRA_OK;
 }
 
-static mithra_status set_optical_beam(Batch &b, int s, const mithra_beam *beam)
+static mithra_status check_beam(const mithra_beam *beam, const char *what)
 {
-    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
-    if (!beam) return fail(MITHRA_EINVAL, "beam is NULL");
+    if (!beam) return fail(MITHRA_EINVAL, "%s: beam is NULL", what);
     if (beam->type != MITHRA_BEAM_PLANE && beam->type != MITHRA_BEAM_GAUSSIAN)
-        return fail(MITHRA_EINVAL, "optical beam: unknown type %d", beam->type);
+        return fail(MITHRA_EINVAL, "%s: unknown beam type %d", what, beam->type);
     if (beam->type == MITHRA_BEAM_GAUSSIAN) {
         for (int a = 0; a < 2; ++a)
             if (!std::isfinite(beam->rayleigh[a]) || !(beam->rayleigh[a] > 0.0))
-                return fail(MITHRA_EINVAL, "optical beam: Rayleigh lengths must be finite and > 0");
+                return fail(MITHRA_EINVAL, "%s: Rayleigh lengths must be finite and > 0", what);
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(beam->focus[a]))
-                return fail(MITHRA_EINVAL, "optical beam: the focus must be finite");
+                return fail(MITHRA_EINVAL, "%s: the focus must be finite", what);
     }
+    return MITHRA_OK;
+}
+
+static mithra_status set_optical_beam(Batch &b, int s, const mithra_beam *beam)
+{
+    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
+    mithra_status st = check_beam(beam, "optical beam");
+    if (st) return st;
     HIP_TRY(hipStreamSynchronize(b.stream));
     HostSim &h = b.hs[s];
     h.beam = *beam;
     fill_optical(h, b.sd[s]);
+    HIP_TRY(hipMemcpyAsync(b.d_sims + s, &b.sd[s], sizeof(SimDev), hipMemcpyHostToDevice, b.stream));
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    return MITHRA_OK;
+}
+
+static mithra_status set_seed_beam(Batch &b, int s, const mithra_beam *beam)
+{
+    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
+    mithra_status st = check_beam(beam, "seed beam");
+    if (st) return st;
+    HostSim &h = b.hs[s];
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    if (beam->type == MITHRA_BEAM_GAUSSIAN && !h.seed_corr) {
+        // corrections of A_x and A_y on planes 2 and 3, every column
+        h.seed_corr = (double *)dev_alloc(b, sizeof(double) * 4 * (size_t)h.mesh.n[0] * h.mesh.n[1],
+                                          b.mem_fixed);
+        if (!h.seed_corr) return fail(MITHRA_ENOMEM, "device allocation of the seed corrections failed");
+    }
+    const std::vector<int> before = seed_beam_sims(b);
+    h.seed_beam = *beam;
+    fill_seed(h, b.sd[s]);
+    if (seed_beam_sims(b) != before) drop_graph(b);
     HIP_TRY(hipMemcpyAsync(b.d_sims + s, &b.sd[s], sizeof(SimDev), hipMemcpyHostToDevice, b.stream));
     HIP_TRY(hipStreamSynchronize(b.stream));
     return MITHRA_OK;
@@ -1754,6 +1810,12 @@ mithra_status mithra_set_optical_beam(mithra_sim *sim, const mithra_beam *beam)
     return set_optical_beam(*sim->b, 0, beam);
 }
 
+mithra_status mithra_set_seed_beam(mithra_sim *sim, const mithra_beam *beam)
+{
+    if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
+    return set_seed_beam(*sim->b, 0, beam);
+}
+
 mithra_status mithra_run(mithra_sim *sim, int64_t nsteps)
 {
     if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
@@ -1913,6 +1975,12 @@ mithra_status mithra_batch_set_optical_beam(mithra_batch *bb, int32_t sim, const
 {
     if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
     return set_optical_beam(*bb->b, sim, beam);
+}
+
+mithra_status mithra_batch_set_seed_beam(mithra_batch *bb, int32_t sim, const mithra_beam *beam)
+{
+    if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
+    return set_seed_beam(*bb->b, sim, beam);
 }
 
 mithra_status mithra_batch_tune(mithra_batch *bb, int32_t trial_steps)

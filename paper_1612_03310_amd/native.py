@@ -38,6 +38,7 @@ ABI_FUNCTIONS = (
     "mithra_batch_destroy", "mithra_set_seed", "mithra_batch_set_seed",
     "mithra_set_optical_undulator", "mithra_batch_set_optical_undulator",
     "mithra_set_optical_beam", "mithra_batch_set_optical_beam",
+    "mithra_set_seed_beam", "mithra_batch_set_seed_beam",
 )
 
 SIGNALS = {"neumann": 0, "gaussian": 1, "secant": 2, "flat-top": 3}
@@ -165,6 +166,8 @@ def load_library(path: str = LIB_PATH):
         "mithra_batch_set_optical_undulator": [P, I32, ctypes.POINTER(Seed)],
         "mithra_set_optical_beam": [P, ctypes.POINTER(Beam)],
         "mithra_batch_set_optical_beam": [P, I32, ctypes.POINTER(Beam)],
+        "mithra_set_seed_beam": [P, ctypes.POINTER(Beam)],
+        "mithra_batch_set_seed_beam": [P, I32, ctypes.POINTER(Beam)],
         "mithra_run": [P, I64],
         "mithra_sync": [P],
         "mithra_get_field": [P, I32, dp],
@@ -356,6 +359,11 @@ class Sim:
         b = make_beam(beam, rayleigh, focus)
         _check(self._lib.mithra_set_optical_beam(self._h, ctypes.byref(b)))
 
+    def set_seed_beam(self, beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)):
+        """Beam of the seed (see mithra_set_seed_beam)."""
+        b = make_beam(beam, rayleigh, focus)
+        _check(self._lib.mithra_set_seed_beam(self._h, ctypes.byref(b)))
+
     def config_diag(self, probe, kp, every=1, capacity=4096, spectrum=False):
         c = DiagCfg()
         for a in range(3):
@@ -481,6 +489,10 @@ class Batch:
     def set_optical_beam(self, s, beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)):
         b = make_beam(beam, rayleigh, focus)
         _check(self._lib.mithra_batch_set_optical_beam(self._h, int(s), ctypes.byref(b)))
+
+    def set_seed_beam(self, s, beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)):
+        b = make_beam(beam, rayleigh, focus)
+        _check(self._lib.mithra_batch_set_seed_beam(self._h, int(s), ctypes.byref(b)))
 
     def config_diag(self, s, probe, kp, every=1, capacity=4096, spectrum=False):
         c = DiagCfg()

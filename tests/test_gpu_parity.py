@@ -219,6 +219,89 @@ def test_seed_plane_wave_matches_oracle(courant, precision):
             assert np.max(np.abs(g)) == 0.0, name
 
 
+def _gaussian_seed_case(precision, courant=0.9):
+    """A round, nearly collimated Gaussian beam (k z_R = 100, waist 5.6
+    cells) entering through the TF/SF planes, focused 60 cells in; Mur on
+    every face."""
+    dz = 1e-6
+    n, d = (40, 40, 100), (8 * dz, 8 * dz, dz)
+    origin = (-156 * dz, -156 * dz, 0.0)
+    lam, tau = 20 * dz, 15 * dz / C
+    k = 2 * np.pi / lam
+    zr = 100.0 / k
+    seed = dict(polarization=(0.6, 0.8), frequency=C / lam, t0=4 * tau, tau=tau, cep=0.3,
+                signal="gaussian", z_ref=0.0)
+    beam = dict(beam="gaussian", rayleigh=(zr, 0.7 * zr), focus=(8e-6, -5e-6, 60 * dz))
+    orc = oracle.OracleSim(n, d, origin, courant=courant, bc=(0, 0, 0), K=0.0, gamma_beam=50.0)
+    orc.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+    sim = native.Sim(n, d, origin, courant=courant, bc=(0, 0, 0), K=0.0, gamma_beam=50.0,
+                     precision=precision)
+    sim.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+    return orc, sim, seed, beam
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_gaussian_seed_matches_oracle(precision):
+    """The Gaussian-beam seed: 30 steps as a plane wave, then the beam shape
+    switched on (the captured step is rebuilt with the corrections kernel)
+    and 60 more steps; all four potentials against the oracle, which the
+    beam shape moves far from the plane-wave run."""
+    orc, sim, seed, beam = _gaussian_seed_case(precision)
+    plane, _, _, _ = _gaussian_seed_case(precision)
+    say("case gaussian seed", precision, beam)
+    for o in (orc, plane):
+        o.set_seed(1e-3, **seed)
+        o.step(30)
+    sim.set_seed(1e-3, **seed)
+    sim.run(30)
+    sim.sync()
+    orc.set_seed_beam(**beam)
+    sim.set_seed_beam(**beam)
+    orc.step(60)
+    plane.step(60)
+    sim.run(60)
+    sim.sync()
+    tol = TOL64 if precision == "f64" else 1e-4
+    for c, name in enumerate(POT):
+        g, o = sim.get_field(name), orc.pot(c, "cur")
+        if c < 2:
+            assert np.max(np.abs(o)) > 1e-4
+            assert rel_l2(g, o) < tol, (name, rel_l2(g, o))
+            shaped = rel_l2(o, plane.pot(c, "cur"))
+            say(name, "rel-L2", rel_l2(g, o), "beam against plane wave", shaped)
+            assert shaped > 0.1
+        else:
+            assert np.max(np.abs(g)) == 0.0, name
+
+
+def test_batch_with_gaussian_and_plane_seeds_equals_separate_runs():
+    _, _, seed, beam = _gaussian_seed_case("f64")
+    dz = 1e-6
+    n, d = (40, 40, 100), (8 * dz, 8 * dz, dz)
+    origin = (-156 * dz, -156 * dz, 0.0)
+    mesh = native.make_mesh(n, d, origin, 0.9, -1.0, 1, 1, (0, 0, 0))
+    und = native.make_undulator(0.015, 0.0, 50.0, 0.0)
+    b = native.Batch([mesh, mesh], [und, und], precision="f64")
+    for s in range(2):
+        b.set_particles(s, np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+        b.set_seed(s, 1e-3, **seed)
+    b.set_seed_beam(1, **beam)
+    b.run(70)
+    b.sync()
+    for s in range(2):
+        sim = native.Sim(n, d, origin, courant=0.9, bc=(0, 0, 0), K=0.0, gamma_beam=50.0)
+        sim.set_particles(np.zeros((0, 3)), np.zeros((0, 3)), -QE, ME)
+        sim.set_seed(1e-3, **seed)
+        if s == 1:
+            sim.set_seed_beam(**beam)
+        sim.run(70)
+        sim.sync()
+        for name in ("Ax", "Ay"):
+            assert np.array_equal(b.get_field(s, name), sim.get_field(name)), (s, name)
+    assert not np.array_equal(b.get_field(0, "Ax"), b.get_field(1, "Ax"))
+    b.close()
+
+
 def test_seeded_full_loop_f64():
     """A seed and a bunch together, Mur on every face: the whole state and
     the diagnostics against the oracle."""
