@@ -258,7 +258,7 @@ mithra_status mithra_set_optical_undulator(mithra_sim *sim, const mithra_seed *w
    the analytic signal (envelope times exp(i(2 pi f x + cep))),
    U = u(xi, z_par) u(eta, z_perp), u(v, z_R) = sqrt(i z_R / q)
    exp(-i k v^2 / (2 q)), q = (z_f - z) + i z_R, k = 2 pi f / c, xi and eta
-   the distances from the axis along p and along z x p; E = -dA/dt,
+   the distances from the axis along p/|p| and along z x p/|p|; E = -dA/dt,
    B = curl A (no scalar potential; Gauss's and Ampere's laws then hold to
    the paraxial order 1/(k z_R)).  Waist radius sqrt(2 z_R / k) at the
    focus.  Type 0 is the plane wave (default).  Kept when the wave itself
