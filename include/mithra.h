@@ -229,6 +229,15 @@ mithra_status mithra_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
 mithra_status mithra_set_particles(mithra_sim *sim, int64_t np, const double *pos,
                                    const double *u, double q_macro, double m_macro);
 
+/* Test fixture: a static background charge density rho_bg [C/m^3] at the
+   vertices (n[0]*n[1]*n[2] doubles, x fastest; copied), added to rho in the
+   source of phi of eq. (updateEquation) at every step, e.g. the negative of
+   the initial bunch charge for a neutral system.  The diagnostics and the
+   deposited rho do not include it.  NULL removes it.  EINVAL for a value that
+   is not finite; ENOMEM if the two device arrays (the background and
+   rho + background) cannot be allocated. */
+mithra_status mithra_set_background(mithra_sim *sim, const double *rho_bg);
+
 mithra_status mithra_config_diag(mithra_sim *sim, const mithra_diag_cfg *cfg);
 
 /* Set (or, with amplitude 0 or seed == NULL, clear) the seed plane wave of

@@ -134,6 +134,18 @@ __global__ __launch_bounds__(BLOCK) void k_seed_beam(const SimDev *__restrict__ 
     S.seed_corr[(long long)(2 * comp + 1) * ncol + col] = pull(2);
 }
 
+// rho + background of one simulation, for the source of phi this step
+template <typename R>
+__global__ __launch_bounds__(BLOCK) void k_background(const SimDev *__restrict__ sims, int sim,
+                                                      long long ncell, Arena ar)
+{
+    const long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= ncell) return;
+    const SimDev &S = sims[sim];
+    const R *rho = (const R *)ar.rho[*ar.d_step & 1] + S.cell0;
+    ((R *)S.rho_bg)[c] = rho[c] + ((const R *)S.bg)[c];
+}
+
 // Rate ds/dt of the optical undulator's signal (the seed's four shapes with
 // the undulator's parameters): carrier C = cos(w x + cep), envelope
 // g = exp(-2 ln2 x^2 / tau^2), x = t - t0.
@@ -414,8 +426,10 @@ __global__ __launch_bounds__(TX *TY) void k_stencil(const SimDev *__restrict__ s
     const R *__restrict__ P = (const R *)ar.pot[step % 3][comp] + S.cell0;
     const R *__restrict__ Q = (const R *)ar.pot[(step + 2) % 3][comp] + S.cell0;
     R *__restrict__ Rn = (R *)ar.pot[(step + 1) % 3][comp] + S.cell0;
+    // with a static background charge, phi's source is rho + background
     const R *__restrict__ Src =
-        (comp < 3 ? (const R *)ar.J[comp] : (const R *)ar.rho[step & 1]) + S.cell0;
+        comp < 3 ? (const R *)ar.J[comp] + S.cell0
+                 : (S.rho_bg ? (const R *)S.rho_bg : (const R *)ar.rho[step & 1] + S.cell0);
 
     int lo[3], hi[3];
 #pragma unroll
@@ -2166,6 +2180,14 @@ void launch_seed_beam(hipStream_t st, const SimDev *sims, int sim, int ncol,
 }
 
 template <typename R>
+void launch_background(hipStream_t st, const SimDev *sims, int sim, long long ncell,
+                       const Arena &ar)
+{
+    hipLaunchKernelGGL((k_background<R>), dim3((unsigned)((ncell + BLOCK - 1) / BLOCK)),
+                       dim3(BLOCK), 0, st, sims, sim, ncell, ar);
+}
+
+template <typename R>
 void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long ncell,
                           const Arena &ar, double *out6)
 {
@@ -2188,7 +2210,9 @@ void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long
     template void launch_diag<R>(hipStream_t, const SimDev *, int, const int2 *, int,           \
                                  const int2 *, int, const int2 *, int, const Arena &);          \
     template void launch_vertex_fields<R>(hipStream_t, const SimDev *, int, long long,          \
-                                          const Arena &, double *);
+                                          const Arena &, double *);                             \
+    template void launch_background<R>(hipStream_t, const SimDev *, int, long long,             \
+                                       const Arena &);
 
 MITHRA_INSTANTIATE(float)
 MITHRA_INSTANTIATE(double)

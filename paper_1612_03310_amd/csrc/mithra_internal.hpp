@@ -86,6 +86,10 @@ struct SimDev {
     int seed_beam;
     double seed_zr[2], seed_focus[3], seed_k;
     double *seed_corr;
+    // static background charge density at the vertices (R, this simulation's
+    // cells) and the sum rho + background the potential update of phi reads
+    // (written before it each step); both null when there is none
+    void *bg, *rho_bg;
     // optical undulator: a plane wave towards -z, A = a p s(t + (z - z_ref)/c),
     // in place of the static undulator (same signal shapes as the seed)
     int opt_on, opt_sig;
@@ -143,6 +147,10 @@ void launch_stencil(hipStream_t st, const SimDev *sims, const int4 *items, int n
 // step (ncol = nx * ny columns), before its potential update
 void launch_seed_beam(hipStream_t st, const SimDev *sims, int sim, int ncol,
                       const long long *d_step);
+// background charge: rho + background of simulation `sim` for this step
+template <typename R>
+void launch_background(hipStream_t st, const SimDev *sims, int sim, long long ncell,
+                       const Arena &ar);
 template <typename R>
 void launch_boundary(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg,
                      long long total, const Arena &ar);

@@ -59,6 +59,8 @@ struct HostSim {
     mithra_beam beam{};     // its beam (type 0: plane wave)
     mithra_beam seed_beam{};        // the seed's beam (type 0: plane wave)
     double *seed_corr = nullptr;    // device: Gaussian-beam seed corrections
+    bool has_bg = false;            // a static background charge is set
+    void *bg = nullptr, *rho_bg = nullptr;  // device: background, rho + background
     double dt, dtb, A, gamma0, beta0, B0, ku;
     bool loaded = false;
     double q = 0.0, m = 0.0;
@@ -413,6 +415,17 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     S.mesh_every = h.diag.mesh_diag_every;
     S.ring_cap = h.diag.capacity;
     S.spec_on = h.diag.power_spectrum ? 1 : 0;
+    S.bg = h.has_bg ? h.bg : nullptr;
+    S.rho_bg = h.has_bg ? h.rho_bg : nullptr;
+}
+
+// which simulations add a background charge before the potential update
+static std::vector<int> background_sims(const Batch &b)
+{
+    std::vector<int> v;
+    for (int s = 0; s < b.nsim; ++s)
+        if (b.sd[s].rho_bg) v.push_back(s);
+    return v;
 }
 
 static int tile_key_host(const SimDev &S, int ci, int cj, int ck)
@@ -975,6 +988,9 @@ static void enqueue_step(Batch &b, bool timed)
     mark(K_STENCIL, true);
     for (int s : seed_beam_sims(b))
         launch_seed_beam(st, b.d_sims, s, b.sd[s].n[0] * b.sd[s].n[1], b.ar.d_step);
+    for (int s : background_sims(b))
+        launch_background<R>(st, b.d_sims, s, (long long)b.sd[s].n[0] * b.sd[s].n[1] * b.sd[s].n[2],
+                             b.ar);
     launch_stencil<R>(st, b.d_sims, b.d_stencil, b.n_stencil, b.ar, b.tile_x, b.tile_y, b.kz,
                       b.fuse_x);
     mark(K_STENCIL, false);
@@ -1444,6 +1460,50 @@ static mithra_status set_seed_beam(Batch &b, int s, const mithra_beam *beam)
     return MITHRA_OK;
 }
 
+template <typename R>
+static mithra_status upload_background(Batch &b, HostSim &h, const double *rho)
+{
+    const size_t ncell = (size_t)h.mesh.n[0] * h.mesh.n[1] * h.mesh.n[2];
+    std::vector<R> v(ncell);
+    for (size_t c = 0; c < ncell; ++c) v[c] = (R)rho[c];
+    HIP_TRY(hipMemcpy(h.bg, v.data(), sizeof(R) * ncell, hipMemcpyHostToDevice));
+    return MITHRA_OK;
+}
+
+static mithra_status set_background(Batch &b, int s, const double *rho)
+{
+    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
+    HostSim &h = b.hs[s];
+    const size_t ncell = (size_t)h.mesh.n[0] * h.mesh.n[1] * h.mesh.n[2];
+    if (rho)
+        for (size_t c = 0; c < ncell; ++c)
+            if (!std::isfinite(rho[c]))
+                return fail(MITHRA_EINVAL, "background: value %zu is not finite", c);
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    if (rho && !h.bg) {
+        h.bg = dev_alloc(b, b.rs * ncell, b.mem_fixed);
+        h.rho_bg = h.bg ? dev_alloc(b, b.rs * ncell, b.mem_fixed) : nullptr;
+        if (!h.bg || !h.rho_bg) {
+            h.bg = h.rho_bg = nullptr;  // released with the batch
+            return fail(MITHRA_ENOMEM, "device allocation of the background failed");
+        }
+    }
+    if (rho) {
+        mithra_status st = b.prec == MITHRA_F64 ? upload_background<double>(b, h, rho)
+                                                : upload_background<float>(b, h, rho);
+        if (st) return st;
+    }
+    const std::vector<int> before = background_sims(b);
+    h.has_bg = rho != nullptr;
+    SimDev &S = b.sd[s];
+    S.bg = h.has_bg ? h.bg : nullptr;
+    S.rho_bg = h.has_bg ? h.rho_bg : nullptr;
+    if (background_sims(b) != before) drop_graph(b);
+    HIP_TRY(hipMemcpyAsync(b.d_sims + s, &S, sizeof(SimDev), hipMemcpyHostToDevice, b.stream));
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    return MITHRA_OK;
+}
+
 static mithra_status get_info(Batch &b, int s, mithra_info *info)
 {
     if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
@@ -1808,6 +1868,12 @@ mithra_status mithra_set_optical_beam(mithra_sim *sim, const mithra_beam *beam)
 {
     if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
     return set_optical_beam(*sim->b, 0, beam);
+}
+
+mithra_status mithra_set_background(mithra_sim *sim, const double *rho)
+{
+    if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
+    return set_background(*sim->b, 0, rho);
 }
 
 mithra_status mithra_set_seed_beam(mithra_sim *sim, const mithra_beam *beam)

@@ -38,7 +38,7 @@ ABI_FUNCTIONS = (
     "mithra_batch_destroy", "mithra_set_seed", "mithra_batch_set_seed",
     "mithra_set_optical_undulator", "mithra_batch_set_optical_undulator",
     "mithra_set_optical_beam", "mithra_batch_set_optical_beam",
-    "mithra_set_seed_beam", "mithra_batch_set_seed_beam",
+    "mithra_set_seed_beam", "mithra_batch_set_seed_beam", "mithra_set_background",
 )
 
 SIGNALS = {"neumann": 0, "gaussian": 1, "secant": 2, "flat-top": 3}
@@ -167,6 +167,7 @@ def load_library(path: str = LIB_PATH):
         "mithra_set_optical_beam": [P, ctypes.POINTER(Beam)],
         "mithra_batch_set_optical_beam": [P, I32, ctypes.POINTER(Beam)],
         "mithra_set_seed_beam": [P, ctypes.POINTER(Beam)],
+        "mithra_set_background": [P, dp],
         "mithra_batch_set_seed_beam": [P, I32, ctypes.POINTER(Beam)],
         "mithra_run": [P, I64],
         "mithra_sync": [P],
@@ -358,6 +359,16 @@ class Sim:
         """Beam of the optical undulator (see mithra_set_optical_beam)."""
         b = make_beam(beam, rayleigh, focus)
         _check(self._lib.mithra_set_optical_beam(self._h, ctypes.byref(b)))
+
+    def set_background(self, rho):
+        """Static background charge density at the vertices, (nz, ny, nx) or
+        None to remove it (see mithra_set_background)."""
+        if rho is None:
+            _check(self._lib.mithra_set_background(self._h, None))
+            return
+        nx, ny, nz = self.n
+        a = np.ascontiguousarray(rho, dtype=np.float64).reshape(nz, ny, nx)
+        _check(self._lib.mithra_set_background(self._h, _dptr(a)))
 
     def set_seed_beam(self, beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)):
         """Beam of the seed (see mithra_set_seed_beam)."""

@@ -302,6 +302,53 @@ def test_batch_with_gaussian_and_plane_seeds_equals_separate_runs():
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_background_charge_matches_oracle(precision):
+    """The tiny bunch with a static background equal to minus its initial
+    charge density (a neutral system): 60 steps against the oracle with the
+    same background; phi differs far from the run without it."""
+    w = W.config(0, steps=60)
+    orc = oracle.from_workload(w)
+    bg = -orc.rho.copy()
+    orc.set_background(bg)
+    bare = oracle.from_workload(w)
+    sim = native.sim_from_workload(w, precision=precision, every=1)
+    sim.set_background(bg)
+    sim.run(60)
+    sim.sync()
+    orc.step(60)
+    bare.step(60)
+    if precision == "f64":
+        compare_state(sim, orc, TOL64, "background")
+        compare_diag(sim.get_diag(), orc.diag(), TOL64, "background")
+    else:
+        err = rel_l2(sim.get_field("phi"), orc.pot(3, "cur"))
+        say("background f32 phi rel-L2", err)
+        assert err < 1e-4, err
+    moved = rel_l2(orc.pot(3, "cur"), bare.pot(3, "cur"))
+    say("phi, with background against without", moved)
+    assert moved > 0.5
+    with pytest.raises(native.MithraError) as e:
+        bad = bg.copy()
+        bad.flat[5] = np.nan
+        sim.set_background(bad)
+    assert e.value.status == native.EINVAL
+
+
+def test_background_removed_is_the_plain_run_bitwise():
+    w = W.config(0, steps=20)
+    outs = []
+    for toggle in (False, True):
+        sim = native.sim_from_workload(w, precision="f64")
+        if toggle:
+            sim.set_background(np.ones((w.n[2], w.n[1], w.n[0])))
+            sim.set_background(None)
+        sim.run(20)
+        sim.sync()
+        outs.append((sim.get_field("phi"), sim.get_diag().tobytes()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
 def test_seeded_full_loop_f64():
     """A seed and a bunch together, Mur on every face: the whole state and
     the diagnostics against the oracle."""
