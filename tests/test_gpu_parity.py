@@ -763,7 +763,7 @@ def test_precision_config_f32_split():
         "phi": rel_l2(sim.get_field("phi"), orc.pot(3, "cur")),
     }
     # a particle lost at the mesh edge takes its charge along, which the
-    # continuity residual of that step reports; judge the other steps
+    # continuity residual of that step reports; check the other steps
     steady = np.concatenate([[gd["lost"][0] == 0], np.diff(gd["lost"]) == 0])
     cont = np.max(gd["continuity_residual"][steady])
     say("f32 split", errs, other, "continuity", cont, "lost", gd["lost"][-1], orc.lost)
