@@ -284,7 +284,7 @@ def main():
                          "default) or large (256x256x2048, 16.8M particles, f32 split)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(the z-slab sharding is a design note only); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
