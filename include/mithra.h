@@ -14,7 +14,13 @@
  *   4. charge and current deposition (section "Current Deposition",
  *      eq. (currentIntegral)), charge-conserving;
  *   5. double-precision diagnostics (charge, continuity, radiated power,
- *      energies, field probe).
+ *      energies, field probe, bunching factor, power at the harmonics).
+ *
+ * Also: second-order Mur boundaries; a seed brought in through the
+ * total-field/scattered-field planes and an optical undulator, each a plane
+ * wave or a Gaussian beam; a static background charge (test fixture);
+ * checkpoints; batches of independent simulations replayed from one
+ * captured HIP graph, with a tile autotuner.
  *
  * Conventions used by every call:
  *   - SI units in and out; the rest frame of the bunch (the frame moving with
