@@ -20,11 +20,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mithra_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-NDIAG = 24
+NDIAG = 27
 DIAG_COLUMNS = ("step", "t", "total_charge", "continuity_residual", "power",
                 "field_energy", "kinetic_energy", "Ex", "Ey", "Ez", "Bx", "By",
                 "Bz", "lost", "nonfinite", "spare", "bunching1", "bunching2",
-                "bunching3", "spare2", "power_h1", "power_h2", "power_h3", "spare3")
+                "bunching3", "spare2", "power_h1", "power_h2", "power_h3", "spare3",
+                "power_extra1", "power_extra2", "power_extra3")
 
 _lib = None
 
@@ -68,6 +69,7 @@ def _load():
     lib.orc_seed_signal.argtypes = [P, D]
     lib.orc_seed_signal.restype = D
     lib.orc_config_diag.argtypes = [P, I, I, I, I]
+    lib.orc_config_extra_planes.argtypes = [P, I, I, I]
     for name in ("orc_field_update", "orc_vertex_fields", "orc_push", "orc_deposit",
                  "orc_rotate"):
         getattr(lib, name).argtypes = [P]
@@ -183,8 +185,10 @@ class OracleSim:
                                        float(rayleigh[0]), float(rayleigh[1]), float(focus[0]),
                                        float(focus[1]), float(focus[2]))
 
-    def config_diag(self, probe, kp):
+    def config_diag(self, probe, kp, extra_planes=()):
         self._lib.orc_config_diag(self._h, int(probe[0]), int(probe[1]), int(probe[2]), int(kp))
+        k = list(extra_planes) + [-1] * (3 - len(extra_planes))
+        self._lib.orc_config_extra_planes(self._h, int(k[0]), int(k[1]), int(k[2]))
 
     # ---- stepping ----------------------------------------------------------
     def step(self, nsteps=1):

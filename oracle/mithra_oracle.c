@@ -93,7 +93,7 @@
 #define ORC_MU0 (1.0 / (ORC_EPS0 * ORC_C * ORC_C))
 #define ORC_PI 3.14159265358979323846
 
-#define ORC_NDIAG 24
+#define ORC_NDIAG 27
 
 typedef struct orc_sim {
     int n[3];
@@ -135,6 +135,7 @@ typedef struct orc_sim {
     int nonfinite_u;
     /* diagnostics */
     int probe[3], kp;
+    int kp_extra[3]; /* further sampling plates (-1: none), power only */
     double *diag;
     long ndiag, cap;
     /* running DFT of Ex, Ey, Bx, By on the power plane at h omega_1 (h = 1..3):
@@ -265,6 +266,7 @@ orc_sim *orc_create(const int n[3], const double d[3], const double origin[3],
     s->probe[1] = n[1] / 2;
     s->probe[2] = n[2] / 2;
     s->kp = n[2] / 2;
+    for (int e = 0; e < 3; e++) s->kp_extra[e] = -1;
     s->cap = 1024;
     s->diag = (double *)malloc(sizeof(double) * ORC_NDIAG * s->cap);
     s->spec = (double *)calloc((size_t)n[0] * n[1] * 24, sizeof(double));
@@ -307,6 +309,15 @@ void orc_config_diag(orc_sim *s, int pi, int pj, int pk, int kp)
     s->probe[1] = pj;
     s->probe[2] = pk;
     s->kp = kp;
+}
+
+/* Further sampling plates (section "FEL-OUTPUT": the plate distance may be
+   repeated): the radiated power through planes k1..k3, -1 for none. */
+void orc_config_extra_planes(orc_sim *s, int k1, int k2, int k3)
+{
+    s->kp_extra[0] = k1;
+    s->kp_extra[1] = k2;
+    s->kp_extra[2] = k3;
 }
 
 /* ---- cloud-in-cell weights (eq. (fieldInterpolation), reading R4) ------ */
@@ -1013,7 +1024,8 @@ void orc_deposit(orc_sim *s)
    row: step, t, total charge, continuity residual, radiated power through the
    plane k = kp, field energy, kinetic energy, probe E (3), probe B (3), lost,
    non-finite flag, spare, bunching factor at harmonics 1..3, spare, power at
-   the harmonics 1..3 through the plane k = kp, spare.
+   the harmonics 1..3 through the plane k = kp, spare, radiated power through
+   the further plates (0 where none).
 
    Bunching factor (the quantity <exp(j k z)> of section "Bunching factor",
    reading R21): b_h = |(1/N) sum_p exp(i h K z_p)| over the N live particles,
@@ -1090,6 +1102,21 @@ static void bunching(const orc_sim *s, double *b)
     for (int h = 0; h < 3; h++) b[h] = n > 0 ? sqrt(re[h] * re[h] + im[h] * im[h]) / (double)n : 0.0;
 }
 
+/* radiated power: the flux of the Poynting vector of the self field through
+   the plane k, over the interior points */
+static double plane_power(const orc_sim *s, int k)
+{
+    int lo[2], hi[2];
+    for (int a = 0; a < 2; a++) interior(s, a, &lo[a], &hi[a]);
+    double power = 0.0;
+    for (int j = lo[1]; j <= hi[1]; j++)
+        for (int i = lo[0]; i <= hi[0]; i++) {
+            long p = IX(s, i, j, k);
+            power += (s->E[0][p] * s->B[1][p] - s->E[1][p] * s->B[0][p]) / ORC_MU0 * s->d[0] * s->d[1];
+        }
+    return power;
+}
+
 void orc_diag_row(orc_sim *s, double *row)
 {
     int lo[3], hi[3];
@@ -1110,12 +1137,7 @@ void orc_diag_row(orc_sim *s, double *row)
                 double r = fabs(s->rho[p] - s->rho_prev[p] + s->dt * div);
                 if (r > resmax) resmax = r;
             }
-    double power = 0.0;
-    for (int j = lo[1]; j <= hi[1]; j++)
-        for (int i = lo[0]; i <= hi[0]; i++) {
-            long p = IX(s, i, j, s->kp);
-            power += (s->E[0][p] * s->B[1][p] - s->E[1][p] * s->B[0][p]) / ORC_MU0 * dx * dy;
-        }
+    double power = plane_power(s, s->kp);
     double wf = 0.0;
     for (int k = lo[2]; k <= hi[2]; k++)
         for (int j = lo[1]; j <= hi[1]; j++)
@@ -1153,6 +1175,7 @@ void orc_diag_row(orc_sim *s, double *row)
     row[19] = 0.0;
     harmonic_power(s, &row[20]);
     row[23] = 0.0;
+    for (int e = 0; e < 3; e++) row[24 + e] = s->kp_extra[e] >= 0 ? plane_power(s, s->kp_extra[e]) : 0.0;
 }
 
 /* ---- O11: rotate the time levels ------------------------------------------ */

@@ -1403,3 +1403,27 @@ def test_gaussian_seed_corrections_are_the_update_of_the_incident_field():
             want = plain.pot(comp, "next")[dst, 1:-1, 1:-1]
             got = seeded.pot(comp, "next")[dst, 1:-1, 1:-1]
             assert np.allclose(sign * got, want, rtol=0, atol=1e-13 * np.abs(want).max()), comp
+
+
+# ---- further sampling plates (section "FEL-OUTPUT") ---------------------------
+
+def test_extra_plates_see_the_seed_pulse_later_by_its_travel_time():
+    """At c dt = dz a transversely uniform pulse moves one cell per step, so
+    the power through a plate m cells further on is the main plate's power m
+    steps later, to round-off; a further plate on the main plane repeats the
+    main plane's power exactly, and unused plates read zero."""
+    dz = 1e-6
+    d, n = (2 * dz, 2 * dz, dz), (4, 4, 240)
+    sim = oracle.OracleSim(n, d, (0.0, 0.0, 0.0), courant=1.0, bc=(1, 1, 0), K=0.0)
+    _empty(sim)
+    tau = 15 * dz / C
+    sim.set_seed(1e-3, (0.6, 0.8), C / (20 * dz), 4 * tau, tau, 0.3, "gaussian", z_ref=0.0)
+    sim.config_diag((1, 1, 50), 60, extra_planes=(60, 100))
+    sim.step(230)
+    rows = sim.diag()
+    main, same, far, unused = rows[:, 4], rows[:, 24], rows[:, 25], rows[:, 26]
+    assert np.array_equal(main, same)
+    assert not unused.any()
+    assert np.abs(main).max() > 0
+    shift = 40
+    assert np.allclose(far[shift:], main[:-shift], rtol=0, atol=1e-10 * np.abs(main).max())
