@@ -163,6 +163,9 @@ typedef struct {
     int32_t power_spectrum;  /* 1: sample the running DFT of the power plane each step for
                                 mithra_diag_row.power_harmonic (FEL output); 0 (default):
                                 off, power_harmonic = 0.  Changes only before the first step */
+    int32_t extra_planes[3]; /* z indices of further sampling plates (section "FEL-OUTPUT":
+                                the plate distance may be repeated), -1 for none: the
+                                radiated power through each, mithra_diag_row.power_extra */
 } mithra_diag_cfg;
 
 /* One row per completed step s (fields at t = (s+1/2) dt). */
@@ -190,6 +193,8 @@ typedef struct {
                                    (2/T^2) sum Re(F_Ex F_By* - F_Ey F_Bx*)/mu0 dx dy with
                                    F(omega) = sum_n f(t_n) exp(-i omega t_n) dt the running
                                    DFT of the plane's vertex fields and T = (s+1) dt */
+    double power_extra[3];      /* radiated power [W] through the further plates of
+                                   mithra_diag_cfg.extra_planes, as power; 0 where none */
 } mithra_diag_row;
 
 /* Derived constants and bookkeeping of a simulation. */

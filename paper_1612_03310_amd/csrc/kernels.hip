@@ -1798,21 +1798,25 @@ __device__ __forceinline__ void diag_plane(const SimDev *__restrict__ sims, int2
     // Per block of plane points: the Poynting flux, and the running DFT of
     // Ex, Ey, Bx, By at h omega_1 (h = 1, 2, 3) advanced by this step's sample
     // at t = (s + 1/2) dt, with each point's Re(F_Ex F_By* - F_Ey F_Bx*).
+    // item y = plate * nb_plane + block; plate 0 is the main plane (power and
+    // spectrum), plates 1.. the further ones (power only)
     const SimDev &S = sims[it.x];
     const long long step = *ar.d_step;
     const FieldPtrs<R> f = field_ptrs<R>(S, ar, step % 3, (step + 1) % 3, (int)(step % 3));
-    const int e = it.y * BLOCK + threadIdx.x;
+    const int plate = it.y / S.nb_plane, blk = it.y - plate * S.nb_plane;
+    const int kz = plate == 0 ? S.kp : S.kp_extra[plate - 1];
+    const int e = blk * BLOCK + threadIdx.x;
     const long long npl = (long long)S.n[0] * S.n[1];
     double t[PLANE_TERMS] = {0.0, 0.0, 0.0, 0.0};
     if (e < npl) {
         const int i = e % S.n[0], j = e / S.n[0];
-        if (vertex_valid(S, i, j, S.kp)) {
+        if (vertex_valid(S, i, j, kz)) {
             R E[3], B[3];
-            vertex_EB<R>(S, f, i, j, S.kp, E, B);
+            vertex_EB<R>(S, f, i, j, kz, E, B);
             t[0] = (double)E[0] * (double)B[1] - (double)E[1] * (double)B[0];
             const double fv[4] = {(double)E[0], (double)E[1], (double)B[0], (double)B[1]};
             const double tm = ((double)step + 0.5) * S.dt;
-            if (S.spec_on) {
+            if (S.spec_on && plate == 0) {
                 // the sums are stored sum-major (sum q of point e at q * npl + e),
                 // so each access is one contiguous span per wavefront; one
                 // harmonic (8 sums) at a time keeps the register count of the
@@ -1844,10 +1848,16 @@ __device__ __forceinline__ void diag_plane(const SimDev *__restrict__ sims, int2
         }
     }
     __shared__ double sh[BLOCK];
+    if (plate > 0) {
+        const double tot = block_sum(t[0], sh);
+        if (threadIdx.x == 0)
+            ar.partial[S.part_extra0 + (long long)(plate - 1) * S.nb_plane + blk] = tot;
+        return;
+    }
     const int nterms = S.spec_on ? PLANE_TERMS : 1;  // uniform over the block
     for (int q = 0; q < nterms; ++q) {
         const double tot = block_sum(t[q], sh);
-        if (threadIdx.x == 0) ar.partial[S.part_plane0 + (long long)PLANE_TERMS * it.y + q] = tot;
+        if (threadIdx.x == 0) ar.partial[S.part_plane0 + (long long)PLANE_TERMS * blk + q] = tot;
     }
 }
 
@@ -1969,6 +1979,13 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
 #pragma unroll
     for (int q = 0; q < PLANE_TERMS; ++q) pt[q] = block_sum(pt[q], sh);
     const double pw = pt[0];
+    double px[3] = {0.0, 0.0, 0.0};
+    for (int p = 0; p < S.n_extra; ++p) {  // uniform over the block
+        double v = 0.0;
+        for (int b = threadIdx.x; b < S.nb_plane; b += BLOCK)
+            v += ar.partial[S.part_extra0 + (long long)p * S.nb_plane + b];
+        px[p] = block_sum(v, sh);
+    }
     double q = 0.0, wf = 0.0, rmax = 0.0, res = 0.0, kt[KIN_TERMS];
 #pragma unroll
     for (int t = 0; t < KIN_TERMS; ++t) kt[t] = 0.0;
@@ -2029,6 +2046,7 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
         for (int h = 0; h < 3; ++h)
             row[20 + h] = S.spec_on ? 2.0 / (T * T) * pt[1 + h] * S.dxdy_mu0 : 0.0;
         row[23] = 0.0;
+        for (int p = 0; p < 3; ++p) row[24 + p] = p < S.n_extra ? px[p] * S.dxdy_mu0 : 0.0;
         // every block has read the step counter before it counts itself done
         if (atomicAdd(ar.fin_ctr, 1) == (int)gridDim.x - 1) {
             *ar.fin_ctr = 0;

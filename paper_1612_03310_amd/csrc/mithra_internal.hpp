@@ -15,7 +15,7 @@ constexpr int TILE = 8;
 constexpr int TILE_CELLS = TILE * TILE * TILE;
 constexpr int TILE_VERT = TILE + 1;  // vertices per axis a tile's cells touch
 constexpr int NKINDS = 7;            // kernel kinds for timing
-constexpr int NDIAG = 24;            // doubles per diagnostic row
+constexpr int NDIAG = 27;            // doubles per diagnostic row
 constexpr int BLOCK = 256;
 constexpr int SCAN_PER_THREAD = 16;
 constexpr int SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
@@ -50,6 +50,8 @@ struct SimDev {
     int ring_cap;
     long long ring0;    // first row of this simulation in the ring arena
     int part_plane0, nb_plane;  // partial-sum slots
+    int kp_extra[3], n_extra;   // further sampling plates (power only), how many
+    int part_extra0;            // their partial-sum slots, nb_plane per plate
     int part_mesh0, nb_mesh;
     int part_kin0, nb_kin;
     // potential update, eq. (updateEquation) in the regrouped form

@@ -415,6 +415,9 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     S.mesh_every = h.diag.mesh_diag_every;
     S.ring_cap = h.diag.capacity;
     S.spec_on = h.diag.power_spectrum ? 1 : 0;
+    S.n_extra = 0;
+    for (int e = 0; e < 3; ++e)
+        if (h.diag.extra_planes[e] >= 0) S.kp_extra[S.n_extra++] = h.diag.extra_planes[e];
     S.bg = h.has_bg ? h.bg : nullptr;
     S.rho_bg = h.has_bg ? h.rho_bg : nullptr;
 }
@@ -591,11 +594,14 @@ static mithra_status build_tables(Batch &b)
                                     : 0;
         S.part_plane0 = slot;
         slot += PLANE_TERMS * S.nb_plane;
+        S.part_extra0 = slot;
+        slot += S.n_extra * S.nb_plane;
         S.part_mesh0 = slot;
         slot += 4 * S.nb_mesh;
         S.part_kin0 = slot;
         slot += KIN_TERMS * S.nb_kin;
-        for (int i = 0; i < S.nb_plane; ++i) plane.push_back(make_int2(s, i));
+        // plate p (0 the main one) block i is item y = p * nb_plane + i
+        for (int i = 0; i < (1 + S.n_extra) * S.nb_plane; ++i) plane.push_back(make_int2(s, i));
         for (int i = 0; i < S.nb_mesh; ++i) mesh.push_back(make_int2(s, i));
         for (int i = 0; i < S.nb_kin; ++i) kin.push_back(make_int2(s, i));
     }
@@ -694,6 +700,7 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
         h.diag.power_plane_k = h.mesh.n[2] / 2;
         h.diag.mesh_diag_every = 1;
         h.diag.capacity = 4096;
+        for (int e = 0; e < 3; ++e) h.diag.extra_planes[e] = -1;
         derive(h);
         SimDev &S = b->sd[s];
         std::memset(&S, 0, sizeof S);
@@ -1289,6 +1296,7 @@ static mithra_status get_diag(Batch &b, int s, mithra_diag_row *rows, int64_t ca
         o.has_mesh_terms = (int32_t)v[15];
         for (int h = 0; h < 3; ++h) o.bunching[h] = v[16 + h];
         for (int h = 0; h < 3; ++h) o.power_harmonic[h] = v[20 + h];
+        for (int e = 0; e < 3; ++e) o.power_extra[e] = v[24 + e];
     }
     h.read_step = first + n;
     *nrows = n;
@@ -1314,6 +1322,10 @@ static mithra_status config_diag(Batch &b, int s, const mithra_diag_cfg *cfg)
         return fail(MITHRA_EINVAL, "power_spectrum must be 0 or 1");
     if (cfg->power_spectrum != h.diag.power_spectrum && b.step > 0)
         return fail(MITHRA_ESTATE, "the power spectrum can only be switched before the first step");
+    for (int e = 0; e < 3; ++e)
+        if (cfg->extra_planes[e] < -1 || cfg->extra_planes[e] >= h.mesh.n[2])
+            return fail(MITHRA_EINVAL, "extra_planes[%d] = %d: -1 or a z index of the mesh", e,
+                        cfg->extra_planes[e]);
     HIP_TRY(hipStreamSynchronize(b.stream));
     if (cfg->capacity != h.diag.capacity) {
         // re-lay the ring arena (no rows exist before the first step); the
@@ -1347,6 +1359,9 @@ static mithra_status config_diag(Batch &b, int s, const mithra_diag_cfg *cfg)
     S.mesh_every = cfg->mesh_diag_every;
     S.ring_cap = cfg->capacity;
     S.spec_on = cfg->power_spectrum;
+    S.n_extra = 0;
+    for (int e = 0; e < 3; ++e)
+        if (cfg->extra_planes[e] >= 0) S.kp_extra[S.n_extra++] = cfg->extra_planes[e];
     return build_tables(b);
 }
 

@@ -99,7 +99,7 @@ def make_beam(beam="plane", rayleigh=(0.0, 0.0), focus=(0.0, 0.0, 0.0)) -> Beam:
 class DiagCfg(ctypes.Structure):
     _fields_ = [("probe", ctypes.c_int32 * 3), ("power_plane_k", ctypes.c_int32),
                 ("mesh_diag_every", ctypes.c_int32), ("capacity", ctypes.c_int32),
-                ("power_spectrum", ctypes.c_int32)]
+                ("power_spectrum", ctypes.c_int32), ("extra_planes", ctypes.c_int32 * 3)]
 
 
 class DiagRow(ctypes.Structure):
@@ -109,7 +109,8 @@ class DiagRow(ctypes.Structure):
                 ("kinetic_energy", ctypes.c_double), ("probe_E", ctypes.c_double * 3),
                 ("probe_B", ctypes.c_double * 3), ("lost", ctypes.c_int64),
                 ("nonfinite", ctypes.c_int32), ("has_mesh_terms", ctypes.c_int32),
-                ("bunching", ctypes.c_double * 3), ("power_harmonic", ctypes.c_double * 3)]
+                ("bunching", ctypes.c_double * 3), ("power_harmonic", ctypes.c_double * 3),
+                ("power_extra", ctypes.c_double * 3)]
 
 
 class Info(ctypes.Structure):
@@ -126,7 +127,7 @@ DIAG_DTYPE = np.dtype([("step", np.int64), ("t", np.float64), ("total_charge", n
                        ("probe_E", np.float64, 3), ("probe_B", np.float64, 3),
                        ("lost", np.int64), ("nonfinite", np.int32),
                        ("has_mesh_terms", np.int32), ("bunching", np.float64, 3),
-                       ("power_harmonic", np.float64, 3)])
+                       ("power_harmonic", np.float64, 3), ("power_extra", np.float64, 3)])
 assert DIAG_DTYPE.itemsize == ctypes.sizeof(DiagRow)
 
 
@@ -294,6 +295,21 @@ def make_undulator(lambda_u, K, gamma_beam, z_entrance) -> Undulator:
 assert DIAG_DTYPE.itemsize == ctypes.sizeof(DiagRow)
 
 
+def make_diag_cfg(probe, kp, every=1, capacity=4096, spectrum=False, extra_planes=()) -> DiagCfg:
+    """Diagnostic settings; extra_planes: up to three further plate z indices."""
+    c = DiagCfg()
+    for a in range(3):
+        c.probe[a] = int(probe[a])
+    c.power_plane_k = int(kp)
+    c.mesh_diag_every = int(every)
+    c.capacity = int(capacity)
+    c.power_spectrum = 1 if spectrum else 0
+    k = list(extra_planes) + [-1] * (3 - len(extra_planes))
+    for e in range(3):
+        c.extra_planes[e] = int(k[e])
+    return c
+
+
 def _rows_to_array(rows, n):
     out = np.zeros(n, dtype=DIAG_DTYPE)
     ctypes.memmove(out.ctypes.data, rows, n * DIAG_DTYPE.itemsize)
@@ -375,14 +391,8 @@ class Sim:
         b = make_beam(beam, rayleigh, focus)
         _check(self._lib.mithra_set_seed_beam(self._h, ctypes.byref(b)))
 
-    def config_diag(self, probe, kp, every=1, capacity=4096, spectrum=False):
-        c = DiagCfg()
-        for a in range(3):
-            c.probe[a] = int(probe[a])
-        c.power_plane_k = int(kp)
-        c.mesh_diag_every = int(every)
-        c.capacity = int(capacity)
-        c.power_spectrum = 1 if spectrum else 0
+    def config_diag(self, probe, kp, every=1, capacity=4096, spectrum=False, extra_planes=()):
+        c = make_diag_cfg(probe, kp, every, capacity, spectrum, extra_planes)
         _check(self._lib.mithra_config_diag(self._h, ctypes.byref(c)))
 
     def run(self, nsteps: int):
@@ -505,14 +515,9 @@ class Batch:
         b = make_beam(beam, rayleigh, focus)
         _check(self._lib.mithra_batch_set_seed_beam(self._h, int(s), ctypes.byref(b)))
 
-    def config_diag(self, s, probe, kp, every=1, capacity=4096, spectrum=False):
-        c = DiagCfg()
-        for a in range(3):
-            c.probe[a] = int(probe[a])
-        c.power_plane_k = int(kp)
-        c.mesh_diag_every = int(every)
-        c.capacity = int(capacity)
-        c.power_spectrum = 1 if spectrum else 0
+    def config_diag(self, s, probe, kp, every=1, capacity=4096, spectrum=False,
+                    extra_planes=()):
+        c = make_diag_cfg(probe, kp, every, capacity, spectrum, extra_planes)
         _check(self._lib.mithra_batch_config_diag(self._h, int(s), ctypes.byref(c)))
 
     def tune(self, trials: int = 5):

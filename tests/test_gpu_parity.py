@@ -97,6 +97,7 @@ def compare_diag(gd, od, tol, what=""):
     errs["probe_B"] = rel_l2(gd["probe_B"], od[:, 10:13])
     errs["bunching"] = rel_l2(gd["bunching"], od[:, 16:19])
     errs["power_harmonic"] = rel_l2(gd["power_harmonic"], od[:, 20:23])
+    errs["power_extra"] = rel_l2(gd["power_extra"], od[:, 24:27])
     bad = {k: v for k, v in errs.items() if not v <= tol}
     say(what, "diag", errs)
     assert not bad, (what, bad)
@@ -726,6 +727,29 @@ def test_harmonic_power_of_a_pure_tone(precision):
     assert abs(P[0]) <= tol * mean and abs(P[2]) <= tol * mean
 
 
+def test_further_sampling_plates_match_oracle():
+    """Two further plates (one on the main plane, one nearer the bunch) on the
+    tiny configuration, 60 steps: every row against the oracle; the plate on
+    the main plane repeats the main power bit for bit; the unused one is 0."""
+    w = W.config(0, steps=60)
+    extra = (w.kp, w.kp - 12)
+    orc = oracle.from_workload(w)
+    orc.config_diag(w.probe, w.kp, extra_planes=extra)
+    sim = native.sim_from_workload(w, precision="f64", every=1)
+    sim.config_diag(w.probe, w.kp, every=1, spectrum=True, extra_planes=extra)
+    sim.run(60)
+    sim.sync()
+    orc.step(60)
+    gd = sim.get_diag()
+    compare_diag(gd, orc.diag(), TOL64, "plates")
+    assert np.array_equal(gd["power_extra"][:, 0], gd["power"])
+    assert not gd["power_extra"][:, 2].any()
+    assert np.abs(gd["power_extra"][:, 1]).max() > 0
+    with pytest.raises(native.MithraError) as e:
+        sim.config_diag(w.probe, w.kp, spectrum=True, extra_planes=(w.n[2],))
+    assert e.value.status == native.EINVAL
+
+
 def test_power_spectrum_is_off_by_default_and_fixed_after_the_first_step():
     w = W.config(0, steps=5)
     sim = native.sim_from_workload(w, spectrum=False)
@@ -1110,11 +1134,16 @@ def test_device_bytes_follow_reallocations():
     """device_bytes is what the simulation holds: a re-laid diagnostic ring
     replaces the old one, and re-loading particles leaves no blocks behind."""
     w = W.config(0, steps=4)
-    sim = native.sim_from_workload(w)  # ring of 4096 rows of 24 doubles
+    sim = native.sim_from_workload(w)  # ring of 4096 rows of 27 doubles
+    row = 27 * 8  # bytes of one row of the device ring
+
+    def block(n):  # device blocks are sized in multiples of 256 bytes
+        return (n + 255) // 256 * 256
+
     b0 = sim.info()["device_bytes"]
     sim.config_diag(w.probe, w.kp, capacity=100)
     b1 = sim.info()["device_bytes"]
-    assert b0 - b1 == 4096 * 24 * 8 - 100 * 24 * 8
+    assert b0 - b1 == block(4096 * row) - block(100 * row)
     sim.config_diag(w.probe, w.kp, capacity=4096)
     assert sim.info()["device_bytes"] == b0
     sim.set_particles(w.x, w.u, w.q, w.m)
