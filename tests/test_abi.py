@@ -2,6 +2,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -64,3 +65,29 @@ def test_allocator_callbacks_outlive_every_simulation():
     native.use_torch_allocator(True)
     assert len(native._hooks) == 2
     assert native._hooks[0] is first[0] and native._hooks[1] is first[1]
+
+
+def test_struct_field_offsets_match_the_header(tmp_path):
+    """Every field of every struct the binding passes sits where a C compiler
+    puts it (gcc on include/mithra.h, offsetof), not only the sizes."""
+    structs = {"mithra_mesh": native.Mesh, "mithra_undulator": native.Undulator,
+               "mithra_seed": native.Seed, "mithra_beam": native.Beam,
+               "mithra_diag_cfg": native.DiagCfg, "mithra_diag_row": native.DiagRow,
+               "mithra_info": native.Info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mithra.h"', 'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append('printf("%%s %%zu\\n", "%s", sizeof(%s));' % (cname, cname))
+        for fname, _ in cls._fields_:
+            lines.append('printf("%%s.%%s %%zu\\n", "%s", "%s", offsetof(%s, %s));'
+                         % (cname, fname, cname, fname))
+    lines.append('return 0; }')
+    src = tmp_path / "offsets.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "offsets"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    out = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)]).decode().split("\n")
+               if line)
+    for cname, cls in structs.items():
+        assert int(out[cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(out["%s.%s" % (cname, fname)]) == getattr(cls, fname).offset, (cname, fname)
