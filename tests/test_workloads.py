@@ -1,4 +1,5 @@
-"""The seeded input generators (no GPU): the infrared FEL example's loading."""
+"""The seeded input generators (no GPU): the published configurations, the
+parameter scan and the infrared FEL example's loading."""
 import math
 
 import numpy as np
@@ -44,3 +45,33 @@ def test_example1_loading():
     b0 = math.sqrt(1 - 1 / g0 ** 2)
     glab = g0 * (np.sqrt(1 + (w.u ** 2).sum(1)) + b0 * w.u[:, 2])
     assert abs(glab.mean() / w.gamma_beam - 1) < 1e-5 and abs(glab.std() / w.gamma_beam - 1e-4) < 2e-5
+
+
+def test_configurations_have_the_published_shapes():
+    """The tiny, mid and precision workloads: mesh, particle count,
+    beam and undulator parameters, bunch widths n/8 cells, every particle
+    inside the safe interior and seeded (same inputs on every call)."""
+    want = {0: ((32, 32, 64), 4096, 100.0, 1.0, 0.015), 1: ((128, 128, 512), 1 << 20, 100.0, 1.0, 0.015),
+            2: ((32, 32, 64), 4096, 100.0, 1.0, 0.015)}
+    for idx, (n, npart, gamma, K, lam) in want.items():
+        w = W.config(idx)
+        assert tuple(w.n) == n and w.np == npart
+        assert (w.gamma_beam, w.K, w.lambda_u) == (gamma, K, lam)
+        c = np.floor((w.x - np.asarray(w.origin)) / np.asarray(w.d))
+        assert np.all(c >= 2) and np.all(c <= np.asarray(n) - 3)
+        sig = np.std(c, axis=0)
+        assert np.all(np.abs(sig / (np.asarray(n) / 8) - 1) < 0.15), sig
+        assert np.array_equal(W.config(idx).x, w.x)
+
+
+def test_batch_scan_draws_within_the_published_ranges():
+    """64 simulations: meshes from 32x32x128 to 96x96x384 (n_z = 4 n_x),
+    16K-256K particles, K in [0.8, 2.0], gamma in [80, 250]."""
+    ws = W.batch_configs(64, steps=10)
+    assert len(ws) == 64
+    for w in ws:
+        nx, ny, nz = w.n
+        assert nx == ny and nz == 4 * nx and 32 <= nx <= 96 and nx % 8 == 0
+        assert 16 * 1024 <= w.np <= 256 * 1024
+        assert 0.8 <= w.K <= 2.0 and 80.0 <= w.gamma_beam <= 250.0
+    assert len({w.n for w in ws}) > 5 and len({w.np for w in ws}) > 30
