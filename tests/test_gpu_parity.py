@@ -1296,3 +1296,41 @@ def test_example1_grows_exponentially_and_saturates():
     assert 1.5 < z_sat < 2.95  # the peak lies inside the run, not at its end
     assert b - a > 1000  # more than half a metre of exponential growth
     assert l1 < lg < 2.0 * l3, (lg, l1, l3)
+
+
+def test_plain_c_caller_equals_the_binding_bitwise(tmp_path):
+    """The library used from C alone (tests/abi_driver.c: no Python, no
+    PyTorch, device memory from hipMalloc, its own stream) gives the same
+    diagnostic rows and A_x, bit for bit, as the Python binding on PyTorch's
+    allocator and stream: the tiny configuration, 40 steps."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_1612_03310_amd")
+    exe = tmp_path / "abi_driver"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(root, "include"),
+                           os.path.join(root, "tests", "abi_driver.c"), "-L", pkg, "-lmithra",
+                           "-Wl,-rpath," + pkg, "-Wl,-rpath-link,/opt/rocm/lib", "-o", str(exe)])
+    w = W.config(0, steps=40)
+    head = (list(w.n) + list(w.d) + list(w.origin) + [w.courant, w.nsfd_A, w.substeps,
+            w.space_charge] + list(w.bc) + [w.lambda_u, w.K, w.gamma_beam, w.z_e, w.q, w.m,
+            w.np, 40] + list(w.probe) + [w.kp, 0.0, 0.0])
+    inp = tmp_path / "in.bin"
+    with open(inp, "wb") as f:
+        np.asarray(head, dtype=np.float64).tofile(f)
+        np.ascontiguousarray(w.x, dtype=np.float64).tofile(f)
+        np.ascontiguousarray(w.u, dtype=np.float64).tofile(f)
+    out = tmp_path / "out.bin"
+    say("case plain C caller", w.n, w.np)
+    subprocess.run([str(exe), str(inp), str(out)], check=True, timeout=120)
+    raw = out.read_bytes()
+    nrows = int(np.frombuffer(raw[:8], dtype=np.int64)[0])
+    rowbytes = native.DIAG_DTYPE.itemsize * nrows
+    c_rows = raw[8:8 + rowbytes]
+    c_ax = np.frombuffer(raw[8 + rowbytes:], dtype=np.float64).reshape(w.n[2], w.n[1], w.n[0])
+    sim = native.sim_from_workload(w, precision="f64", every=1, spectrum=False)
+    sim.run(40)
+    sim.sync()
+    assert nrows == 40
+    assert sim.get_diag().tobytes() == c_rows
+    assert np.array_equal(sim.get_field("Ax"), c_ax)
