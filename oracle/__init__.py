@@ -30,13 +30,18 @@ DIAG_COLUMNS = ("step", "t", "total_charge", "continuity_residual", "power",
 _lib = None
 
 
+def gcc_command(src: str, out: str, extra=()):
+    """The oracle's compile line (no fast-math, no FMA contraction); `extra`
+    adds flags, e.g. sanitizers or OpenMP."""
+    return ["gcc", "-O3", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+            "-fno-fast-math", "-Wall", *extra, "-o", out, src, "-lm"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O3", "-std=c99", "-fPIC", "-shared",
-                               "-ffp-contract=off", "-fno-fast-math", "-Wall",
-                               "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(gcc_command(_SRC, tmp))
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -47,7 +52,27 @@ def _load():
         return _lib
     if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         build(force=True)
-    lib = ctypes.CDLL(_LIB)
+    _lib = _open(_LIB)
+    return _lib
+
+
+def use_library(path):
+    """Make simulations created from now on use the oracle built at `path`
+    (the tests build copies with one planted mistake to show that a pin
+    catches it).  Returns the library in use before, for restore_library."""
+    global _lib
+    before = _load()
+    _lib = _open(path)
+    return before
+
+
+def restore_library(lib):
+    global _lib
+    _lib = lib
+
+
+def _open(path):
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     D = ctypes.c_double
     I = ctypes.c_int
@@ -87,7 +112,6 @@ def _load():
     lib.orc_boris.argtypes = [D, D, D, dp, dp, dp]
     lib.orc_gather.argtypes = [P, dp, dp, dp]
     lib.orc_deposit_current.argtypes = [P, dp, dp]
-    _lib = lib
     return lib
 
 
