@@ -19,6 +19,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mithra_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with OpenMP: the loops that write disjoint points or
+# particles (potential update, vertex fields, push, plane spectrum) run on
+# all threads; sums stay sequential, so every result equals the plain
+# build's bit for bit.  For long oracle runs and the all-core CPU baseline.
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 NDIAG = 27
 DIAG_COLUMNS = ("step", "t", "total_charge", "continuity_residual", "power",
@@ -34,16 +39,34 @@ def gcc_command(src: str, out: str, extra=()):
     """The oracle's compile line (no fast-math, no FMA contraction); `extra`
     adds flags, e.g. sanitizers or OpenMP."""
     return ["gcc", "-O3", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-            "-fno-fast-math", "-Wall", *extra, "-o", out, src, "-lm"]
+            "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas", *extra, "-o", out, src, "-lm"]
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(gcc_command(_SRC, tmp))
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc, plain and with OpenMP."""
+    for lib, extra in ((_LIB, ()), (_LIB_OMP, ("-fopenmp",))):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+            tmp = lib + ".tmp%d" % os.getpid()
+            subprocess.check_call(gcc_command(_SRC, tmp, extra))
+            os.replace(tmp, lib)
     return _LIB
+
+
+_lib_omp = None
+
+
+def _load_parallel():
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP) or os.path.getmtime(_LIB_OMP) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib_omp = _open(_LIB_OMP)
+    return _lib_omp
+
+
+def threads(parallel: bool = True) -> int:
+    """Threads the oracle's parallel loops use (1 for the plain build)."""
+    return int((_load_parallel() if parallel else _load()).orc_threads())
 
 
 def _load():
@@ -112,6 +135,8 @@ def _open(path):
     lib.orc_boris.argtypes = [D, D, D, dp, dp, dp]
     lib.orc_gather.argtypes = [P, dp, dp, dp]
     lib.orc_deposit_current.argtypes = [P, dp, dp]
+    lib.orc_threads.restype = I
+    lib.orc_threads.argtypes = []
     return lib
 
 
@@ -134,8 +159,8 @@ class OracleSim:
 
     def __init__(self, n, d, origin, courant=0.9, nsfd_A=-1.0, substeps=1,
                  space_charge=1, bc=(0, 0, 0), lambda_u=0.015, K=1.0,
-                 gamma_beam=100.0, z_e=0.0):
-        lib = _load()
+                 gamma_beam=100.0, z_e=0.0, parallel=False):
+        lib = _load_parallel() if parallel else _load()
         self._lib = lib
         self.n = tuple(int(v) for v in n)
         n_c = (ctypes.c_int * 3)(*self.n)
@@ -341,10 +366,11 @@ def boris(q, m, dtb, u, E, B):
     return u
 
 
-def from_workload(w):
-    """Oracle simulation loaded with a workload from the seeded generator."""
+def from_workload(w, parallel=False):
+    """Oracle simulation loaded with a workload from the seeded generator
+    (parallel: the OpenMP build, same results)."""
     s = OracleSim(w.n, w.d, w.origin, w.courant, w.nsfd_A, w.substeps, w.space_charge,
-                  w.bc, w.lambda_u, w.K, w.gamma_beam, w.z_e)
+                  w.bc, w.lambda_u, w.K, w.gamma_beam, w.z_e, parallel=parallel)
     s.config_diag(w.probe, w.kp)
     s.set_particles(w.x, w.u, w.q, w.m)
     return s

@@ -77,7 +77,11 @@
  *       (zeta = z - z_f, argument t - (z - z_ref)/c) injected point by point
  *       through the TF/SF planes.
  */
+#include <assert.h>
 #include <complex.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #undef I /* loops use I, J, K as vertex indices; the imaginary unit is ORC_J */
 #define ORC_J _Complex_I
@@ -372,6 +376,11 @@ void orc_deposit_current(orc_sim *s, const double *x0, const double *x1)
     cell_of(s, x1, c1, f1);
     double S0[3][3], DS[3][3];
     for (int a = 0; a < 3; a++) {
+        /* the 3-point shape arrays below hold a move of at most one cell per
+           axis: a particle moves less than c dt per field step, and
+           c dt <= d_a on every mesh the library accepts (nu <= 1 with the
+           stability condition dz < dx, dy) */
+        assert(c1[a] - c0[a] >= -1 && c1[a] - c0[a] <= 1);
         base[a] = c0[a] < c1[a] ? c0[a] : c1[a];
         double s1[3] = {0.0, 0.0, 0.0};
         for (int m = 0; m < 3; m++) S0[a][m] = 0.0;
@@ -461,6 +470,7 @@ void orc_field_update(orc_sim *s)
             lo[a] = s->bc[a] ? 0 : 1;
             hi[a] = s->bc[a] ? s->n[a] - 1 : extent(s, c, a) - 2;
         }
+#pragma omp parallel for schedule(static)
         for (int k = lo[2]; k <= hi[2]; k++)
             for (int j = lo[1]; j <= hi[1]; j++)
                 for (int i = lo[0]; i <= hi[0]; i++) {
@@ -600,7 +610,9 @@ static void boundary_mur1(orc_sim *s, int c)
     double *P = s->pot[s->lcur][c], *Q = s->pot[s->lprev][c], *R = s->pot[s->lnext][c];
     int ext[3];
     for (int a = 0; a < 3; a++) ext[a] = extent(s, c, a);
+    /* a point of one stage reads only points of earlier stages */
     for (int stage = 1; stage <= 3; stage++)
+#pragma omp parallel for schedule(static)
         for (int k = 0; k < ext[2]; k++)
             for (int j = 0; j < ext[1]; j++)
                 for (int i = 0; i < ext[0]; i++) {
@@ -711,7 +723,9 @@ static void boundary_mur2(orc_sim *s, int c)
     double *R = s->pot[s->lnext][c];
     int ext[3];
     for (int a = 0; a < 3; a++) ext[a] = extent(s, c, a);
+    /* a point of one stage reads only points of earlier stages */
     for (int stage = 1; stage <= 3; stage++)
+#pragma omp parallel for schedule(static)
         for (int k = 0; k < ext[2]; k++)
             for (int j = 0; j < ext[1]; j++)
                 for (int i = 0; i < ext[0]; i++) {
@@ -752,6 +766,7 @@ void orc_vertex_fields(orc_sim *s)
     double *const *An1 = s->pot[s->lnext];
     const double *phi = s->pot[s->lcur][3];
     double dx = s->d[0], dy = s->d[1], dz = s->d[2], dt = s->dt;
+#pragma omp parallel for schedule(static)
     for (int k = lo[2]; k <= hi[2]; k++)
         for (int j = lo[1]; j <= hi[1]; j++)
             for (int i = lo[0]; i <= hi[0]; i++) {
@@ -969,6 +984,9 @@ void orc_boris(double q, double m, double dtb, double *u, const double *E, const
 void orc_push(orc_sim *s)
 {
     double t0 = (s->step + 0.5) * s->dt;
+    long lost = 0;
+    int nonfinite = 0;
+#pragma omp parallel for schedule(static) reduction(+ : lost) reduction(| : nonfinite)
     for (long p = 0; p < s->np; p++) {
         double *x = &s->x[3 * p], *u = &s->u[3 * p];
         s->x_old[3 * p + 0] = x[0];
@@ -990,9 +1008,9 @@ void orc_push(orc_sim *s)
         }
         if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(x[0]) &&
               isfinite(x[1]) && isfinite(x[2]))) {
-            s->nonfinite_u = 1;
+            nonfinite = 1;
             s->alive[p] = 0;
-            s->lost++;
+            lost++;
             continue;
         }
         /* O8: loss (reading R17) */
@@ -1001,9 +1019,11 @@ void orc_push(orc_sim *s)
         cell_of(s, x, c, f);
         if (!inside(s, c)) {
             s->alive[p] = 0;
-            s->lost++;
+            lost++;
         }
     }
+    s->lost += lost;
+    if (nonfinite) s->nonfinite_u = 1;
 }
 
 /* ---- O9: deposit rho^{n+3/2} and J^{n+1} ---------------------------------- */
@@ -1055,6 +1075,7 @@ void orc_spectrum_sample(orc_sim *s)
     for (int h = 1; h <= 3; h++) {
         const double w = h * omega1(s);
         const double cs = cos(w * t), sn = sin(w * t);
+#pragma omp parallel for schedule(static)
         for (int j = lo[1]; j <= hi[1]; j++)
             for (int i = lo[0]; i <= hi[0]; i++) {
                 long p = IX(s, i, j, s->kp);
@@ -1242,6 +1263,18 @@ long orc_info(orc_sim *s, int which)
     case 4: return s->ncell;
     default: return -1;
     }
+}
+
+/* threads the loops without floating-point reductions run on (1 unless
+   built with OpenMP, which changes no result: those loops write disjoint
+   points or particles, and every sum stays sequential) */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Set the step counter (the time levels the next step uses: potentials at
