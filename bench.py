@@ -1,12 +1,18 @@
 """Throughput of the boosted-frame FDTD/PIC step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--extra]
+python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Default workload: the 128x128x512 mesh with 1,048,576 macro-particles in
-double precision (the mid configuration).  One step is the whole hot path:
-potential update + Mur boundary, gather + undulator + Boris push, binning,
-charge-conserving deposition, and the double-precision diagnostics.  Inputs
-are synthetic (seeded generator) and resident in HBM before timing starts.
+Headline workload: the 256x256x2048 mesh with 16,777,216 macro-particles in
+the float split form (float fields and push, int32 cell + float offset
+positions, double-precision reductions), the largest configuration.  One
+step is the whole hot path: potential update + Mur boundary, gather +
+undulator + Boris push, binning, charge-conserving deposition, and the
+double-precision diagnostics.  Inputs are synthetic (seeded generator) and
+resident in HBM before timing starts.  Also timed by default: the same shape
+in double precision (speedup, and the float form's error against it), the
+64-simulation parameter scan against 64 sequential runs, the mid
+configuration (128x128x512, double) with its variants, and the CPU oracle on
+a slab of the headline workload, on one thread and on all threads.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -196,14 +202,16 @@ def timed_run(sim, steps, torch):
 
 def measure(w, precision, steps, warmup, torch, native, tune=True, every=100, seed=None):
     """Graph-replayed timed region, then an event-timed region of the same
-    length for the per-kernel durations."""
+    length for the per-kernel durations.  The library captures its step graph
+    on the first run, so the warm-up run builds it before timing starts."""
     t_setup = time.perf_counter()
-    sim = native.sim_from_workload(w, precision=precision, every=every, spectrum=False)
+    sim = native.sim_from_workload(w, precision=precision, every=every, spectrum=False,
+                                   capacity=2 * steps + warmup + 8)
     if seed is not None:
         sim.set_seed(**seed)
     if tune:
         sim.tune(3)
-    sim.run(warmup)
+    sim.run(max(warmup, 1))
     sim.sync()
     log("  set-up + warm-up %.1f s, tile %s" % (time.perf_counter() - t_setup,
                                                 sim.info()["stencil_tile"]))
@@ -220,58 +228,224 @@ def measure(w, precision, steps, warmup, torch, native, tune=True, every=100, se
     return dt, dt_ev, per_launch, dg, info
 
 
-def cpu_baseline(w, steps):
-    """The oracle as it stands, single thread, on a bounded sample of the same
-    workload (whole steps of the full mesh and bunch; set-up excluded)."""
+def occupied_tiles(w):
+    """8x8x8-cell tiles holding at least one particle of the workload (the
+    tiles whose potentials the push reads)."""
+    c = np.floor((w.x - np.asarray(w.origin)) / np.asarray(w.d)).astype(np.int64) // 8
+    nt = [(w.n[a] + 7) // 8 for a in range(3)]
+    return int(np.unique((c[:, 2] * nt[1] + c[:, 1]) * nt[0] + c[:, 0]).size)
+
+
+def roofline_block(kind, t_ms, nbytes, traffic=None, **extra):
+    achieved = nbytes / (t_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "algorithmic_bytes_per_launch": int(nbytes), "avg_launch_ms": round(t_ms, 5)}
+    out.update(extra)
+    return out
+
+
+def kernels_table(per, w, rs, nbp):
+    out = {}
+    for kind, t in per.items():
+        b = kernel_bytes(kind, w, rs, nbp)
+        out[kind] = {"ms": round(t, 5)}
+        if b:
+            out[kind]["algorithmic_GBs"] = round(b / (t * 1e-3) / 1e9, 1)
+            out[kind]["frac_hbm"] = round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
+def push_roofline(per, w, rs, tiles, profile_name):
+    """The push against HBM: particle bytes plus the potentials of the
+    occupied tiles it gathers from (A^s, A^{s+1}, phi: 7 values per cell)."""
+    part = kernel_bytes("push", w, rs)
+    gather = tiles * 512 * 7 * rs
+    t = per["push"]
+    return roofline_block("push", t, part + gather, traffic_from_profile("push", profile_name),
+                          particle_bytes=int(part), gather_bytes=int(gather),
+                          occupied_tiles=tiles,
+                          frac_particle_bytes_only=round(part / (t * 1e-3) / 1e9
+                                                         / HBM_PEAK_GBS, 4))
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def slab_of(w, planes):
+    """A bounded sample of a workload for the CPU baseline: the full
+    transverse mesh over `planes` z-planes at the bunch centre, with every
+    k-th of the particles inside them so that the sample holds as many
+    particles per cell as the whole job (its cell-updates/s then stand for
+    the whole job's)."""
+    import dataclasses
+    k0 = (w.n[2] - planes) // 2
+    z0 = w.origin[2] + k0 * w.d[2]
+    zc = (w.x[:, 2] - z0) / w.d[2]
+    sel = np.nonzero((zc >= 3.0) & (zc < planes - 4.0))[0]
+    want = w.np * (w.n[0] * w.n[1] * planes) / w.ncell
+    sel = sel[::max(1, int(round(len(sel) / want)))]
+    n = (w.n[0], w.n[1], planes)
+    kp = planes // 2
+    return dataclasses.replace(w, name=w.name + "-slab", n=n,
+                               origin=(w.origin[0], w.origin[1], z0), x=w.x[sel].copy(),
+                               u=w.u[sel].copy(), probe=(n[0] // 2, n[1] // 2, kp), kp=kp)
+
+
+def cpu_baseline(w, planes, steps_1t, steps_all):
+    """The oracle as it stands on a bounded sample of the headline workload:
+    one thread (the plain build), then every host thread (the OpenMP build of
+    the same source, which parallelises the loops over disjoint points and
+    particles and keeps every sum sequential).  Set-up excluded."""
     import oracle
 
-    sim = oracle.from_workload(w)
+    ws = slab_of(w, planes)
+    res = {}
+    for par, steps in ((False, steps_1t), (True, steps_all)):
+        sim = oracle.from_workload(ws, parallel=par)
+        t0 = time.perf_counter()
+        sim.step(steps)
+        dt = time.perf_counter() - t0
+        res[par] = (ws.ncell * steps / dt, ws.np * steps * ws.substeps / dt, dt, steps)
+        del sim
+    nthreads = oracle.threads(True)
+    cu, pp, dt, st = res[True]
+    cu1, pp1, dt1, st1 = res[False]
+    return {"value": cu, "unit": "cell-updates/s", "cores": nthreads, "kind": "oracle",
+            "particle_pushes_per_s": pp, "cpu_model": cpu_model(),
+            "single_thread": {"value": cu1, "unit": "cell-updates/s", "cores": 1,
+                              "particle_pushes_per_s": pp1, "seconds": round(dt1, 2),
+                              "steps": st1},
+            "sample": "%d and %d full steps (one thread, %d threads) of a %dx%dx%d slab at the "
+                      "bunch centre of the %s workload with %d of its particles (the whole "
+                      "job's particles per cell; %.1f s and %.1f s, set-up excluded), plain C "
+                      "double precision"
+                      % (st1, st, nthreads, ws.n[0], ws.n[1], ws.n[2], w.name, ws.np, dt1, dt)}
+
+
+def batch_leg(nb, torch, native, W):
+    """The parameter scan: 64 simulations of uneven meshes and bunches in one
+    graph-replayed batch against the same 64 run one after another."""
+    ws = W.batch_configs(64, steps=nb)
+    b = native.batch_from_workloads(ws, precision="f32", every=100, spectrum=False,
+                                    capacity=nb + 16)
+    b.tune(2)
+    b.run(8)
+    b.sync()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(steps)
-    dt = time.perf_counter() - t0
-    return {"value": w.ncell * steps / dt, "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle", "particle_pushes_per_s": w.np * steps / dt,
-            "sample": "%d full steps of the %dx%dx%d mesh with %d particles (%.1f s, set-up "
-                      "excluded), plain C double precision, one thread"
-                      % (steps, w.n[0], w.n[1], w.n[2], w.np, dt)}
+    b.run(nb)
+    b.sync()
+    dtb = time.perf_counter() - t0
+    b.close()
+    seq = 0.0
+    for wi in ws:
+        s = native.sim_from_workload(wi, precision="f32", every=100, spectrum=False,
+                                     capacity=nb + 16)
+        s.run(8)
+        s.sync()
+        seq += timed_run(s, nb, torch)
+        s.close()
+    cells = sum(x.ncell for x in ws)
+    parts = sum(x.np for x in ws)
+    return {"workload": "scan-64-sims-32..96x32..96x128..384", "simulations": 64,
+            "precision": "f32 split", "steps": nb, "cells": cells, "particles": parts,
+            "batched_s": round(dtb, 4), "sequential_s": round(seq, 4),
+            "speedup": round(seq / dtb, 3), "cell_updates_per_s": cells * nb / dtb,
+            "particle_pushes_per_s": parts * nb / dtb,
+            "sequential_cell_updates_per_s": cells * nb / seq}
 
 
-def large_measurements(wl, kl, torch, native):
-    """The large configuration in float split form and the same shape in double."""
-    log("large configuration %s, %d particles, f32 split, %d steps" % (wl.n, wl.np, kl))
-    dtl, _, perl, dgl, _ = measure(wl, "f32", kl, 5, torch, native)
-    log("  %.3f ms/step" % (dtl * 1e3 / kl))
-    kl64 = max(10, kl // 4)
-    log("same shape in f64, %d steps" % kl64)
-    dtl64, _, perl64, _, _ = measure(wl, "f64", kl64, 3, torch, native)
-    log("  %.3f ms/step" % (dtl64 * 1e3 / kl64))
-    return {"fp32_large": {
-        "workload": "large-256x256x2048-16.8M-particles", "precision": "f32 split",
-        "steps": kl, "ms_per_step": round(dtl * 1e3 / kl, 4),
-        "cell_updates_per_s": wl.ncell * kl / dtl, "particle_pushes_per_s": wl.np * kl / dtl,
-        "kernels_ms": {k: round(v, 4) for k, v in perl.items()},
-        "stencil_frac_hbm": round(kernel_bytes("stencil", wl, 4) / (perl["stencil"] * 1e-3)
-                                  / 1e9 / HBM_PEAK_GBS, 4),
-        "push_frac_hbm": round(kernel_bytes("push", wl, 4) / (perl["push"] * 1e-3)
-                               / 1e9 / HBM_PEAK_GBS, 4),
-        "lost": int(dgl["lost"][-1]), "nonfinite": bool(dgl["nonfinite"].any()),
-        "fp64_same_shape_ms_per_step": round(dtl64 * 1e3 / kl64, 4),
-        "speedup_fp32_vs_fp64": round((dtl64 / kl64) / (dtl / kl), 3),
-    }}
+def mid_legs(args, K, Wm, torch, native, W):
+    """The mid configuration in double precision and its variants (second-order
+    Mur, a TF/SF seed) and the paper's infrared FEL example."""
+    import dataclasses
+    out = {}
+    w = W.config(1)
+    km = max(50, K)
+    log("mid configuration %s, %d particles, f64, %d steps" % (w.n, w.np, km))
+    dt, dt_ev, per, dg, info = measure(w, "f64", km, Wm, torch, native)
+    nbp = boundary_points(w, info["stencil_tile"][0])
+    t_st = per["stencil"]
+    out["mid_f64"] = {
+        "workload": "mid-128x128x512-1M-particles", "precision": "f64", "steps": km,
+        "ms_per_step": round(dt * 1e3 / km, 5),
+        "event_region_ms_per_step": round(dt_ev * 1e3 / km, 5),
+        "cell_updates_per_s": w.ncell * km / dt, "particle_pushes_per_s": w.np * km / dt,
+        "kernels": kernels_table(per, w, 8, nbp),
+        "roofline_stencil": roofline_block("stencil", t_st, kernel_bytes("stencil", w, 8),
+                                           traffic_from_profile("stencil", "mid"))}
+    log("  %.4f ms/step" % (dt * 1e3 / km))
+    if not args.no_mur2:
+        w2 = dataclasses.replace(w, bc=(2, 2, 2))
+        log("second-order Mur on the mid configuration, %d steps" % km)
+        dt2, _, per2, _, _ = measure(w2, "f64", km, Wm, torch, native)
+        b2 = mur2_boundary_bytes(w2, 8)
+        out["mur2_mid"] = {
+            "bc": [2, 2, 2], "steps": km, "ms_per_step": round(dt2 * 1e3 / km, 5),
+            "cell_updates_per_s": w2.ncell * km / dt2, "boundary_ms": round(per2["boundary"], 5),
+            "boundary_algorithmic_GBs": round(b2 / (per2["boundary"] * 1e-3) / 1e9, 1),
+            "boundary_frac_hbm": round(b2 / (per2["boundary"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernels_ms": {k: round(v, 5) for k, v in per2.items()}}
+        log("  %.4f ms/step, boundary %.4f ms" % (dt2 * 1e3 / km, per2["boundary"]))
+    if not args.no_seed:
+        # a modulated-Gaussian plane wave at the rest-frame resonant
+        # wavelength (32 cells), a0 = 0.1, entering through z_min
+        c_light, q_e, m_e = 299792458.0, 1.602176634e-19, 9.1093837015e-31
+        lam = 32 * w.d[2]
+        tau = 40 * w.d[2] / c_light
+        seed = dict(amplitude=0.1 * m_e * c_light / q_e, polarization=(1.0, 0.0),
+                    frequency=c_light / lam, t0=3 * tau, tau=tau, cep=0.0, signal="gaussian",
+                    z_ref=w.origin[2])
+        log("seeded mid configuration (TF/SF plane wave), %d steps" % km)
+        dt3, _, per3, dg3, _ = measure(w, "f64", km, Wm, torch, native, seed=seed)
+        out["seed_mid"] = {
+            "steps": km, "ms_per_step": round(dt3 * 1e3 / km, 5),
+            "cell_updates_per_s": w.ncell * km / dt3, "stencil_ms": round(per3["stencil"], 5),
+            "probe_Ex_max": float(np.max(np.abs(dg3["probe_E"][:, 0]))) if len(dg3) else None}
+        log("  %.4f ms/step, stencil %.4f ms" % (dt3 * 1e3 / km, per3["stencil"]))
+    if not args.no_example1:
+        log("infrared FEL example: 64x64x2800, 131072 particles, 6000 steps")
+        ex = example1_run(6000, torch, native, W)
+        out["example1"] = ex
+        log("  %.4f ms/step, gain length %s m (1D %.3f, 3D fit %.3f, paper 0.22), "
+            "saturation at %.2f m" % (ex["ms_per_step"], ex["gain_length_m"],
+                                       ex["gain_length_1d_m"], ex["gain_length_3d_xie_m"],
+                                       ex["saturation_at_m"]))
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--extra", action="store_true", help="also time the batched scan")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-planes", type=int, default=64,
+                    help="z-planes of the large mesh in the CPU baseline's sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device 5 times (a kernel of known "
                          "traffic, to scale hardware byte counters)")
-    ap.add_argument("--skip-large", action="store_true")
+    ap.add_argument("--no-f64", action="store_true",
+                    help="skip the same shape in double precision")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-simulation scan against 64 sequential runs")
+    ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--no-mid", action="store_true",
+                    help="skip the mid configuration (128x128x512, f64) and its variants")
     ap.add_argument("--no-mur2", action="store_true",
                     help="skip the second-order Mur leg (mid configuration, bc code 2)")
     ap.add_argument("--no-seed", action="store_true",
@@ -279,15 +453,16 @@ def main():
     ap.add_argument("--no-example1", action="store_true",
                     help="skip the paper's infrared FEL example (64x64x2800, 131072 "
                          "particles, run to saturation, gain length fitted)")
-    ap.add_argument("--workload", choices=("mid", "large"), default="mid",
-                    help="headline workload: mid (128x128x512, 1M particles, f64, the "
-                         "default) or large (256x256x2048, 16.8M particles, f32 split)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline workload only (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(the z-slab sharding is a design note only); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.only_headline:
+        args.no_f64 = args.no_batch = args.no_mid = args.no_cpu = True
 
     import torch
 
@@ -305,130 +480,83 @@ def main():
         log("copy probe: 5 x 1 GiB read + 1 GiB written")
         del src, dst
 
-    # ---- headline: the mid configuration in double precision ----------------
-    if args.workload == "mid":
-        w, wname, prec, rs = W.config(1), "mid-128x128x512-1M-particles", "f64", 8
-    else:
-        w, wname, prec, rs = W.config(3), "large-256x256x2048-16.8M-particles", "f32", 4
-        args.skip_large = True
-    log("%s configuration %s, %d particles, %s, %d steps" % (args.workload, w.n, w.np, prec, K))
-    dt, dt_ev, per, dg, info = measure(w, prec, K, Wm, torch, native)
+    # ---- headline: the large configuration, float split form -----------------
+    w = W.config(3)
+    wname = "large-256x256x2048-16.8M-particles"
+    log("large configuration %s, %d particles, f32 split, %d steps" % (w.n, w.np, K))
+    dt, dt_ev, per, dg, info = measure(w, "f32", K, Wm, torch, native)
     ms_step = dt * 1e3 / K
     value = w.ncell * K / dt
     pushes = w.np * K * w.substeps / dt
-    log("  %.4f ms/step, %.3e cell-updates/s, %.3e pushes/s" % (ms_step, value, pushes))
-
+    log("  %.4f ms/step (event-timed %.4f), %.3e cell-updates/s, %.3e pushes/s"
+        % (ms_step, dt_ev * 1e3 / K, value, pushes))
+    tiles = occupied_tiles(w)
     nbp = boundary_points(w, info["stencil_tile"][0])
-    kernels = {}
-    for kind, t in per.items():
-        b = kernel_bytes(kind, w, rs, nbp)
-        kernels[kind] = {"ms": round(t, 5)}
-        if b:
-            kernels[kind]["algorithmic_GBs"] = round(b / (t * 1e-3) / 1e9, 1)
-            kernels[kind]["frac_hbm"] = round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    dom = max((k for k in per if kernel_bytes(k, w, rs, nbp)), key=lambda k: per[k])
-    dom_bytes = kernel_bytes(dom, w, rs, nbp)
-    achieved = dom_bytes / (per[dom] * 1e-3) / 1e9
-    traffic = traffic_from_profile(dom, args.workload)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes_per_launch": dom_bytes,
-                "avg_launch_ms": round(per[dom], 5)}
-    step_bytes = sum(kernel_bytes(k, w, rs, nbp) for k in per)
+    kernels = kernels_table(per, w, 4, nbp)
+    roofline = roofline_block("stencil", per["stencil"], kernel_bytes("stencil", w, 4),
+                              traffic_from_profile("stencil", "large"))
+    roof_push = push_roofline(per, w, 4, tiles, "large")
+    step_bytes = sum(kernel_bytes(k, w, 4, nbp) for k in per)
 
-    # ---- the large float configuration and the same shape in double ---------
     out_extra = {}
-    if args.workload == "mid" and not args.no_mur2:
-        import dataclasses
-        w2 = dataclasses.replace(w, bc=(2, 2, 2))
-        k2 = max(50, K // 4)
-        log("second-order Mur on the mid configuration, %d steps" % k2)
-        dt2, _, per2, _, info2 = measure(w2, prec, k2, Wm, torch, native)
-        b2 = mur2_boundary_bytes(w2, rs)
-        out_extra["mur2_mid"] = {
-            "bc": [2, 2, 2], "steps": k2, "ms_per_step": round(dt2 * 1e3 / k2, 5),
-            "cell_updates_per_s": w2.ncell * k2 / dt2, "boundary_ms": round(per2["boundary"], 5),
-            "boundary_algorithmic_GBs": round(b2 / (per2["boundary"] * 1e-3) / 1e9, 1),
-            "boundary_frac_hbm": round(b2 / (per2["boundary"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "kernels_ms": {k: round(v, 5) for k, v in per2.items()}}
-        log("  %.4f ms/step, boundary %.4f ms" % (dt2 * 1e3 / k2, per2["boundary"]))
-    if args.workload == "mid" and not args.no_seed:
-        # a modulated-Gaussian plane wave at the rest-frame resonant
-        # wavelength (32 cells), a0 = 0.1, entering through z_min
-        c_light, q_e, m_e = 299792458.0, 1.602176634e-19, 9.1093837015e-31
-        lam = 32 * w.d[2]
-        tau = 40 * w.d[2] / c_light
-        seed = dict(amplitude=0.1 * m_e * c_light / q_e, polarization=(1.0, 0.0),
-                    frequency=c_light / lam, t0=3 * tau, tau=tau, cep=0.0, signal="gaussian",
-                    z_ref=w.origin[2])
-        k3 = max(50, K // 4)
-        log("seeded mid configuration (TF/SF plane wave), %d steps" % k3)
-        dt3, _, per3, dg3, _ = measure(w, prec, k3, Wm, torch, native, seed=seed)
-        out_extra["seed_mid"] = {
-            "steps": k3, "ms_per_step": round(dt3 * 1e3 / k3, 5),
-            "cell_updates_per_s": w.ncell * k3 / dt3, "stencil_ms": round(per3["stencil"], 5),
-            "probe_Ex_max": float(np.max(np.abs(dg3["probe_E"][:, 0]))) if len(dg3) else None}
-        log("  %.4f ms/step, stencil %.4f ms" % (dt3 * 1e3 / k3, per3["stencil"]))
-    if args.workload == "mid" and not args.no_example1:
-        log("infrared FEL example: 64x64x2800, 131072 particles, 6000 steps")
-        ex = example1_run(6000, torch, native, W)
-        out_extra["example1"] = ex
-        log("  %.4f ms/step, gain length %s m (1D %.3f, 3D fit %.3f, paper 0.22), "
-            "saturation at %.2f m" % (ex["ms_per_step"], ex["gain_length_m"],
-                                       ex["gain_length_1d_m"], ex["gain_length_3d_xie_m"],
-                                       ex["saturation_at_m"]))
-    wl = None if args.skip_large else W.config(3)
-    kl = max(20, min(200, K // 10))
-    if wl is not None:
-        out_extra.update(large_measurements(wl, kl, torch, native))
-
-    if args.extra:
-        log("batched scan: 64 simulations")
-        ws = W.batch_configs(64, steps=100)
-        b = native.batch_from_workloads(ws, precision="f32", every=100, spectrum=False)
-        b.tune(2)
-        b.run(8)
-        b.sync()
-        nb = 100
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.run(nb)
-        b.sync()
-        dtb = time.perf_counter() - t0
-        b.close()
-        seq = 0.0
-        for i, wi in enumerate(ws):
-            s = native.sim_from_workload(wi, precision="f32", every=100, spectrum=False)
-            s.run(8)
-            s.sync()
-            seq += timed_run(s, nb, torch)
-            s.close()
-        cells = sum(x.ncell for x in ws)
-        out_extra["batch"] = {"simulations": 64, "steps": nb, "batched_s": round(dtb, 4),
-                              "sequential_s": round(seq, 4), "speedup": round(seq / dtb, 3),
-                              "cell_updates_per_s": cells * nb / dtb}
+    if not args.no_f64:
+        log("same shape in f64, %d steps" % K)
+        dt64, dt64_ev, per64, dg64, info64 = measure(w, "f64", K, Wm, torch, native)
+        nbp64 = boundary_points(w, info64["stencil_tile"][0])
+        n = min(len(dg), len(dg64))
+        acc = {"rows": n,
+               "probe_Ex_rel_l2": rel_l2(dg["probe_E"][:n, 0], dg64["probe_E"][:n, 0]),
+               "power_rel_l2": rel_l2(dg["power"][:n], dg64["power"][:n])}
+        out_extra["fp64_same_shape"] = {
+            "workload": wname, "dtype": "f64", "steps": K,
+            "ms_per_step": round(dt64 * 1e3 / K, 5),
+            "event_region_ms_per_step": round(dt64_ev * 1e3 / K, 5),
+            "cell_updates_per_s": w.ncell * K / dt64,
+            "particle_pushes_per_s": w.np * K * w.substeps / dt64,
+            "kernels": kernels_table(per64, w, 8, nbp64),
+            "roofline": roofline_block("stencil", per64["stencil"],
+                                       kernel_bytes("stencil", w, 8),
+                                       traffic_from_profile("stencil", "large-f64")),
+            "roofline_push": push_roofline(per64, w, 8, tiles, "large-f64")}
+        out_extra["speedup_fp32_vs_fp64"] = round(dt64 / dt, 3)
+        out_extra["fp32_vs_fp64_accuracy"] = acc
+        log("  %.4f ms/step; f32 against f64 over %d rows: probe Ex %.2e, power %.2e"
+            % (dt64 * 1e3 / K, n, acc["probe_Ex_rel_l2"], acc["power_rel_l2"]))
+    if not args.no_batch:
+        log("batched scan: 64 simulations, %d steps, against 64 sequential runs"
+            % args.batch_steps)
+        out_extra["batch"] = batch_leg(args.batch_steps, torch, native, W)
+        log("  batched %.3f s, sequential %.3f s" % (out_extra["batch"]["batched_s"],
+                                                     out_extra["batch"]["sequential_s"]))
+    if not args.no_mid:
+        out_extra.update(mid_legs(args, K, Wm, torch, native, W))
 
     cpu = None
-    if not args.no_cpu and args.workload == "mid":  # a large step takes minutes on one core
-        log("cpu baseline: oracle, %d steps of the mid configuration" % args.cpu_steps)
-        cpu = cpu_baseline(w, args.cpu_steps)
-        log("  %.3e cell-updates/s" % cpu["value"])
+    if not args.no_cpu:
+        log("cpu baseline: oracle on a %d-plane slab of the large configuration"
+            % args.cpu_planes)
+        cpu = cpu_baseline(w, args.cpu_planes, 3, 6)
+        log("  %.3e cell-updates/s on %d threads, %.3e on one" % (
+            cpu["value"], cpu["cores"], cpu["single_thread"]["value"]))
 
     line = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": round(ms_step, 5), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wname, "mesh": list(w.n), "particles": w.np,
-                   "precision": prec, "courant": w.courant, "nsfd_A": info["nsfd_A"],
-                   "substeps": w.substeps, "space_charge": w.space_charge,
-                   "gamma": w.gamma_beam, "K": w.K, "lambda_u": w.lambda_u,
-                   "mesh_diag_every": 100, "stencil_tile": info["stencil_tile"]},
+                   "precision": "f32 split (int32 cell + f32 offset, f64 reductions)",
+                   "courant": w.courant, "nsfd_A": info["nsfd_A"], "substeps": w.substeps,
+                   "space_charge": w.space_charge, "gamma": w.gamma_beam, "K": w.K,
+                   "lambda_u": w.lambda_u, "mesh_diag_every": 100,
+                   "stencil_tile": info["stencil_tile"]},
         "particle_pushes_per_s": pushes,
+        "event_region_ms_per_step": round(dt_ev * 1e3 / K, 5),
         "whole_step_algorithmic_GBs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
         "roofline": roofline,
+        "roofline_push": roof_push,
         "kernels": kernels,
-        "event_region_ms_per_step": round(dt_ev * 1e3 / K, 5),
         "lost": int(dg["lost"][-1]) if len(dg) else 0,
+        "nonfinite": bool(dg["nonfinite"].any()) if len(dg) else False,
         "cpu_baseline": cpu,
     }
     line.update(out_extra)

@@ -329,6 +329,21 @@ mithra_status mithra_set_field(mithra_sim *sim, mithra_field which, const double
 mithra_status mithra_get_particles(mithra_sim *sim, double *pos, double *u, uint8_t *alive,
                                    int64_t *np_alive);
 
+/* The binning of the particles by cell that the deposit of the next step
+   reads (the paper's deposition, section "Current Deposition", sums over the
+   particles of each cell's neighbourhood; the library keeps them sorted by
+   cell for that).  Cells are grouped in tiles of 8x8x8: with
+   nt[a] = ceil(n[a] / 8), the key of cell (i, j, k) is
+   ((k/8 * nt[1] + j/8) * nt[0] + i/8) * 512 + ((k%8) * 8 + j%8) * 8 + i%8,
+   and key nkeys = nt[0] nt[1] nt[2] 512 holds the lost particles.
+   keys [np]: the key of the particle in each slot of the particle buffer;
+   ids [np]: its input index; starts [nkeys + 2]: the first slot of each key
+   (starts[nkeys + 1] = np), so the particles of key g sit in slots
+   starts[g] .. starts[g+1]-1, in no fixed order inside a key.  Any pointer
+   may be NULL; *nkeys receives nkeys.  ESTATE before the first run. */
+mithra_status mithra_get_bins(mithra_sim *sim, int32_t *keys, int32_t *ids, int32_t *starts,
+                              int64_t *nkeys);
+
 /* Copy the unread diagnostic rows (oldest first, at most cap) and mark them
    read; at most the last `capacity` rows are kept. */
 mithra_status mithra_get_diag(mithra_sim *sim, mithra_diag_row *rows, int64_t cap,

@@ -1048,8 +1048,13 @@ static mithra_status run_impl(Batch &b, int64_t nsteps)
         b.step += nsteps;
         return MITHRA_OK;
     }
+    // The step graph is captured and instantiated on the first run after
+    // any change of the launch tables, whatever its length, so that the
+    // one-off cost of building it falls on that run and not on a later,
+    // longer one; runs replay it G steps at a time and enqueue the rest
+    // directly.
     const int G = b.graph_steps;
-    if (nsteps >= G && !b.gexec) {
+    if (!b.gexec) {
         HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
         for (int i = 0; i < G; ++i) enqueue_step<R>(b, false);
         hipError_t e = hipStreamEndCapture(b.stream, &b.graph);
@@ -1260,6 +1265,31 @@ static mithra_status get_particles(Batch &b, int s, double *pos, double *u, uint
     if (st) return st;
     return b.prec == MITHRA_F64 ? get_particles_impl<double>(b, s, pos, u, alive, np_alive)
                                 : get_particles_impl<float>(b, s, pos, u, alive, np_alive);
+}
+
+// the binning of the current particle buffer, as the next step reads it
+static mithra_status get_bins(Batch &b, int s, int32_t *keys, int32_t *ids, int32_t *starts,
+                              int64_t *nkeys)
+{
+    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
+    if (!b.committed) return fail(MITHRA_ESTATE, "particles are not on the device yet (run first)");
+    mithra_status st = sync_stream(b);
+    if (st) return st;
+    const SimDev &S = b.sd[s];
+    const int par = (int)(b.step & 1);
+    if (nkeys) *nkeys = S.nkeys;
+    if (S.np > 0 && keys) {
+        HIP_TRY(hipMemcpy(keys, b.ar.key[par] + S.part0, sizeof(int) * S.np, hipMemcpyDeviceToHost));
+        for (long long i = 0; i < S.np; ++i) keys[i] -= (int32_t)S.key0;
+    }
+    if (S.np > 0 && ids)
+        HIP_TRY(hipMemcpy(ids, b.ar.id[par] + S.part0, sizeof(int) * S.np, hipMemcpyDeviceToHost));
+    if (starts) {
+        HIP_TRY(hipMemcpy(starts, b.ar.offs[par] + S.key0, sizeof(int) * ((size_t)S.nkeys + 2),
+                          hipMemcpyDeviceToHost));
+        for (long long g = 0; g < (long long)S.nkeys + 2; ++g) starts[g] -= (int32_t)S.part0;
+    }
+    return MITHRA_OK;
 }
 
 static mithra_status get_diag(Batch &b, int s, mithra_diag_row *rows, int64_t cap, int64_t *nrows)
@@ -1927,6 +1957,13 @@ mithra_status mithra_get_particles(mithra_sim *sim, double *pos, double *u, uint
 {
     if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
     return get_particles(*sim->b, 0, pos, u, alive, np_alive);
+}
+
+mithra_status mithra_get_bins(mithra_sim *sim, int32_t *keys, int32_t *ids, int32_t *starts,
+                              int64_t *nkeys)
+{
+    if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
+    return get_bins(*sim->b, 0, keys, ids, starts, nkeys);
 }
 
 mithra_status mithra_get_diag(mithra_sim *sim, mithra_diag_row *rows, int64_t cap, int64_t *nrows)

@@ -39,6 +39,7 @@ ABI_FUNCTIONS = (
     "mithra_set_optical_undulator", "mithra_batch_set_optical_undulator",
     "mithra_set_optical_beam", "mithra_batch_set_optical_beam",
     "mithra_set_seed_beam", "mithra_batch_set_seed_beam", "mithra_set_background",
+    "mithra_get_bins",
 )
 
 SIGNALS = {"neumann": 0, "gaussian": 1, "secant": 2, "flat-top": 3}
@@ -177,6 +178,8 @@ def load_library(path: str = LIB_PATH):
         "mithra_get_particles": [P, dp, dp, ctypes.POINTER(ctypes.c_uint8),
                                  ctypes.POINTER(ctypes.c_int64)],
         "mithra_get_diag": [P, ctypes.POINTER(DiagRow), I64, ctypes.POINTER(ctypes.c_int64)],
+        "mithra_get_bins": [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)],
         "mithra_get_info": [P, ctypes.POINTER(Info)],
         "mithra_get_state": [P, P, ctypes.POINTER(ctypes.c_size_t)],
         "mithra_set_state": [P, P, ctypes.c_size_t],
@@ -428,6 +431,21 @@ class Sim:
         n = ctypes.c_int64()
         _check(self._lib.mithra_get_diag(self._h, rows, cap, ctypes.byref(n)))
         return _rows_to_array(rows, n.value)
+
+    def get_bins(self):
+        """(keys [np], ids [np], starts [nkeys + 2], nkeys) of the particle
+        buffer the next step reads."""
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        nk = ctypes.c_int64()
+        _check(self._lib.mithra_get_bins(self._h, None, None, None, ctypes.byref(nk)))
+        npart = self._np
+        keys = np.empty(max(npart, 1), dtype=np.int32)
+        ids = np.empty(max(npart, 1), dtype=np.int32)
+        starts = np.empty(nk.value + 2, dtype=np.int32)
+        _check(self._lib.mithra_get_bins(self._h, keys.ctypes.data_as(i32),
+                                         ids.ctypes.data_as(i32), starts.ctypes.data_as(i32),
+                                         ctypes.byref(nk)))
+        return keys[:npart], ids[:npart], starts, int(nk.value)
 
     def info(self) -> dict:
         i = Info()

@@ -647,6 +647,82 @@ def test_mid_subcase_full_loop_f64():
     compare_diag(sim.get_diag(), orc.diag(), TOL64, "mid-subcase")
 
 
+@pytest.mark.timeout(1200)
+def test_mid_subcase_2000_steps_f64():
+    """The oracle-checkable slice of the mid configuration (64x64x128, 65536
+    particles) over the configuration's full 2000 steps: every diagnostic row
+    and, at the end, every array and particle.  The oracle runs its OpenMP
+    build (the same results as the plain one, bit for bit)."""
+    w = W.mid_subcase(steps=2000)
+    say("case", w.name, w.n, w.np, "steps", 2000, "f64 (oracle on %d threads)"
+        % oracle.threads(True))
+    sim = native.sim_from_workload(w, precision="f64", every=1, capacity=2048)
+    sim.run(2000)
+    sim.sync()
+    orc = oracle.from_workload(w, parallel=True)
+    for _ in range(20):
+        orc.step(100)
+        say("  oracle at step", orc.step_count)
+    compare_state(sim, orc, TOL64, "mid-subcase-2000")
+    compare_diag(sim.get_diag(), orc.diag(), TOL64, "mid-subcase-2000")
+
+
+def _host_counting_sort(sim, w):
+    """Bin keys of the particles from their positions (read back in SI and
+    mapped to cells on the host) and the bucket starts of a counting sort.
+    Positions within 1e-9 of a cell face may map to either cell on the host;
+    for those the device's key must be one of the two, and it is kept."""
+    pos, u, alive = sim.get_particles()
+    keys, ids, starts, nkeys = sim.get_bins()
+    nt = [(w.n[a] + 7) // 8 for a in range(3)]
+    assert nkeys == nt[0] * nt[1] * nt[2] * 512
+    dev_key = np.empty(w.np, dtype=np.int64)
+    dev_key[ids] = keys  # key the device gave particle id
+    v = (pos - np.asarray(w.origin)) / np.asarray(w.d)
+    v[~alive] = 0.0
+
+    def key_of(c):
+        t = ((c[:, 2] // 8) * nt[1] + c[:, 1] // 8) * nt[0] + c[:, 0] // 8
+        return t * 512 + ((c[:, 2] % 8) * 8 + c[:, 1] % 8) * 8 + c[:, 0] % 8
+
+    c = np.floor(v).astype(np.int64)
+    near = (v - c > 1.0 - 1e-9) & alive[:, None]
+    exp_key = key_of(c)
+    up = key_of(c + near.astype(np.int64))
+    amb = near.any(axis=1)
+    assert np.all((dev_key[amb] == exp_key[amb]) | (dev_key[amb] == up[amb]))
+    exp_key[amb] = dev_key[amb]
+    exp_key[~alive] = nkeys
+    counts = np.bincount(exp_key, minlength=nkeys + 1)
+    exp_starts = np.concatenate([[0], np.cumsum(counts)])
+    return keys, ids, starts, exp_key, exp_starts, int(amb.sum())
+
+
+@pytest.mark.parametrize("precision,steps", [("f64", 7), ("f32", 8), ("f32", 15)])
+def test_binning_is_a_counting_sort(precision, steps):
+    """After a step the particle buffer is the counting sort of the particles
+    by cell key: the bucket starts equal the host's exclusive prefix sums of
+    the per-key counts, exactly; every slot holds a particle of its bucket's
+    key; the slots hold every particle once (lost ones in the last bucket).
+    The order inside a bucket is free and not compared."""
+    w = W.make_workload("bins", (64, 48, 96), 20000, 120.0, 1.3, 0.015, 1e-4, 4242, steps,
+                        sigma_cells=(6.0, 5.0, 10.0))
+    # a few particles start outside the live cells (lost at load)
+    w.x[:5, 0] = w.origin[0] + 0.5 * w.d[0]
+    say("case bins", w.n, w.np, precision, steps)
+    sim = native.sim_from_workload(w, precision=precision)
+    sim.run(steps)
+    sim.sync()
+    keys, ids, starts, exp_key, exp_starts, namb = _host_counting_sort(sim, w)
+    say("  ambiguous positions", namb, "lost", int(np.sum(exp_key == len(exp_starts) - 2)))
+    assert np.array_equal(starts, exp_starts)
+    assert np.array_equal(np.sort(ids), np.arange(w.np))
+    assert np.array_equal(keys.astype(np.int64), exp_key[ids])
+    slot = np.arange(w.np)
+    assert np.all((starts[keys] <= slot) & (slot < starts[keys + 1]))
+    sim.close()
+
+
 def test_mid_config_full_size_f64():
     """128x128x512, 1M particles, in the launch configuration the benchmark
     times: a few steps against the oracle at full size."""
@@ -913,6 +989,38 @@ def test_batch_with_mixed_boundaries_equals_separate_runs():
         for f in ("Ax", "Ay", "Az", "phi", "Jx", "rho", "Ez", "Bx"):
             assert np.array_equal(b.get_field(s, f), sim.get_field(f)), (s, f)
         assert b.get_diag(s).tobytes() == sim.get_diag().tobytes()
+        sim.close()
+    b.close()
+
+
+@pytest.mark.timeout(900)
+def test_batch_config_full_size_sims_equal_separate_runs_bitwise():
+    """The 64-simulation scan at its full sizes, 200 steps in one batch; the
+    simulations with the fewest and the most cells and the median one, each
+    run alone for 200 steps, give the same fields, particles and diagnostic
+    rows bit for bit."""
+    steps = 200
+    ws = W.batch_configs(64, steps=steps)
+    say("case full batch, bitwise", len(ws), "simulations", steps, "steps")
+    b = native.batch_from_workloads(ws, precision="f32", every=10, spectrum=False,
+                                    capacity=steps + 8)
+    b.run(steps)
+    b.sync()
+    order = sorted(range(len(ws)), key=lambda i: ws[i].ncell)
+    for s in (order[0], order[len(order) // 2], order[-1]):
+        w = ws[s]
+        say("  simulation", s, w.n, w.np)
+        sim = native.sim_from_workload(w, precision="f32", every=10, spectrum=False,
+                                       capacity=steps + 8)
+        sim.run(steps)
+        sim.sync()
+        for f in ("Ax", "Ay", "Az", "phi", "Jx", "Jy", "Jz", "rho", "Ex", "By"):
+            assert np.array_equal(b.get_field(s, f), sim.get_field(f)), (s, f)
+        pb, ub, ab = b.get_particles(s)
+        ps, us, as_ = sim.get_particles()
+        assert np.array_equal(ab, as_), s
+        assert np.array_equal(pb[ab], ps[as_]) and np.array_equal(ub, us), s
+        assert b.get_diag(s).tobytes() == sim.get_diag().tobytes(), s
         sim.close()
     b.close()
 
