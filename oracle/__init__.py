@@ -25,12 +25,13 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # build's bit for bit.  For long oracle runs and the all-core CPU baseline.
 _LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
-NDIAG = 27
+NDIAG = 29
+MAXF = 32
 DIAG_COLUMNS = ("step", "t", "total_charge", "continuity_residual", "power",
                 "field_energy", "kinetic_energy", "Ex", "Ey", "Ez", "Bx", "By",
                 "Bz", "lost", "nonfinite", "spare", "bunching1", "bunching2",
                 "bunching3", "spare2", "power_h1", "power_h2", "power_h3", "spare3",
-                "power_extra1", "power_extra2", "power_extra3")
+                "power_extra1", "power_extra2", "power_extra3", "power_lab", "z_undulator")
 
 _lib = None
 
@@ -118,6 +119,8 @@ def _open(path):
     lib.orc_seed_signal.restype = D
     lib.orc_config_diag.argtypes = [P, I, I, I, I]
     lib.orc_config_extra_planes.argtypes = [P, I, I, I]
+    lib.orc_set_spectrum.argtypes = [P, dp, I]
+    lib.orc_set_undulator_length.argtypes = [P, D]
     for name in ("orc_field_update", "orc_vertex_fields", "orc_push", "orc_deposit",
                  "orc_rotate"):
         getattr(lib, name).argtypes = [P]
@@ -238,6 +241,28 @@ class OracleSim:
         self._lib.orc_config_diag(self._h, int(probe[0]), int(probe[1]), int(probe[2]), int(kp))
         k = list(extra_planes) + [-1] * (3 - len(extra_planes))
         self._lib.orc_config_extra_planes(self._h, int(k[0]), int(k[1]), int(k[2]))
+
+    def set_spectrum(self, nu):
+        """Normalized frequencies nu_f (omega_f = nu_f omega_1) of the plane
+        spectrum, at most 32; restarts it."""
+        nu = np.ascontiguousarray(nu, dtype=np.float64).reshape(-1)
+        self._nfreq = int(nu.size)
+        self._lib.orc_set_spectrum(self._h, _dptr(nu), int(nu.size))
+
+    def set_undulator_length(self, length):
+        """Lab length of the static undulator [m] (whole periods); <= 0: unbounded."""
+        self._lib.orc_set_undulator_length(self._h, float(length))
+
+    def spectrum_rows(self):
+        """(rest, lab): the mean power [W] at each frequency since the
+        restart, one row per step, in the bunch frame and in the lab."""
+        nd = int(self._lib.orc_info(self._h, 3))
+        nf = getattr(self, "_nfreq", 3)
+        if nd == 0:
+            return np.zeros((0, nf)), np.zeros((0, nf))
+        ptr = self._lib.orc_array(self._h, 27)
+        a = np.ctypeslib.as_array(ptr, shape=(nd, 2, MAXF)).copy()
+        return a[:, 0, :nf], a[:, 1, :nf]
 
     # ---- stepping ----------------------------------------------------------
     def step(self, nsteps=1):

@@ -97,7 +97,8 @@
 #define ORC_MU0 (1.0 / (ORC_EPS0 * ORC_C * ORC_C))
 #define ORC_PI 3.14159265358979323846
 
-#define ORC_NDIAG 27
+#define ORC_NDIAG 29
+#define ORC_MAXF 32 /* normalized frequencies of the plane spectrum */
 
 typedef struct orc_sim {
     int n[3];
@@ -120,6 +121,7 @@ typedef struct orc_sim {
     int opt_beam;
     double opt_zr[2], opt_focus[3];
     double lambda_u, K, gamma_beam, z_e;
+    double und_len; /* lab length of the static undulator from z' = 0; <= 0: unbounded */
     /* derived constants */
     double dt, dtb, a1, a2, a4, a6, a8;
     double mur[3][5];
@@ -142,10 +144,16 @@ typedef struct orc_sim {
     int kp_extra[3]; /* further sampling plates (-1: none), power only */
     double *diag;
     long ndiag, cap;
-    /* running DFT of Ex, Ey, Bx, By on the power plane at h omega_1 (h = 1..3):
-       per plane point 3 x 4 complex sums (reading R22) */
+    /* running DFT of Ex, Ey, Bx, By on the power plane at nu_f omega_1
+       (reading R22; f < nfreq, nu = 1, 2, 3 unless set): per plane point and
+       frequency 4 complex sums, restarted when particles are loaded */
+    int nfreq;
+    double fnu[ORC_MAXF];
     double *spec;
     long nspec;
+    /* per row: the mean power at each frequency since the restart, rest
+       frame then lab frame (2 nfreq doubles) */
+    double *srow;
 } orc_sim;
 
 /* ---- indexing ---------------------------------------------------------- */
@@ -273,8 +281,12 @@ orc_sim *orc_create(const int n[3], const double d[3], const double origin[3],
     for (int e = 0; e < 3; e++) s->kp_extra[e] = -1;
     s->cap = 1024;
     s->diag = (double *)malloc(sizeof(double) * ORC_NDIAG * s->cap);
-    s->spec = (double *)calloc((size_t)n[0] * n[1] * 24, sizeof(double));
+    s->nfreq = 3;
+    for (int f = 0; f < 3; f++) s->fnu[f] = f + 1.0;
+    s->spec = (double *)calloc((size_t)n[0] * n[1] * 8 * s->nfreq, sizeof(double));
     s->nspec = 0;
+    s->srow = (double *)malloc(sizeof(double) * 2 * ORC_MAXF * s->cap);
+    s->und_len = 0.0;
     return s;
 }
 
@@ -297,6 +309,7 @@ void orc_destroy(orc_sim *s)
     free(s->alive);
     free(s->diag);
     free(s->spec);
+    free(s->srow);
     free(s);
 }
 
@@ -314,6 +327,23 @@ void orc_config_diag(orc_sim *s, int pi, int pj, int pk, int kp)
     s->probe[2] = pk;
     s->kp = kp;
 }
+
+/* Normalized frequencies of the plane spectrum (section "FEL-OUTPUT":
+   normalized-frequency, or a sweep from the minimum to the maximum at the
+   given resolution), nu_f = omega_f / omega_1; the running DFT restarts. */
+void orc_set_spectrum(orc_sim *s, const double *nu, int nfreq)
+{
+    if (nfreq < 1 || nfreq > ORC_MAXF) abort();
+    s->nfreq = nfreq;
+    for (int f = 0; f < nfreq; f++) s->fnu[f] = nu[f];
+    free(s->spec);
+    s->spec = (double *)calloc((size_t)s->n[0] * s->n[1] * 8 * nfreq, sizeof(double));
+    s->nspec = 0;
+}
+
+/* Total lab length of the static undulator (section "UNDULATOR", length),
+   a whole number of periods; <= 0 leaves it unbounded. */
+void orc_set_undulator_length(orc_sim *s, double length) { s->und_len = length; }
 
 /* Further sampling plates (section "FEL-OUTPUT": the plate distance may be
    repeated): the radiated power through planes k1..k3, -1 for none. */
@@ -445,6 +475,9 @@ int orc_set_particles(orc_sim *s, long np, const double *x, const double *u, dou
         deposit_rho(s, s->rho, &s->x[3 * p]);
     }
     memcpy(s->rho_prev, s->rho, sizeof(double) * s->ncell);
+    /* the plane spectrum is a mean since the particles were loaded */
+    memset(s->spec, 0, sizeof(double) * (size_t)s->n[0] * s->n[1] * 8 * s->nfreq);
+    s->nspec = 0;
     return 0;
 }
 
@@ -945,7 +978,13 @@ void orc_undulator(const orc_sim *s, double x, double y, double z, double t, dou
     }
     double zp = s->gamma0 * (z - s->z_e + s->beta0 * ORC_C * t); /* lab z' */
     double ph = s->ku * zp, by, bz;
-    if (zp >= 0.0) {
+    if (s->und_len > 0.0 && zp > s->und_len) {
+        /* past the exit (reading R26): the entrance fringe mirrored about
+           z' = L, which joins the last whole period in value and slope */
+        double pe = s->ku * (zp - s->und_len), g = exp(-pe * pe / 2.0);
+        by = s->B0 * cosh(s->ku * y) * pe * g;
+        bz = s->B0 * sinh(s->ku * y) * g;
+    } else if (zp >= 0.0) {
         by = s->B0 * cosh(s->ku * y) * sin(ph);
         bz = s->B0 * sinh(s->ku * y) * cos(ph);
     } else {
@@ -1053,14 +1092,16 @@ void orc_deposit(orc_sim *s)
    number of the ponderomotive phase in the frame of the undulator-averaged
    bunch (k_u = 2 pi / lambda_u in the lab). */
 
-/* Power at the harmonics h omega_1 (h = 1, 2, 3) of the rest-frame resonant
+/* Power at the normalized frequencies nu_f of the rest-frame resonant
    frequency omega_1 = gamma0 beta0 c k_u through the power plane (reading
-   R22).  Each step adds the sample at t = (s + 1/2) dt to the running DFT
+   R22; section "FEL-OUTPUT", normalized-frequency and its sweep).  Each step
+   adds the sample at t = (s + 1/2) dt to the running DFT
    F(omega) = sum_n f(t_n) exp(-i omega t_n) dt of Ex, Ey, Bx, By at every
    plane point; after T = (number of samples) dt the mean power carried at
    omega is (2 / T^2) sum_plane Re(F_Ex conj(F_By) - F_Ey conj(F_Bx)) / mu0 dx dy,
    which for a field that is a pure tone over whole periods equals the time
-   mean of the instantaneous Poynting flux. */
+   mean of the instantaneous Poynting flux.  The normalized frequency is the
+   same in both frames for waves along z. */
 
 static double omega1(const orc_sim *s)
 {
@@ -1072,15 +1113,16 @@ void orc_spectrum_sample(orc_sim *s)
     int lo[2], hi[2];
     for (int a = 0; a < 2; a++) interior(s, a, &lo[a], &hi[a]);
     const double t = (s->step + 0.5) * s->dt;
-    for (int h = 1; h <= 3; h++) {
-        const double w = h * omega1(s);
+    const int nf = s->nfreq;
+    for (int fq = 0; fq < nf; fq++) {
+        const double w = s->fnu[fq] * omega1(s);
         const double cs = cos(w * t), sn = sin(w * t);
 #pragma omp parallel for schedule(static)
         for (int j = lo[1]; j <= hi[1]; j++)
             for (int i = lo[0]; i <= hi[0]; i++) {
                 long p = IX(s, i, j, s->kp);
                 const double f[4] = {s->E[0][p], s->E[1][p], s->B[0][p], s->B[1][p]};
-                double *acc = &s->spec[((long)j * s->n[0] + i) * 24 + (h - 1) * 8];
+                double *acc = &s->spec[(((long)j * s->n[0] + i) * nf + fq) * 8];
                 for (int c = 0; c < 4; c++) {
                     acc[2 * c] += f[c] * cs * s->dt;
                     acc[2 * c + 1] -= f[c] * sn * s->dt;
@@ -1090,20 +1132,43 @@ void orc_spectrum_sample(orc_sim *s)
     s->nspec++;
 }
 
-static void harmonic_power(const orc_sim *s, double *P)
+/* The fields of the bunch frame seen in the lab (the frame moves along +z at
+   beta0 c): E_x = g (E'_x + b c B'_y), E_y = g (E'_y - b c B'_x),
+   B_x = g (B'_x - b E'_y / c), B_y = g (B'_y + b E'_x / c), E_z and B_z
+   unchanged (section "Lorentz Transformation").  f = (Ex, Ey, Bx, By). */
+static void to_lab(const orc_sim *s, const double *f, double *lab)
+{
+    const double g = s->gamma0, b = s->beta0;
+    lab[0] = g * (f[0] + b * ORC_C * f[3]);
+    lab[1] = g * (f[1] - b * ORC_C * f[2]);
+    lab[2] = g * (f[2] - b * f[1] / ORC_C);
+    lab[3] = g * (f[3] + b * f[0] / ORC_C);
+}
+
+/* mean power at each frequency since the restart, in the bunch frame (rest)
+   and, from the same DFT sums taken to the lab by to_lab, in the lab */
+static void spectrum_power(const orc_sim *s, double *rest, double *lab)
 {
     int lo[2], hi[2];
     for (int a = 0; a < 2; a++) interior(s, a, &lo[a], &hi[a]);
     const double T = s->nspec * s->dt;
-    for (int h = 1; h <= 3; h++) {
-        double sum = 0.0;
+    const int nf = s->nfreq;
+    for (int fq = 0; fq < nf; fq++) {
+        double sr = 0.0, sl = 0.0;
         for (int j = lo[1]; j <= hi[1]; j++)
             for (int i = lo[0]; i <= hi[0]; i++) {
-                const double *a = &s->spec[((long)j * s->n[0] + i) * 24 + (h - 1) * 8];
+                const double *a = &s->spec[(((long)j * s->n[0] + i) * nf + fq) * 8];
                 /* a[0..1] Ex, a[2..3] Ey, a[4..5] Bx, a[6..7] By (re, im) */
-                sum += (a[0] * a[6] + a[1] * a[7]) - (a[2] * a[4] + a[3] * a[5]);
+                sr += (a[0] * a[6] + a[1] * a[7]) - (a[2] * a[4] + a[3] * a[5]);
+                const double re[4] = {a[0], a[2], a[4], a[6]}, im[4] = {a[1], a[3], a[5], a[7]};
+                double lr[4], li[4];
+                to_lab(s, re, lr);
+                to_lab(s, im, li);
+                sl += (lr[0] * lr[3] + li[0] * li[3]) - (lr[1] * lr[2] + li[1] * li[2]);
             }
-        P[h - 1] = s->nspec > 0 ? 2.0 / (T * T) * sum / ORC_MU0 * s->d[0] * s->d[1] : 0.0;
+        const double k = s->nspec > 0 ? 2.0 / (T * T) / ORC_MU0 * s->d[0] * s->d[1] : 0.0;
+        rest[fq] = k * sr;
+        lab[fq] = k * sl;
     }
 }
 
@@ -1123,6 +1188,24 @@ static void bunching(const orc_sim *s, double *b)
     for (int h = 0; h < 3; h++) b[h] = n > 0 ? sqrt(re[h] * re[h] + im[h] * im[h]) / (double)n : 0.0;
 }
 
+/* the flux of the lab Poynting vector of the self field (the fields of
+   plane k taken to the lab by to_lab) through the plane k */
+static double plane_power_lab(const orc_sim *s, int k)
+{
+    int lo[2], hi[2];
+    for (int a = 0; a < 2; a++) interior(s, a, &lo[a], &hi[a]);
+    double power = 0.0;
+    for (int j = lo[1]; j <= hi[1]; j++)
+        for (int i = lo[0]; i <= hi[0]; i++) {
+            long p = IX(s, i, j, k);
+            const double f[4] = {s->E[0][p], s->E[1][p], s->B[0][p], s->B[1][p]};
+            double l[4];
+            to_lab(s, f, l);
+            power += (l[0] * l[3] - l[1] * l[2]) / ORC_MU0 * s->d[0] * s->d[1];
+        }
+    return power;
+}
+
 /* radiated power: the flux of the Poynting vector of the self field through
    the plane k, over the interior points */
 static double plane_power(const orc_sim *s, int k)
@@ -1138,7 +1221,17 @@ static double plane_power(const orc_sim *s, int k)
     return power;
 }
 
+static void diag_row(orc_sim *s, double *row, double *rest, double *lab);
+
 void orc_diag_row(orc_sim *s, double *row)
+{
+    double rest[ORC_MAXF], lab[ORC_MAXF];
+    diag_row(s, row, rest, lab);
+}
+
+/* the row, and the mean power at each frequency in the bunch frame (rest)
+   and in the lab (lab) */
+static void diag_row(orc_sim *s, double *row, double *rest, double *lab)
 {
     int lo[3], hi[3];
     for (int a = 0; a < 3; a++) interior(s, a, &lo[a], &hi[a]);
@@ -1194,9 +1287,14 @@ void orc_diag_row(orc_sim *s, double *row)
     row[15] = 0.0;
     bunching(s, &row[16]);
     row[19] = 0.0;
-    harmonic_power(s, &row[20]);
+    spectrum_power(s, rest, lab);
+    for (int f = 0; f < 3; f++) row[20 + f] = f < s->nfreq ? rest[f] : 0.0;
     row[23] = 0.0;
     for (int e = 0; e < 3; e++) row[24 + e] = s->kp_extra[e] >= 0 ? plane_power(s, s->kp_extra[e]) : 0.0;
+    /* FEL output in the lab: the lab flux through the plane and the plane's
+       position along the undulator at the row's time */
+    row[27] = plane_power_lab(s, s->kp);
+    row[28] = s->gamma0 * (s->o[2] + s->kp * s->d[2] - s->z_e + s->beta0 * ORC_C * row[1]);
 }
 
 /* ---- O11: rotate the time levels ------------------------------------------ */
@@ -1222,8 +1320,10 @@ void orc_step(orc_sim *s, long nsteps)
         if (s->ndiag == s->cap) {
             s->cap *= 2;
             s->diag = (double *)realloc(s->diag, sizeof(double) * ORC_NDIAG * s->cap);
+            s->srow = (double *)realloc(s->srow, sizeof(double) * 2 * ORC_MAXF * s->cap);
         }
-        orc_diag_row(s, &s->diag[ORC_NDIAG * s->ndiag]);
+        double *sr = &s->srow[2 * ORC_MAXF * s->ndiag];
+        diag_row(s, &s->diag[ORC_NDIAG * s->ndiag], sr, sr + ORC_MAXF);
         s->ndiag++;
         orc_rotate(s);
     }
@@ -1248,6 +1348,7 @@ double *orc_array(orc_sim *s, int which)
     if (which == 24) return s->u;
     if (which == 25) return s->x_old;
     if (which == 26) return s->diag;
+    if (which == 27) return s->srow;
     return NULL;
 }
 

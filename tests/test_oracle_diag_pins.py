@@ -214,12 +214,12 @@ MUTANTS = [
      "0.5 * ORC_EPS0 * e2", "ORC_EPS0 * e2", pin_uniform_fields),
     ("field energy with mu0 multiplied", "void orc_diag_row",
      "0.5 * b2 / ORC_MU0", "0.5 * b2 * ORC_MU0", pin_uniform_fields),
-    ("flux with the E_y B_x sign flipped", "static double plane_power",
+    ("flux with the E_y B_x sign flipped", "static double plane_power(",
      "- s->E[1][p] * s->B[0][p]", "+ s->E[1][p] * s->B[0][p]",
      lambda: pin_plane_wave(1, 1)),
-    ("flux without dy", "static double plane_power",
+    ("flux without dy", "static double plane_power(",
      "/ ORC_MU0 * s->d[0] * s->d[1]", "/ ORC_MU0 * s->d[0]", pin_uniform_fields),
-    ("flux plane one row short", "static double plane_power",
+    ("flux plane one row short", "static double plane_power(",
      "j <= hi[1]", "j < hi[1]", pin_uniform_fields),
     ("kinetic energy with gamma for gamma - 1", "void orc_diag_row",
      " - 1.0) * s->m * ORC_C * ORC_C", ") * s->m * ORC_C * ORC_C",
