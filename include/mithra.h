@@ -320,6 +320,18 @@ mithra_status mithra_sync(mithra_sim *sim);
 /* Copy a mesh quantity to host (n[0]*n[1]*n[2] doubles, layout above). */
 mithra_status mithra_get_field(mithra_sim *sim, mithra_field which, double *host);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): mithra_get_field without
+   any device or host allocation.  The output is the same as
+   mithra_get_field's, bit for bit.  E and B are computed, and float fields
+   widened to double, in the library's static scratch of 6 x 2^18 doubles
+   (12 MiB per GPU, held until the process ends), a chunk of whole z-planes
+   at a time; a mesh whose z-plane has more than 2^18 = 262144 points
+   (n[0] * n[1]) is EINVAL.  Every call on one GPU shares that GPU's scratch:
+   calls that overlap on one GPU (from several threads, or simulations on
+   other streams) race and must be serialized by the caller. */
+mithra_status mithra_get_field_noalloc(mithra_sim *sim, mithra_field which, double *host);
+
 /* Overwrite a stored mesh quantity (potentials at the newest or previous
    level, J, rho, rho_prev) from host doubles; E/B are derived and EINVAL. */
 mithra_status mithra_set_field(mithra_sim *sim, mithra_field which, const double *host);

@@ -2059,13 +2059,14 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
 // (levels s-1 and s after s steps), in double, component-major.
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_vertex_fields(const SimDev *__restrict__ sims, int sim,
-                                                          long long ncell, Arena ar,
+                                                          long long g0, long long count, Arena ar,
                                                           double *__restrict__ out)
 {
     const SimDev &S = sims[sim];
     const long long step = *ar.d_step;
-    const long long g = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    if (g >= ncell) return;
+    const long long e = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= count) return;
+    const long long g = g0 + e;
     const int i = (int)(g % S.n[0]), j = (int)((g / S.n[0]) % S.n[1]),
               k = (int)(g / ((long long)S.n[0] * S.n[1]));
     R E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
@@ -2074,9 +2075,17 @@ __global__ __launch_bounds__(BLOCK) void k_vertex_fields(const SimDev *__restric
         vertex_EB<R>(S, f, i, j, k, E, B);
     }
     for (int a = 0; a < 3; ++a) {
-        out[a * ncell + g] = (double)E[a];
-        out[(3 + a) * ncell + g] = (double)B[a];
+        out[a * count + e] = (double)E[a];
+        out[(3 + a) * count + e] = (double)B[a];
     }
+}
+
+// count values of a mesh array, widened to double
+__global__ __launch_bounds__(BLOCK) void k_to_double(const float *__restrict__ src, long long count,
+                                                      double *__restrict__ out)
+{
+    const long long e = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (e < count) out[e] = (double)src[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -2206,11 +2215,17 @@ void launch_background(hipStream_t st, const SimDev *sims, int sim, long long nc
 }
 
 template <typename R>
-void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long ncell,
-                          const Arena &ar, double *out6)
+void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long g0,
+                          long long count, const Arena &ar, double *out6)
 {
-    hipLaunchKernelGGL((k_vertex_fields<R>), dim3((unsigned)((ncell + BLOCK - 1) / BLOCK)),
-                       dim3(BLOCK), 0, st, sims, sim, ncell, ar, out6);
+    hipLaunchKernelGGL((k_vertex_fields<R>), dim3((unsigned)((count + BLOCK - 1) / BLOCK)),
+                       dim3(BLOCK), 0, st, sims, sim, g0, count, ar, out6);
+}
+
+void launch_to_double(hipStream_t st, const float *src, long long count, double *out)
+{
+    hipLaunchKernelGGL(k_to_double, dim3((unsigned)((count + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       st, src, count, out);
 }
 
 #define MITHRA_INSTANTIATE(R)                                                                   \
@@ -2228,7 +2243,7 @@ void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long
     template void launch_diag<R>(hipStream_t, const SimDev *, int, const int2 *, int,           \
                                  const int2 *, int, const int2 *, int, const Arena &);          \
     template void launch_vertex_fields<R>(hipStream_t, const SimDev *, int, long long,          \
-                                          const Arena &, double *);                             \
+                                          long long, const Arena &, double *);                  \
     template void launch_background<R>(hipStream_t, const SimDev *, int, long long,             \
                                        const Arena &);
 

@@ -176,9 +176,12 @@ template <typename R>
 void launch_diag(hipStream_t st, const SimDev *sims, int nsim, const int2 *plane_items,
                  int nplane, const int2 *mesh_items, int nmesh, const int2 *kin_items, int nkin,
                  const Arena &ar);
+// E and B of cells g0 .. g0+count-1 of simulation `sim` into out6: component
+// a (Ex, Ey, Ez, Bx, By, Bz) of cell g0 + e at out6[a * count + e]
 template <typename R>
-void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long ncell,
-                          const Arena &ar, double *out6);
+void launch_vertex_fields(hipStream_t st, const SimDev *sims, int sim, long long g0,
+                          long long count, const Arena &ar, double *out6);
+void launch_to_double(hipStream_t st, const float *src, long long count, double *out);
 bool stencil_shape_supported(int tx, int ty);
 
 }  // namespace mithra

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,17 @@ static const double MU0 = 1.0 / (EPS0 * C_LIGHT * C_LIGHT);
 static const double PI = 3.14159265358979323846;
 
 static thread_local std::string g_err;
+
+// Scratch of the allocation-free read-back (mithra_get_field_noalloc): the six
+// vertex-field components of NOALLOC_CELLS cells, or one field widened to
+// double.  Each GPU the library runs on holds its own copy until the process
+// ends; its address on a device comes from hipGetSymbolAddress, taken once
+// per device when the first simulation is created there.
+constexpr long long NOALLOC_CELLS = 1LL << 18;
+static __device__ __align__(256) double scratch[6 * NOALLOC_CELLS];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
 static void *(*g_alloc)(size_t, void *) = nullptr;
 static void (*g_free)(void *, void *) = nullptr;
 static void *g_alloc_ctx = nullptr;
@@ -664,6 +676,20 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
         return fail(MITHRA_EDEVICE, "device %d is %s; this library is built for gfx950 only", dev,
                     prop.gcnArchName);
 
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return fail(MITHRA_EDEVICE, "device index %d beyond the %d the library supports", dev,
+                    MAX_DEVICES);
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void *ptr = nullptr;
+            hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(MITHRA_EDEVICE, "address of the read-back scratch on device %d: %s",
+                            dev, hipGetErrorString(e));
+            g_scratch_ptr[dev] = ptr;
+        }
+    }
     Batch *b = new Batch();
     b->device = dev;
     b->prec = prec;
@@ -1164,8 +1190,8 @@ static mithra_status get_field(Batch &b, int s, int which, double *host)
             b.d_eb = (double *)dev_alloc(b, sizeof(double) * 6 * maxc, b.mem_tab);
             if (!b.d_eb) return fail(MITHRA_ENOMEM, "device allocation failed");
         }
-        if (b.prec == MITHRA_F64) launch_vertex_fields<double>(b.stream, b.d_sims, s, ncell, b.ar, b.d_eb);
-        else launch_vertex_fields<float>(b.stream, b.d_sims, s, ncell, b.ar, b.d_eb);
+        if (b.prec == MITHRA_F64) launch_vertex_fields<double>(b.stream, b.d_sims, s, 0, ncell, b.ar, b.d_eb);
+        else launch_vertex_fields<float>(b.stream, b.d_sims, s, 0, ncell, b.ar, b.d_eb);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(host, b.d_eb + (size_t)(which - MITHRA_EX) * ncell,
                                sizeof(double) * ncell, hipMemcpyDeviceToHost, b.stream));
@@ -1181,6 +1207,58 @@ static mithra_status get_field(Batch &b, int s, int which, double *host)
         std::vector<float> tmp(ncell);
         HIP_TRY(hipMemcpy(tmp.data(), src, sizeof(float) * ncell, hipMemcpyDeviceToHost));
         for (long long i = 0; i < ncell; ++i) host[i] = tmp[i];
+    }
+    return MITHRA_OK;
+}
+
+// get_field without any allocation, host or device: E and B are computed, and
+// float fields widened, in the library's static scratch a chunk of whole
+// z-planes at a time, each chunk copied to its place in the caller's array
+static mithra_status get_field_noalloc(Batch &b, int s, int which, double *host)
+{
+    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
+    if (!host) return fail(MITHRA_EINVAL, "host is NULL");
+    mithra_status st = sync_stream(b);
+    if (st) return st;
+    const SimDev &S = b.sd[s];
+    const long long plane = (long long)S.n[0] * S.n[1];
+    const long long ncell = plane * S.n[2];
+    if (plane > NOALLOC_CELLS)
+        return fail(MITHRA_EINVAL,
+                    "a z-plane of %lld points exceeds the %lld points of the allocation-free "
+                    "read-back's scratch", plane, NOALLOC_CELLS);
+    double *scr = (double *)g_scratch_ptr[b.device];
+    if (!scr) return fail(MITHRA_ESTATE, "no read-back scratch on device %d", b.device);
+    const bool eb = which >= MITHRA_EX && which <= MITHRA_BZ;
+    void *src = nullptr;
+    if (!eb) {
+        bool ok;
+        src = mesh_ptr(b, s, which, &ok);
+        if (!ok) return fail(MITHRA_EINVAL, "unknown field %d", which);
+        if (b.rs == 8) {
+            HIP_TRY(hipMemcpyAsync(host, src, sizeof(double) * ncell, hipMemcpyDeviceToHost,
+                                   b.stream));
+            HIP_TRY(hipStreamSynchronize(b.stream));
+            return MITHRA_OK;
+        }
+    }
+    const long long per = (NOALLOC_CELLS / plane) * plane;
+    for (long long g0 = 0; g0 < ncell; g0 += per) {
+        const long long count = std::min(per, ncell - g0);
+        const double *from = scr;
+        if (eb) {
+            if (b.prec == MITHRA_F64)
+                launch_vertex_fields<double>(b.stream, b.d_sims, s, g0, count, b.ar, scr);
+            else
+                launch_vertex_fields<float>(b.stream, b.d_sims, s, g0, count, b.ar, scr);
+            from = scr + (size_t)(which - MITHRA_EX) * count;
+        } else {
+            launch_to_double(b.stream, (const float *)src + g0, count, scr);
+        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(host + g0, from, sizeof(double) * count, hipMemcpyDeviceToHost,
+                               b.stream));
+        HIP_TRY(hipStreamSynchronize(b.stream));
     }
     return MITHRA_OK;
 }
@@ -1944,6 +2022,12 @@ mithra_status mithra_get_field(mithra_sim *sim, mithra_field which, double *host
 {
     if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
     return get_field(*sim->b, 0, which, host);
+}
+
+mithra_status mithra_get_field_noalloc(mithra_sim *sim, mithra_field which, double *host)
+{
+    if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
+    return get_field_noalloc(*sim->b, 0, which, host);
 }
 
 mithra_status mithra_set_field(mithra_sim *sim, mithra_field which, const double *host)

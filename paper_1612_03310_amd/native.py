@@ -39,7 +39,7 @@ ABI_FUNCTIONS = (
     "mithra_set_optical_undulator", "mithra_batch_set_optical_undulator",
     "mithra_set_optical_beam", "mithra_batch_set_optical_beam",
     "mithra_set_seed_beam", "mithra_batch_set_seed_beam", "mithra_set_background",
-    "mithra_get_bins",
+    "mithra_get_bins", "mithra_get_field_noalloc",
 )
 
 SIGNALS = {"neumann": 0, "gaussian": 1, "secant": 2, "flat-top": 3}
@@ -174,6 +174,7 @@ def load_library(path: str = LIB_PATH):
         "mithra_run": [P, I64],
         "mithra_sync": [P],
         "mithra_get_field": [P, I32, dp],
+        "mithra_get_field_noalloc": [P, I32, dp],
         "mithra_set_field": [P, I32, dp],
         "mithra_get_particles": [P, dp, dp, ctypes.POINTER(ctypes.c_uint8),
                                  ctypes.POINTER(ctypes.c_int64)],
@@ -407,6 +408,16 @@ class Sim:
     def get_field(self, name: str) -> np.ndarray:
         out = np.empty(self.ncell, dtype=np.float64)
         _check(self._lib.mithra_get_field(self._h, FIELDS[name], _dptr(out)))
+        return out.reshape(self.n[2], self.n[1], self.n[0])
+
+    def get_field_noalloc(self, name: str, out=None) -> np.ndarray:
+        """mithra_get_field_noalloc: the library allocates nothing; out, if
+        given, is a float64 array of the mesh's size the field is written to."""
+        if out is None:
+            out = np.empty(self.ncell, dtype=np.float64)
+        if out.dtype != np.float64 or out.size != self.ncell or not out.flags.c_contiguous:
+            raise ValueError("out must be a contiguous float64 array of %d values" % self.ncell)
+        _check(self._lib.mithra_get_field_noalloc(self._h, FIELDS[name], _dptr(out)))
         return out.reshape(self.n[2], self.n[1], self.n[0])
 
     def set_field(self, name: str, arr):
