@@ -41,12 +41,15 @@ __device__ __forceinline__ int tile_deal(int b, int nb, int chunk)
 }
 
 // index along an axis, wrapped on a periodic axis, clamped otherwise (clamped
-// values are only ever read by points that do not use them)
+// values are only ever read by points that do not use them).  The wrap is a
+// full modulo: a stencil block wider than a periodic axis stages halo columns
+// more than one period away, and every one of them must stay in the mesh.
 __device__ __forceinline__ int axis_index(int v, int n, int periodic)
 {
-    if (v < 0) return periodic ? v + n : 0;
-    if (v >= n) return periodic ? v - n : n - 1;
-    return v;
+    if (v >= 0 && v < n) return v;
+    if (!periodic) return v < 0 ? 0 : n - 1;
+    const int r = v % n;
+    return r < 0 ? r + n : r;
 }
 
 __device__ __forceinline__ void sin_cos(float x, float *s, float *c) { sincosf(x, s, c); }
