@@ -397,5 +397,6 @@ def from_workload(w, parallel=False):
     s = OracleSim(w.n, w.d, w.origin, w.courant, w.nsfd_A, w.substeps, w.space_charge,
                   w.bc, w.lambda_u, w.K, w.gamma_beam, w.z_e, parallel=parallel)
     s.config_diag(w.probe, w.kp)
+    s.set_undulator_length(getattr(w, "und_length", 0.0))
     s.set_particles(w.x, w.u, w.q, w.m)
     return s

@@ -68,6 +68,7 @@ class Workload:
     probe: Tuple[int, int, int]
     kp: int
     steps: int
+    und_length: float = 0.0  # lab length of the undulator [m], whole periods; 0: unbounded
 
     @property
     def ncell(self) -> int:

@@ -98,11 +98,16 @@ def compare_diag(gd, od, tol, what=""):
     errs["bunching"] = rel_l2(gd["bunching"], od[:, 16:19])
     errs["power_harmonic"] = rel_l2(gd["power_harmonic"], od[:, 20:23])
     errs["power_extra"] = rel_l2(gd["power_extra"], od[:, 24:27])
+    # continuity: the residual equals the oracle's on every row (on a step
+    # that loses particles their charge leaves rho without a current), and
+    # holds to round-off of the fixed-point deposit on the other rows
+    errs["continuity_residual"] = rel_l2(gd["continuity_residual"], od[:, 3]) if np.any(
+        od[:, 3] > 1e-9) else 0.0
     bad = {k: v for k, v in errs.items() if not v <= tol}
     say(what, "diag", errs)
     assert not bad, (what, bad)
-    # continuity holds to round-off of the fixed-point deposit on both sides
-    assert np.max(gd["continuity_residual"]) < 1e-11
+    steady = np.concatenate([[gd["lost"][0] == 0], np.diff(gd["lost"]) == 0])
+    assert np.max(gd["continuity_residual"][steady]) < 1e-11
 
 
 def run_pair(w, steps, precision="f64", every=1):
@@ -1422,7 +1427,7 @@ def test_plain_c_caller_equals_the_binding_bitwise(tmp_path):
     w = W.config(0, steps=40)
     head = (list(w.n) + list(w.d) + list(w.origin) + [w.courant, w.nsfd_A, w.substeps,
             w.space_charge] + list(w.bc) + [w.lambda_u, w.K, w.gamma_beam, w.z_e, w.q, w.m,
-            w.np, 40] + list(w.probe) + [w.kp, 0.0, 0.0])
+            w.np, 40] + list(w.probe) + [w.kp, w.und_length, 0.0])
     inp = tmp_path / "in.bin"
     with open(inp, "wb") as f:
         np.asarray(head, dtype=np.float64).tofile(f)
