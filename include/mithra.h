@@ -153,6 +153,11 @@ typedef struct {
     double gamma_beam;  /* lab mean Lorentz factor; gamma0 = gamma / sqrt(1 + K^2/2) > 1 */
     double z_entrance;  /* rest-frame z of the lab entrance z' = 0 at t = 0 [m];
                            z' = gamma0 (z - z_entrance + beta0 c t) */
+    double length;      /* total lab length L [m] (section "UNDULATOR", length), a whole
+                           number of periods (else EINVAL); past the exit z' = L the field
+                           is the entrance fringe mirrored about L, so a particle that
+                           crosses the whole undulator keeps no transverse kick.
+                           <= 0: unbounded */
 } mithra_undulator;
 
 typedef struct {
@@ -187,14 +192,26 @@ typedef struct {
                                    K = 2 gamma0 k_u the ponderomotive wave number in
                                    this frame (section "Bunching factor")  (mesh term) */
     double power_harmonic[3];   /* (with power_spectrum on) mean power [W] carried through
-                                   plane k at h omega_1,
-                                   h = 1, 2, 3, omega_1 = gamma0 beta0 c k_u the rest-frame
-                                   resonant frequency, since the state was committed:
-                                   (2/T^2) sum Re(F_Ex F_By* - F_Ey F_Bx*)/mu0 dx dy with
-                                   F(omega) = sum_n f(t_n) exp(-i omega t_n) dt the running
-                                   DFT of the plane's vertex fields and T = (s+1) dt */
+                                   plane k at the first three normalized frequencies of
+                                   mithra_set_spectrum (default nu omega_1 for nu = 1, 2, 3,
+                                   omega_1 = gamma0 beta0 c k_u the rest-frame resonant
+                                   frequency), since the spectrum started (the last
+                                   particle load): (2/T^2) sum Re(F_Ex F_By* - F_Ey F_Bx*)/mu0
+                                   dx dy with F(omega) = sum_n f(t_n) exp(-i omega t_n) dt the
+                                   running DFT of the plane's vertex fields and T = (number of
+                                   samples) dt; 0 beyond the number of frequencies */
     double power_extra[3];      /* radiated power [W] through the further plates of
                                    mithra_diag_cfg.extra_planes, as power; 0 where none */
+    double power_lab;           /* FEL output in the lab (section "FEL-OUTPUT"): the flux of
+                                   the lab Poynting vector of the self field through plane k,
+                                   the plane's fields seen in the lab (frame moving along +z at
+                                   beta0 c): E_x' = g (E_x + b c B_y), E_y' = g (E_y - b c B_x),
+                                   B_x' = g (B_x - b E_y / c), B_y' = g (B_y + b E_x / c),
+                                   g = gamma0, b = beta0; (E_x' B_y' - E_y' B_x')/mu0 dx dy [W].
+                                   A forward plane wave gives gamma0^2 (1 + beta0)^2 power */
+    double z_undulator;         /* the lab undulator position of plane k at this row's time,
+                                   z' = gamma0 (z_k - z_entrance + beta0 c t) [m]: the abscissa
+                                   of the FEL output (power against undulator position) */
 } mithra_diag_row;
 
 /* Derived constants and bookkeeping of a simulation. */
@@ -250,6 +267,28 @@ mithra_status mithra_set_particles(mithra_sim *sim, int64_t np, const double *po
 mithra_status mithra_set_background(mithra_sim *sim, const double *rho_bg);
 
 mithra_status mithra_config_diag(mithra_sim *sim, const mithra_diag_cfg *cfg);
+
+/* Normalized frequencies of the power spectrum (section "FEL-OUTPUT":
+   normalized-frequency, repeated, or the sweep from minimum- to
+   maximum-normalized-frequency at normalized-frequency-resolution, which the
+   caller lists): nu_f = omega_f / omega_1, omega_1 = gamma0 beta0 c k_u the
+   rest-frame resonant frequency (a wave along z has the same normalized
+   frequency in the lab).  At most MITHRA_MAX_FREQ, each positive; the
+   default is 1, 2, 3.  power_harmonic of the rows holds the first three.
+   ESTATE after the first step. */
+#define MITHRA_MAX_FREQ 32
+mithra_status mithra_set_spectrum(mithra_sim *sim, const double *nu, int32_t nfreq);
+
+/* The mean power at each normalized frequency for rows first_step ..
+   first_step+count-1 (still in the ring of mithra_diag_cfg.capacity rows):
+   rest[r * nfreq + f] in the bunch frame, (2/T^2) sum Re(F_Ex F_By* - F_Ey F_Bx*)
+   / mu0 dx dy with the running DFT F of the plane's vertex fields since the
+   spectrum started (T its length: from the last particle load or the
+   checkpoint's own start), and lab[r * nfreq + f] the same from the DFT of the
+   fields seen in the lab (see power_lab).  ESTATE with power_spectrum off;
+   EINVAL for rows outside the ring. */
+mithra_status mithra_get_spectrum(mithra_sim *sim, int64_t first_step, int64_t count, double *rest,
+                                  double *lab);
 
 /* Set (or, with amplitude 0 or seed == NULL, clear) the seed plane wave of
    the simulation; it acts from the next step.  EINVAL for non-finite
@@ -402,6 +441,10 @@ mithra_status mithra_batch_set_particles(mithra_batch *b, int32_t sim, int64_t n
                                          const double *pos, const double *u, double q_macro,
                                          double m_macro);
 mithra_status mithra_batch_config_diag(mithra_batch *b, int32_t sim, const mithra_diag_cfg *cfg);
+mithra_status mithra_batch_set_spectrum(mithra_batch *b, int32_t sim, const double *nu,
+                                        int32_t nfreq);
+mithra_status mithra_batch_get_spectrum(mithra_batch *b, int32_t sim, int64_t first_step,
+                                        int64_t count, double *rest, double *lab);
 mithra_status mithra_batch_set_seed(mithra_batch *b, int32_t sim, const mithra_seed *seed);
 mithra_status mithra_batch_set_optical_undulator(mithra_batch *b, int32_t sim,
                                                  const mithra_seed *wave);

@@ -843,7 +843,15 @@ __device__ __forceinline__ void undulator_kick(const SimDev &S, double ph_cell, 
     const double full = ph_cell + kzc * (double)fz;
     const R kuy = (R)(S.ku * y);
     const R ch = cosh(kuy), sh = sinh(kuy);
-    if (full >= 0.0) {
+    if (S.und_kL > 0.0 && full > S.und_kL) {
+        // past the exit of a finite undulator: the entrance fringe mirrored
+        // about z' = L
+        const R s = (R)((ph_cell - S.und_kL) + kzc * (double)fz);
+        const R g = exp(-s * s * (R)0.5);
+        Ex = (R)S.EuK * ch * s * g;
+        By = (R)S.BuyK * ch * s * g;
+        Bz = (R)S.BuzK * sh * g;
+    } else if (full >= 0.0) {
         const double twopi = 6.283185307179586476925286766559;
         const double red = ph_cell - twopi * floor(ph_cell / twopi);
         const R ph = (R)red + (R)kzc * fz;
@@ -1795,14 +1803,27 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(Arena ar, long long np)
 //    to finish advances the step counter.
 // ---------------------------------------------------------------------------
 
+// f = (E_x, E_y, B_x, B_y) of the bunch frame seen in the lab, where the frame
+// moves along +z at beta0 c (section "Lorentz Transformation"); with
+// G = gamma0 and GB = gamma0 beta0: E_x = G E_x + GB c B_y,
+// E_y = G E_y - GB c B_x, B_x = G B_x - GB E_y / c, B_y = G B_y + GB E_x / c.
+__device__ __forceinline__ void to_lab(const SimDev &S, const double f[4], double l[4])
+{
+    l[0] = S.lab_g * f[0] + S.lab_gb * C_LIGHT_D * f[3];
+    l[1] = S.lab_g * f[1] - S.lab_gb * C_LIGHT_D * f[2];
+    l[2] = S.lab_g * f[2] - S.lab_gb * f[1] / C_LIGHT_D;
+    l[3] = S.lab_g * f[3] + S.lab_gb * f[0] / C_LIGHT_D;
+}
+
 template <typename R>
 __device__ __forceinline__ void diag_plane(const SimDev *__restrict__ sims, int2 it, Arena &ar)
 {
-    // Per block of plane points: the Poynting flux, and the running DFT of
-    // Ex, Ey, Bx, By at h omega_1 (h = 1, 2, 3) advanced by this step's sample
-    // at t = (s + 1/2) dt, with each point's Re(F_Ex F_By* - F_Ey F_Bx*).
-    // item y = plate * nb_plane + block; plate 0 is the main plane (power and
-    // spectrum), plates 1.. the further ones (power only)
+    // Per block of plane points: the Poynting flux in the bunch frame and in
+    // the lab, and the running DFT of Ex, Ey, Bx, By at nu_f omega_1 advanced
+    // by this step's sample at t = (s + 1/2) dt, with each point's
+    // Re(F_Ex F_By* - F_Ey F_Bx*) in both frames.
+    // item y = plate * nb_plane + block; plate 0 is the main plane (power, lab
+    // power and spectrum), plates 1.. the further ones (power only)
     const SimDev &S = sims[it.x];
     const long long step = *ar.d_step;
     const FieldPtrs<R> f = field_ptrs<R>(S, ar, step % 3, (step + 1) % 3, (int)(step % 3));
@@ -1810,57 +1831,75 @@ __device__ __forceinline__ void diag_plane(const SimDev *__restrict__ sims, int2
     const int kz = plate == 0 ? S.kp : S.kp_extra[plate - 1];
     const int e = blk * BLOCK + threadIdx.x;
     const long long npl = (long long)S.n[0] * S.n[1];
-    double t[PLANE_TERMS] = {0.0, 0.0, 0.0, 0.0};
+    double p0 = 0.0, pl = 0.0, fv[4] = {0.0, 0.0, 0.0, 0.0};
+    bool valid = false;
     if (e < npl) {
         const int i = e % S.n[0], j = e / S.n[0];
         if (vertex_valid(S, i, j, kz)) {
             R E[3], B[3];
             vertex_EB<R>(S, f, i, j, kz, E, B);
-            t[0] = (double)E[0] * (double)B[1] - (double)E[1] * (double)B[0];
-            const double fv[4] = {(double)E[0], (double)E[1], (double)B[0], (double)B[1]};
-            const double tm = ((double)step + 0.5) * S.dt;
-            if (S.spec_on && plate == 0) {
-                // the sums are stored sum-major (sum q of point e at q * npl + e),
-                // so each access is one contiguous span per wavefront; one
-                // harmonic (8 sums) at a time keeps the register count of the
-                // launch, which all roles share, low
-                double *acc = ar.spec + S.spec0 + e;
-                // harmonics 2 and 3 of the phase by angle addition from the first
-                double s1, c1;
-                sincos(S.omega1 * tm, &s1, &c1);
-                double sn = 0.0, cs = 1.0;
-                for (int h = 1; h <= 3; ++h) {
-                    const double sn_next = sn * c1 + cs * s1;
-                    cs = cs * c1 - sn * s1;
-                    sn = sn_next;
-                    double *ah = acc + (long long)(h - 1) * 8 * npl;
-                    double a[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) a[q] = ah[q * npl];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        a[2 * c] = a[2 * c] + fv[c] * cs * S.dt;
-                        a[2 * c + 1] = a[2 * c + 1] - fv[c] * sn * S.dt;
-                    }
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) ah[q * npl] = a[q];
-                    // (re, im) pairs: Ex a[0..1], Ey a[2..3], Bx a[4..5], By a[6..7]
-                    t[h] = (a[0] * a[6] + a[1] * a[7]) - (a[2] * a[4] + a[3] * a[5]);
-                }
-            }
+            fv[0] = (double)E[0];
+            fv[1] = (double)E[1];
+            fv[2] = (double)B[0];
+            fv[3] = (double)B[1];
+            p0 = fv[0] * fv[3] - fv[1] * fv[2];
+            double l[4];
+            to_lab(S, fv, l);
+            pl = l[0] * l[3] - l[1] * l[2];
+            valid = true;
         }
     }
     __shared__ double sh[BLOCK];
     if (plate > 0) {
-        const double tot = block_sum(t[0], sh);
+        const double tot = block_sum(p0, sh);
         if (threadIdx.x == 0)
             ar.partial[S.part_extra0 + (long long)(plate - 1) * S.nb_plane + blk] = tot;
         return;
     }
-    const int nterms = S.spec_on ? PLANE_TERMS : 1;  // uniform over the block
-    for (int q = 0; q < nterms; ++q) {
-        const double tot = block_sum(t[q], sh);
-        if (threadIdx.x == 0) ar.partial[S.part_plane0 + (long long)PLANE_TERMS * blk + q] = tot;
+    double *o = ar.partial + S.part_plane0 + (long long)PLANE_STRIDE * blk;
+    {
+        const double t0 = block_sum(p0, sh);
+        const double t1 = block_sum(pl, sh);
+        if (threadIdx.x == 0) {
+            o[0] = t0;
+            o[1] = t1;
+        }
+    }
+    if (!S.spec_on) return;  // uniform over the block
+    // the sums are stored sum-major (sum q of point e at q * npl + e), so each
+    // access is one contiguous span per wavefront; one frequency (8 sums) at
+    // a time keeps the register count of the launch, which all roles share, low
+    const double tm = ((double)step + 0.5) * S.dt;
+    for (int fq = 0; fq < S.nfreq; ++fq) {  // uniform over the block
+        double tr = 0.0, tl = 0.0;
+        if (valid) {
+            double sn, cs;
+            sincos(S.fnu[fq] * S.omega1 * tm, &sn, &cs);
+            double *af = ar.spec + S.spec0 + e + (long long)fq * SPEC_PER_FREQ * npl;
+            double a[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[q] = af[q * npl];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                a[2 * c] = a[2 * c] + fv[c] * cs * S.dt;
+                a[2 * c + 1] = a[2 * c + 1] - fv[c] * sn * S.dt;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) af[q * npl] = a[q];
+            // (re, im) pairs: Ex a[0..1], Ey a[2..3], Bx a[4..5], By a[6..7]
+            tr = (a[0] * a[6] + a[1] * a[7]) - (a[2] * a[4] + a[3] * a[5]);
+            const double re[4] = {a[0], a[2], a[4], a[6]}, im[4] = {a[1], a[3], a[5], a[7]};
+            double lr[4], li[4];
+            to_lab(S, re, lr);
+            to_lab(S, im, li);
+            tl = (lr[0] * lr[3] + li[0] * li[3]) - (lr[1] * lr[2] + li[1] * li[2]);
+        }
+        const double sr = block_sum(tr, sh);
+        const double sl = block_sum(tl, sh);
+        if (threadIdx.x == 0) {
+            o[2 + 2 * fq] = sr;
+            o[3 + 2 * fq] = sl;
+        }
     }
 }
 
@@ -1973,14 +2012,14 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
     const long long step = *ar.d_step;
     const bool mesh = S.mesh_every > 0 && ((step + 1) % S.mesh_every) == 0;
     __shared__ double sh[BLOCK];
-    double pt[PLANE_TERMS] = {0.0, 0.0, 0.0, 0.0};
+    double pt[2] = {0.0, 0.0};
     for (int b = threadIdx.x; b < S.nb_plane; b += BLOCK) {
-        const double *o = ar.partial + S.part_plane0 + (long long)PLANE_TERMS * b;
-#pragma unroll
-        for (int q = 0; q < PLANE_TERMS; ++q) pt[q] += o[q];
+        const double *o = ar.partial + S.part_plane0 + (long long)PLANE_STRIDE * b;
+        pt[0] += o[0];
+        pt[1] += o[1];
     }
-#pragma unroll
-    for (int q = 0; q < PLANE_TERMS; ++q) pt[q] = block_sum(pt[q], sh);
+    pt[0] = block_sum(pt[0], sh);
+    pt[1] = block_sum(pt[1], sh);
     const double pw = pt[0];
     double px[3] = {0.0, 0.0, 0.0};
     for (int p = 0; p < S.n_extra; ++p) {  // uniform over the block
@@ -2045,11 +2084,36 @@ __global__ __launch_bounds__(BLOCK) void k_diag_final(const SimDev *__restrict__
                               ? sqrt(kt[2 + 2 * h] * kt[2 + 2 * h] + kt[3 + 2 * h] * kt[3 + 2 * h]) / live
                               : 0.0;
         row[19] = 0.0;
-        const double T = ((double)step + 1.0) * S.dt;
-        for (int h = 0; h < 3; ++h)
-            row[20 + h] = S.spec_on ? 2.0 / (T * T) * pt[1 + h] * S.dxdy_mu0 : 0.0;
+        for (int h = 0; h < 3; ++h) row[20 + h] = 0.0;  // the spectrum's first three, below
         row[23] = 0.0;
         for (int p = 0; p < 3; ++p) row[24 + p] = p < S.n_extra ? px[p] * S.dxdy_mu0 : 0.0;
+        row[27] = pt[1] * S.dxdy_mu0;
+        row[28] = S.zu0 + S.zu_rate * row[1];
+    }
+    if (S.spec_on) {
+        // mean power at each frequency since the spectrum started, T = (number
+        // of samples) dt, in the bunch frame and in the lab
+        const double T = ((double)(step + 1 - S.step0)) * S.dt;
+        const double k = T > 0.0 ? 2.0 / (T * T) * S.dxdy_mu0 : 0.0;
+        double *sr = ar.srow + S.srow0 + (step % S.ring_cap) * 2 * S.nfreq;
+        double *row = ar.ring + (S.ring0 + step % S.ring_cap) * NDIAG;
+        for (int fq = 0; fq < S.nfreq; ++fq) {  // uniform over the block
+            double vr = 0.0, vl = 0.0;
+            for (int b = threadIdx.x; b < S.nb_plane; b += BLOCK) {
+                const double *o = ar.partial + S.part_plane0 + (long long)PLANE_STRIDE * b;
+                vr += o[2 + 2 * fq];
+                vl += o[3 + 2 * fq];
+            }
+            vr = block_sum(vr, sh);
+            vl = block_sum(vl, sh);
+            if (threadIdx.x == 0) {
+                sr[fq] = k * vr;
+                sr[S.nfreq + fq] = k * vl;
+                if (fq < 3) row[20 + fq] = k * vr;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
         // every block has read the step counter before it counts itself done
         if (atomicAdd(ar.fin_ctr, 1) == (int)gridDim.x - 1) {
             *ar.fin_ctr = 0;

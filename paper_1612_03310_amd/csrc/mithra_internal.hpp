@@ -15,14 +15,16 @@ constexpr int TILE = 8;
 constexpr int TILE_CELLS = TILE * TILE * TILE;
 constexpr int TILE_VERT = TILE + 1;  // vertices per axis a tile's cells touch
 constexpr int NKINDS = 7;            // kernel kinds for timing
-constexpr int NDIAG = 27;            // doubles per diagnostic row
+constexpr int NDIAG = 29;            // doubles per diagnostic row
 constexpr int BLOCK = 256;
 constexpr int SCAN_PER_THREAD = 16;
 constexpr int SCAN_CHUNK = BLOCK * SCAN_PER_THREAD;
 constexpr int MESH_DIAG_PER_THREAD = 8;
 constexpr int KIN_PER_THREAD = 8;
-constexpr int SPEC_PER_POINT = 24;  // per power-plane point: 3 harmonics x (Ex, Ey, Bx, By) x (re, im)
-constexpr int PLANE_TERMS = 4;      // per plane block: power and the 3 harmonic terms
+constexpr int MAXF = 32;            // normalized frequencies of the plane spectrum
+constexpr int SPEC_PER_FREQ = 8;    // per power-plane point and frequency: (Ex, Ey, Bx, By) x (re, im)
+constexpr int PLANE_STRIDE = 2 + 2 * MAXF;  // per plane block: power, lab power, and per
+                                             // frequency the bunch-frame and lab terms
 constexpr int KIN_TERMS = 8;         // per kinetic block: sum (gamma - 1), live count,
                                      // cos and sin sums of h K z for h = 1, 2, 3
 constexpr int OKEY_LOST = 1 << 9;
@@ -79,6 +81,15 @@ struct SimDev {
     double omega1;      // gamma0 beta0 c k_u: rest-frame resonant frequency
     long long spec0;    // first double of this simulation in the plane-spectrum arena
     int spec_on;        // the plane spectrum is sampled
+    int nfreq;          // normalized frequencies of the spectrum, fnu[f] = omega_f / omega1
+    double fnu[MAXF];
+    long long step0;    // step at which the spectrum (re)started
+    long long srow0;    // first double of this simulation in the spectrum-row arena
+    // FEL output in the lab: fields of the bunch frame seen in the lab
+    // (gamma0, gamma0 beta0), and the power plane's lab undulator position
+    // z' = zu0 + zu_rate t
+    double lab_g, lab_gb, zu0, zu_rate;
+    double und_kL;      // k_u L of a finite undulator (exit at z' = L), 0: unbounded
     // seed plane wave along +z (TF/SF planes k = 2 and 3)
     int seed_on, seed_sig;
     double seed_a0, seed_p[2], seed_f, seed_t0, seed_tau, seed_cep, seed_zref;
@@ -120,8 +131,11 @@ struct Arena {
     double *ke;         // (gamma - 1) by particle id, for the kinetic-energy sum
     double *zr;         // rest-frame z by particle id (NaN once lost), for the bunching factor
     double *partial;    // diagnostic partial sums
-    double *spec;       // running DFT of the power-plane fields at the harmonics, per simulation
-                        // sum-major: sum q of plane point e at spec0 + q * nx * ny + e (reset at commit)
+    double *spec;       // running DFT of the power-plane fields at the frequencies, per simulation
+                        // sum-major: sum q = 8 f + c of plane point e at spec0 + q * nx * ny + e
+                        // (reset at commit)
+    double *srow;       // per diagnostic row: the mean power at each frequency, bunch frame
+                        // then lab (2 nfreq doubles at srow0 + (step % ring_cap) * 2 nfreq)
     double *ring;       // diagnostic rows
     int *flags;         // per simulation: a non-finite value was produced
     int *tact;          // per tile: a particle in the 27-tile neighbourhood at the start of

@@ -82,6 +82,10 @@ struct HostSim {
     std::vector<double> mom;  // 3 per particle
     std::vector<unsigned char> alive;
     long long read_step = 0;
+    // normalized frequencies of the plane spectrum and the step it (re)started
+    int nfreq = 3;
+    double fnu[MAXF] = {1.0, 2.0, 3.0};
+    long long step0 = 0;
 };
 
 struct Batch {
@@ -143,7 +147,7 @@ struct Batch {
         void *p;
         size_t bytes;
     };
-    std::vector<Block> mem_fixed, mem_part, mem_tab, mem_ring;
+    std::vector<Block> mem_fixed, mem_part, mem_tab, mem_ring, mem_spec;
     size_t bytes = 0;
 };
 
@@ -211,6 +215,7 @@ static void destroy_batch(Batch *b)
     dev_free_all(*b, b->mem_tab);
     dev_free_all(*b, b->mem_part);
     dev_free_all(*b, b->mem_ring);
+    dev_free_all(*b, b->mem_spec);
     dev_free_all(*b, b->mem_fixed);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -257,6 +262,15 @@ static mithra_status validate(int s, const mithra_mesh &m, const mithra_undulato
         return fail(MITHRA_EINVAL, "sim %d: gamma_beam and z_entrance must be finite", s);
     if (!(u.gamma_beam / std::sqrt(1.0 + u.K * u.K / 2.0) > 1.0))
         return fail(MITHRA_EINVAL, "sim %d: gamma_beam / sqrt(1 + K^2/2) must exceed 1", s);
+    if (!std::isfinite(u.length)) return fail(MITHRA_EINVAL, "sim %d: length must be finite", s);
+    if (u.length > 0.0) {
+        const double periods = u.length / u.lambda_u;
+        if (std::fabs(periods - std::round(periods)) > 1e-9 * std::max(1.0, periods) ||
+            std::round(periods) < 1.0)
+            return fail(MITHRA_EINVAL,
+                        "sim %d: length = %g m must be a whole number (>= 1) of periods of %g m",
+                        s, u.length, u.lambda_u);
+    }
     // stability: the right-hand side of the NSFD dispersion relation,
     // (c dt)^2 [(1 - 4 A sz)(sx/dx^2 + sy/dy^2) + sz/dz^2] with sx, sy, sz the
     // sin^2 terms in [0, 1], is multilinear, so its largest value sits at a
@@ -351,6 +365,13 @@ static void fill_optical(const HostSim &h, SimDev &S)
 }
 
 // fill the per-simulation constants (offsets are set by the layout)
+// lab undulator position of the power plane at t = 0: z' = gamma0 (z_k - z_e),
+// advancing at gamma0 beta0 c (z' = gamma0 (z - z_e + beta0 c t))
+static double plate_position(const HostSim &h)
+{
+    return h.gamma0 * (h.mesh.origin[2] + h.diag.power_plane_k * h.mesh.d[2] - h.und.z_entrance);
+}
+
 static void fill_simdev(const HostSim &h, SimDev &S)
 {
     const mithra_mesh &m = h.mesh;
@@ -420,6 +441,14 @@ static void fill_simdev(const HostSim &h, SimDev &S)
     S.inv_2mu0 = 0.5 / MU0;
     S.kbunch = 2.0 * h.gamma0 * h.ku;
     S.omega1 = h.gamma0 * h.beta0 * C_LIGHT * h.ku;
+    S.nfreq = h.nfreq;
+    for (int f = 0; f < MAXF; ++f) S.fnu[f] = f < h.nfreq ? h.fnu[f] : 0.0;
+    S.step0 = h.step0;
+    S.lab_g = h.gamma0;
+    S.lab_gb = h.gamma0 * h.beta0;
+    S.zu0 = plate_position(h);
+    S.zu_rate = h.gamma0 * h.beta0 * C_LIGHT;
+    S.und_kL = h.und.length > 0.0 ? h.ku * h.und.length : 0.0;
     S.probe[0] = h.diag.probe[0];
     S.probe[1] = h.diag.probe[1];
     S.probe[2] = h.diag.probe[2];
@@ -605,7 +634,7 @@ static mithra_status build_tables(Batch &b)
         S.nb_kin = S.mesh_every > 0 ? (int)((S.np + BLOCK * KIN_PER_THREAD - 1) / (BLOCK * KIN_PER_THREAD))
                                     : 0;
         S.part_plane0 = slot;
-        slot += PLANE_TERMS * S.nb_plane;
+        slot += PLANE_STRIDE * S.nb_plane;
         S.part_extra0 = slot;
         slot += S.n_extra * S.nb_plane;
         S.part_mesh0 = slot;
@@ -655,6 +684,64 @@ static mithra_status build_tables(Batch &b)
 // ---------------------------------------------------------------------------
 // creation
 // ---------------------------------------------------------------------------
+
+// Lay out the diagnostic ring, the per-row spectrum arena and (spec) the
+// plane-spectrum arena from each simulation's ring capacity and number of
+// frequencies; the old arenas are freed once the new ones are in place.
+// Only before the first step: no rows exist yet and the spectrum is zero.
+static mithra_status relay_diag_arenas(Batch &b, bool spec)
+{
+    long long ring = 0, srow = 0, plate = 0;
+    for (int i = 0; i < b.nsim; ++i) {
+        const HostSim &h = b.hs[i];
+        ring += h.diag.capacity;
+        srow += (long long)h.diag.capacity * 2 * h.nfreq;
+        plate += (long long)h.mesh.n[0] * h.mesh.n[1] * SPEC_PER_FREQ * h.nfreq;
+    }
+    std::vector<Batch::Block> fr, fs;
+    double *nr = (double *)dev_alloc(b, sizeof(double) * NDIAG * ring, fr);
+    double *nsr = nr ? (double *)dev_alloc(b, sizeof(double) * srow, fr) : nullptr;
+    double *nsp = nullptr;
+    if (nsr && spec) nsp = (double *)dev_alloc(b, sizeof(double) * plate, fs);
+    hipError_t e = hipSuccess;
+    if (nsr && (!spec || nsp)) {
+        e = hipMemset(nr, 0, sizeof(double) * NDIAG * ring);
+        if (e == hipSuccess) e = hipMemset(nsr, 0, sizeof(double) * srow);
+        if (e == hipSuccess && spec) e = hipMemset(nsp, 0, sizeof(double) * plate);
+    }
+    if (!nsr || (spec && !nsp) || e != hipSuccess) {
+        dev_free_all(b, fr);
+        dev_free_all(b, fs);
+        return e != hipSuccess ? fail(MITHRA_EDEVICE, "clearing the diagnostic arenas failed")
+                               : fail(MITHRA_ENOMEM, "device allocation of the diagnostic arenas failed");
+    }
+    drop_graph(b);
+    dev_free_all(b, b.mem_ring);
+    b.mem_ring = fr;
+    b.ar.ring = nr;
+    b.ar.srow = nsr;
+    if (spec) {
+        dev_free_all(b, b.mem_spec);
+        b.mem_spec = fs;
+        b.ar.spec = nsp;
+        b.total_spec = plate;
+    }
+    ring = srow = plate = 0;
+    for (int i = 0; i < b.nsim; ++i) {
+        const HostSim &h = b.hs[i];
+        SimDev &S = b.sd[i];
+        S.ring0 = ring;
+        S.ring_cap = h.diag.capacity;
+        S.srow0 = srow;
+        ring += h.diag.capacity;
+        srow += (long long)h.diag.capacity * 2 * h.nfreq;
+        if (spec) {
+            S.spec0 = plate;
+            plate += (long long)h.mesh.n[0] * h.mesh.n[1] * SPEC_PER_FREQ * h.nfreq;
+        }
+    }
+    return MITHRA_OK;
+}
 
 static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mithra_undulator *unds,
                                   mithra_precision prec, void *stream, Batch **out)
@@ -715,7 +802,7 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     }
     b->hs.resize(nsim);
     b->sd.resize(nsim);
-    long long cells = 0, keys = 0, ring = 0, plate = 0;
+    long long cells = 0, keys = 0;
     for (int s = 0; s < nsim; ++s) {
         HostSim &h = b->hs[s];
         h.mesh = meshes[s];
@@ -733,12 +820,8 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
         fill_simdev(h, S);
         S.cell0 = cells;
         S.key0 = keys;
-        S.ring0 = ring;
-        S.spec0 = plate;
-        plate += (long long)S.n[0] * S.n[1] * SPEC_PER_POINT;
         cells += (long long)S.n[0] * S.n[1] * S.n[2];
         keys += (long long)S.nkeys + 1;
-        ring += S.ring_cap;
     }
     if (keys >= (1LL << 31) - 1) {
         destroy_batch(b);
@@ -746,7 +829,6 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     }
     b->total_cells = cells;
     b->total_keys = keys;
-    b->total_spec = plate;
     // default stencil shape, clamped to the meshes
     int maxn[3] = {0, 0, 0};
     for (int s = 0; s < nsim; ++s)
@@ -766,9 +848,6 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     for (int r = 0; r < 2; ++r) ok &= (b->ar.rho[r] = A(mb)) != nullptr;
     ok &= (b->ar.counts = (int *)A(sizeof(int) * keys)) != nullptr;
     for (int r = 0; r < 2; ++r) ok &= (b->ar.offs[r] = (int *)A(sizeof(int) * (keys + 1))) != nullptr;
-    ok &= (b->ar.ring = (double *)dev_alloc(*b, sizeof(double) * NDIAG * ring, b->mem_ring)) !=
-          nullptr;
-    ok &= (b->ar.spec = (double *)A(sizeof(double) * plate)) != nullptr;
     ok &= (b->ar.flags = (int *)A(sizeof(int) * nsim)) != nullptr;
     ok &= (b->ar.d_step = (long long *)A(sizeof(long long))) != nullptr;
     ok &= (b->ar.fin_ctr = (int *)A(sizeof(int))) != nullptr;
@@ -786,8 +865,6 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.counts, 0, sizeof(int) * keys, b->stream);
     for (int r = 0; r < 2 && e == hipSuccess; ++r)
         e = hipMemsetAsync(b->ar.offs[r], 0, sizeof(int) * (keys + 1), b->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(b->ar.ring, 0, sizeof(double) * NDIAG * ring, b->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(b->ar.spec, 0, sizeof(double) * plate, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.flags, 0, sizeof(int) * nsim, b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.d_step, 0, sizeof(long long), b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->ar.fin_ctr, 0, sizeof(int), b->stream);
@@ -795,7 +872,8 @@ static mithra_status create_batch(int nsim, const mithra_mesh *meshes, const mit
         destroy_batch(b);
         return fail(MITHRA_EDEVICE, "clearing device memory failed: %s", hipGetErrorString(e));
     }
-    mithra_status st = build_tables(*b);
+    mithra_status st = relay_diag_arenas(*b, true);
+    if (!st) st = build_tables(*b);
     if (st) {
         destroy_batch(b);
         return st;
@@ -922,14 +1000,17 @@ static mithra_status commit_impl(Batch &b)
         S.np = (int)b.hs[s].alive.size();
         N += S.np;
         const long long keep0 = S.cell0, keep1 = S.key0, keep2 = S.ring0, keep3 = S.part0,
-                        keep4 = S.spec0;
+                        keep4 = S.spec0, keep5 = S.srow0;
         const int np = S.np;
+        // the plane spectrum restarts with the committed state
+        b.hs[s].step0 = b.step;
         fill_simdev(b.hs[s], S);
         S.cell0 = keep0;
         S.key0 = keep1;
         S.ring0 = keep2;
         S.part0 = keep3;
         S.spec0 = keep4;
+        S.srow0 = keep5;
         S.np = np;
     }
     b.total_particles = N;
@@ -1405,6 +1486,8 @@ static mithra_status get_diag(Batch &b, int s, mithra_diag_row *rows, int64_t ca
         for (int h = 0; h < 3; ++h) o.bunching[h] = v[16 + h];
         for (int h = 0; h < 3; ++h) o.power_harmonic[h] = v[20 + h];
         for (int e = 0; e < 3; ++e) o.power_extra[e] = v[24 + e];
+        o.power_lab = v[27];
+        o.z_undulator = v[28];
     }
     h.read_step = first + n;
     *nrows = n;
@@ -1436,26 +1519,14 @@ static mithra_status config_diag(Batch &b, int s, const mithra_diag_cfg *cfg)
                         cfg->extra_planes[e]);
     HIP_TRY(hipStreamSynchronize(b.stream));
     if (cfg->capacity != h.diag.capacity) {
-        // re-lay the ring arena (no rows exist before the first step); the
-        // new ring is in place before anything else changes
-        long long ring = 0;
-        for (int i = 0; i < b.nsim; ++i) ring += i == s ? cfg->capacity : b.hs[i].diag.capacity;
-        std::vector<Batch::Block> fresh;
-        double *nr = (double *)dev_alloc(b, sizeof(double) * NDIAG * ring, fresh);
-        if (!nr) return fail(MITHRA_ENOMEM, "device allocation of the diagnostic ring failed");
-        if (hipMemset(nr, 0, sizeof(double) * NDIAG * ring) != hipSuccess) {
-            dev_free_all(b, fresh);
-            return fail(MITHRA_EDEVICE, "clearing the diagnostic ring failed");
-        }
-        drop_graph(b);
-        dev_free_all(b, b.mem_ring);
-        b.mem_ring = fresh;
-        b.ar.ring = nr;
-        ring = 0;
-        for (int i = 0; i < b.nsim; ++i) {
-            b.sd[i].ring0 = ring;
-            b.sd[i].ring_cap = i == s ? cfg->capacity : b.hs[i].diag.capacity;
-            ring += b.sd[i].ring_cap;
+        // re-lay the rings (no rows exist before the first step); the new
+        // rings are in place before anything else changes
+        const int old = h.diag.capacity;
+        h.diag.capacity = cfg->capacity;
+        mithra_status st = relay_diag_arenas(b, false);
+        if (st) {
+            h.diag.capacity = old;
+            return st;
         }
     }
     h.diag = *cfg;
@@ -1464,6 +1535,7 @@ static mithra_status config_diag(Batch &b, int s, const mithra_diag_cfg *cfg)
     S.probe[1] = cfg->probe[1];
     S.probe[2] = cfg->probe[2];
     S.kp = cfg->power_plane_k;
+    S.zu0 = plate_position(h);  // the plate may have moved
     S.mesh_every = cfg->mesh_diag_every;
     S.ring_cap = cfg->capacity;
     S.spec_on = cfg->power_spectrum;
@@ -1471,6 +1543,64 @@ static mithra_status config_diag(Batch &b, int s, const mithra_diag_cfg *cfg)
     for (int e = 0; e < 3; ++e)
         if (cfg->extra_planes[e] >= 0) S.kp_extra[S.n_extra++] = cfg->extra_planes[e];
     return build_tables(b);
+}
+
+static mithra_status set_spectrum(Batch &b, int s, const double *nu, int32_t nfreq)
+{
+    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
+    if (!nu || nfreq < 1 || nfreq > MAXF)
+        return fail(MITHRA_EINVAL, "need 1..%d normalized frequencies", MAXF);
+    for (int f = 0; f < nfreq; ++f)
+        if (!(nu[f] > 0.0) || !std::isfinite(nu[f]))
+            return fail(MITHRA_EINVAL, "normalized frequency %d = %g must be positive and finite", f,
+                        nu[f]);
+    if (b.step > 0)
+        return fail(MITHRA_ESTATE, "the spectrum frequencies can only change before the first step");
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    HostSim &h = b.hs[s];
+    const int old_n = h.nfreq;
+    double old_f[MAXF];
+    std::memcpy(old_f, h.fnu, sizeof old_f);
+    h.nfreq = nfreq;
+    for (int f = 0; f < MAXF; ++f) h.fnu[f] = f < nfreq ? nu[f] : 0.0;
+    mithra_status st = relay_diag_arenas(b, true);
+    if (st) {
+        h.nfreq = old_n;
+        std::memcpy(h.fnu, old_f, sizeof old_f);
+        return st;
+    }
+    for (int i = 0; i < b.nsim; ++i) {
+        b.sd[i].nfreq = b.hs[i].nfreq;
+        std::memcpy(b.sd[i].fnu, b.hs[i].fnu, sizeof b.sd[i].fnu);
+    }
+    return build_tables(b);
+}
+
+static mithra_status get_spectrum(Batch &b, int s, int64_t first, int64_t count, double *rest,
+                                  double *lab)
+{
+    if (s < 0 || s >= b.nsim) return fail(MITHRA_EINVAL, "sim index %d out of range", s);
+    if (count < 0 || (count > 0 && (!rest || !lab)))
+        return fail(MITHRA_EINVAL, "count < 0 or rest/lab NULL");
+    mithra_status st = sync_stream(b);
+    if (st) return st;
+    const SimDev &S = b.sd[s];
+    if (!S.spec_on) return fail(MITHRA_ESTATE, "the power spectrum is off (mithra_diag_cfg.power_spectrum)");
+    const long long lo = std::max(0LL, b.step - (long long)S.ring_cap);
+    if (first < lo || first + count > b.step)
+        return fail(MITHRA_EINVAL, "steps %lld..%lld not in the kept rows %lld..%lld",
+                    (long long)first, (long long)(first + count - 1), lo, b.step - 1);
+    if (count == 0) return MITHRA_OK;
+    const int nf = S.nfreq;
+    std::vector<double> ring((size_t)S.ring_cap * 2 * nf);
+    HIP_TRY(hipMemcpy(ring.data(), b.ar.srow + S.srow0, sizeof(double) * ring.size(),
+                      hipMemcpyDeviceToHost));
+    for (int64_t r = 0; r < count; ++r) {
+        const double *v = &ring[(size_t)((first + r) % S.ring_cap) * 2 * nf];
+        std::memcpy(rest + r * nf, v, sizeof(double) * nf);
+        std::memcpy(lab + r * nf, v + nf, sizeof(double) * nf);
+    }
+    return MITHRA_OK;
 }
 
 // checks of a wave's parameters (the seed and the optical undulator)
@@ -1735,6 +1865,12 @@ static mithra_status tune(Batch &b, int trials)
 // checkpoint
 // ---------------------------------------------------------------------------
 
+struct SpecTrailer {
+    int64_t step0;
+    int32_t nfreq, pad;
+    double fnu[MAXF];
+};
+
 struct StateHeader {
     char magic[8];
     int32_t version, prec, n[3], pad;
@@ -1749,11 +1885,15 @@ static mithra_status get_state_impl(Batch &b, void *blob, size_t *bytes)
     const long long np = S.np;
     const size_t mesh_bytes = (size_t)ncell * sizeof(R);
     // potentials at levels s-1 and s, J (3), rho (2), particles in id order:
-    // alive (1 byte), cell (3 int), offset (3 R), u (3 R); then (version 2)
-    // the running DFT of the power plane, SPEC_PER_POINT doubles per point
-    const size_t spec_bytes = sizeof(double) * (size_t)S.n[0] * S.n[1] * SPEC_PER_POINT;
+    // alive (1 byte), cell (3 int), offset (3 R), u (3 R); then (version 3)
+    // the spectrum's start step, frequency count and normalized frequencies
+    // and its running DFT, 8 doubles per plane point and frequency
+    const HostSim &h = b.hs[0];
+    const size_t spec_bytes = sizeof(double) * (size_t)S.n[0] * S.n[1] * SPEC_PER_FREQ * h.nfreq;
     const size_t part_bytes = (size_t)np * (1 + 3 * sizeof(int) + 6 * sizeof(R));
-    const size_t need = sizeof(StateHeader) + mesh_bytes * (8 + 3 + 2) + part_bytes + spec_bytes;
+    const size_t trail_bytes = sizeof(SpecTrailer);
+    const size_t need = sizeof(StateHeader) + mesh_bytes * (8 + 3 + 2) + part_bytes + trail_bytes +
+                        spec_bytes;
     if (!blob) {
         *bytes = need;
         return MITHRA_OK;
@@ -1765,7 +1905,7 @@ static mithra_status get_state_impl(Batch &b, void *blob, size_t *bytes)
     StateHeader hd;
     std::memset(&hd, 0, sizeof hd);
     std::memcpy(hd.magic, "MITHRA1", 8);
-    hd.version = 2;
+    hd.version = 3;
     hd.prec = b.prec;
     for (int a = 0; a < 3; ++a) hd.n[a] = S.n[a];
     hd.step = b.step;
@@ -1827,7 +1967,14 @@ static mithra_status get_state_impl(Batch &b, void *blob, size_t *bytes)
             mo[3 * p + a] = uu[a][i];
         }
     }
-    HIP_TRY(hipMemcpy(w + part_bytes, b.ar.spec + S.spec0, spec_bytes, hipMemcpyDeviceToHost));
+    SpecTrailer tr;
+    std::memset(&tr, 0, sizeof tr);
+    tr.step0 = h.step0;
+    tr.nfreq = h.nfreq;
+    std::memcpy(tr.fnu, h.fnu, sizeof tr.fnu);
+    std::memcpy(w + part_bytes, &tr, sizeof tr);
+    HIP_TRY(hipMemcpy(w + part_bytes + trail_bytes, b.ar.spec + S.spec0, spec_bytes,
+                      hipMemcpyDeviceToHost));
     *bytes = need;
     return MITHRA_OK;
 }
@@ -1840,7 +1987,7 @@ static mithra_status set_state_impl(Batch &b, const void *blob, size_t bytes)
     if (bytes < sizeof(StateHeader)) return fail(MITHRA_EINVAL, "blob too small");
     StateHeader hd;
     std::memcpy(&hd, blob, sizeof hd);
-    if (std::memcmp(hd.magic, "MITHRA1", 8) != 0 || (hd.version != 1 && hd.version != 2))
+    if (std::memcmp(hd.magic, "MITHRA1", 8) != 0 || hd.version < 1 || hd.version > 3)
         return fail(MITHRA_EINVAL, "not a state blob of this library");
     if (hd.prec != b.prec || hd.n[0] != S0.n[0] || hd.n[1] != S0.n[1] || hd.n[2] != S0.n[2])
         return fail(MITHRA_EINVAL, "state belongs to another mesh or precision");
@@ -1851,11 +1998,33 @@ static mithra_status set_state_impl(Batch &b, const void *blob, size_t bytes)
         return fail(MITHRA_EINVAL, "corrupt state blob (step %lld, %lld particles)",
                     (long long)hd.step, np);
     const size_t mesh_bytes = (size_t)ncell * sizeof(R);
-    // version 1 has no plane spectrum: it starts again from zero
-    const size_t spec_bytes =
-        hd.version >= 2 ? sizeof(double) * (size_t)S0.n[0] * S0.n[1] * SPEC_PER_POINT : 0;
+    const size_t npl = (size_t)S0.n[0] * S0.n[1];
     const size_t part_bytes = (size_t)np * (1 + 3 * sizeof(int) + 6 * sizeof(R));
-    const size_t need = sizeof(StateHeader) + mesh_bytes * 13 + part_bytes + spec_bytes;
+    // the plane spectrum: version 3 carries its start step and frequencies,
+    // which must be the simulation's; version 2 carries the harmonics 1, 2, 3
+    // from step 0, kept when the simulation samples exactly those; version 1
+    // has none.  Without one, the spectrum restarts at the restored step.
+    HostSim &h = b.hs[0];
+    const bool harmonics = h.nfreq == 3 && h.fnu[0] == 1.0 && h.fnu[1] == 2.0 && h.fnu[2] == 3.0;
+    size_t trail_bytes = 0, spec_bytes = 0, spec_keep = 0;
+    SpecTrailer tr;
+    std::memset(&tr, 0, sizeof tr);
+    if (hd.version == 3) {
+        trail_bytes = sizeof tr;
+        if (bytes < sizeof(StateHeader) + mesh_bytes * 13 + part_bytes + trail_bytes)
+            return fail(MITHRA_EINVAL, "blob truncated");
+        std::memcpy(&tr, (const char *)blob + sizeof hd + mesh_bytes * 13 + part_bytes, sizeof tr);
+        if (tr.nfreq != h.nfreq || std::memcmp(tr.fnu, h.fnu, sizeof tr.fnu) != 0)
+            return fail(MITHRA_EINVAL, "state blob: its spectrum frequencies differ from the "
+                                       "simulation's (set them with mithra_set_spectrum first)");
+        if (tr.step0 < 0 || tr.step0 > hd.step)
+            return fail(MITHRA_EINVAL, "corrupt state blob (spectrum start %lld)", (long long)tr.step0);
+        spec_bytes = spec_keep = sizeof(double) * npl * SPEC_PER_FREQ * h.nfreq;
+    } else if (hd.version == 2) {
+        spec_bytes = sizeof(double) * npl * 24;
+        spec_keep = harmonics ? spec_bytes : 0;
+    }
+    const size_t need = sizeof(StateHeader) + mesh_bytes * 13 + part_bytes + trail_bytes + spec_bytes;
     if (bytes < need) return fail(MITHRA_EINVAL, "blob truncated");
     const char *r = (const char *)blob + sizeof hd + mesh_bytes * 13;
     const unsigned char *al = (const unsigned char *)r;
@@ -1876,7 +2045,6 @@ static mithra_status set_state_impl(Batch &b, const void *blob, size_t bytes)
     }
     HIP_TRY(hipStreamSynchronize(b.stream));
     // particles first (commit re-lays the arenas at the restored step)
-    HostSim &h = b.hs[0];
     h.alive.assign(al, al + np);
     h.cell.assign(cell, cell + 3 * np);
     h.frac.resize(3 * np);
@@ -1905,10 +2073,14 @@ static mithra_status set_state_impl(Batch &b, const void *blob, size_t bytes)
     HIP_TRY(hipMemcpy((char *)b.ar.rho[s & 1] + off, w, mesh_bytes, hipMemcpyHostToDevice));
     w += mesh_bytes;
     HIP_TRY(hipMemcpy((char *)b.ar.rho[(s + 1) & 1] + off, w, mesh_bytes, hipMemcpyHostToDevice));
-    if (spec_bytes)
+    if (spec_keep) {
         HIP_TRY(hipMemcpy(b.ar.spec + S0.spec0,
-                          (const char *)blob + sizeof hd + mesh_bytes * 13 + part_bytes, spec_bytes,
-                          hipMemcpyHostToDevice));
+                          (const char *)blob + sizeof hd + mesh_bytes * 13 + part_bytes + trail_bytes,
+                          spec_keep, hipMemcpyHostToDevice));
+        h.step0 = hd.version == 3 ? tr.step0 : 0;
+        S0.step0 = h.step0;
+        HIP_TRY(hipMemcpyAsync(b.d_sims, &S0, sizeof(SimDev), hipMemcpyHostToDevice, b.stream));
+    }
     HIP_TRY(mark_sources_dirty(b));
     HIP_TRY(hipStreamSynchronize(b.stream));
     h.read_step = s;
@@ -1973,6 +2145,19 @@ mithra_status mithra_config_diag(mithra_sim *sim, const mithra_diag_cfg *cfg)
 {
     if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
     return config_diag(*sim->b, 0, cfg);
+}
+
+mithra_status mithra_set_spectrum(mithra_sim *sim, const double *nu, int32_t nfreq)
+{
+    if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
+    return set_spectrum(*sim->b, 0, nu, nfreq);
+}
+
+mithra_status mithra_get_spectrum(mithra_sim *sim, int64_t first_step, int64_t count, double *rest,
+                                  double *lab)
+{
+    if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
+    return get_spectrum(*sim->b, 0, first_step, count, rest, lab);
 }
 
 mithra_status mithra_set_seed(mithra_sim *sim, const mithra_seed *seed)
@@ -2158,6 +2343,20 @@ mithra_status mithra_batch_config_diag(mithra_batch *bb, int32_t sim, const mith
 {
     if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
     return config_diag(*bb->b, sim, cfg);
+}
+
+mithra_status mithra_batch_set_spectrum(mithra_batch *bb, int32_t sim, const double *nu,
+                                        int32_t nfreq)
+{
+    if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
+    return set_spectrum(*bb->b, sim, nu, nfreq);
+}
+
+mithra_status mithra_batch_get_spectrum(mithra_batch *bb, int32_t sim, int64_t first_step,
+                                        int64_t count, double *rest, double *lab)
+{
+    if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
+    return get_spectrum(*bb->b, sim, first_step, count, rest, lab);
 }
 
 mithra_status mithra_batch_set_seed(mithra_batch *bb, int32_t sim, const mithra_seed *seed)

@@ -39,8 +39,11 @@ ABI_FUNCTIONS = (
     "mithra_set_optical_undulator", "mithra_batch_set_optical_undulator",
     "mithra_set_optical_beam", "mithra_batch_set_optical_beam",
     "mithra_set_seed_beam", "mithra_batch_set_seed_beam", "mithra_set_background",
-    "mithra_get_bins", "mithra_get_field_noalloc",
+    "mithra_get_bins", "mithra_get_field_noalloc", "mithra_set_spectrum", "mithra_get_spectrum",
+    "mithra_batch_set_spectrum", "mithra_batch_get_spectrum",
 )
+
+MAX_FREQ = 32
 
 SIGNALS = {"neumann": 0, "gaussian": 1, "secant": 2, "flat-top": 3}
 
@@ -54,7 +57,8 @@ class Mesh(ctypes.Structure):
 
 class Undulator(ctypes.Structure):
     _fields_ = [("lambda_u", ctypes.c_double), ("K", ctypes.c_double),
-                ("gamma_beam", ctypes.c_double), ("z_entrance", ctypes.c_double)]
+                ("gamma_beam", ctypes.c_double), ("z_entrance", ctypes.c_double),
+                ("length", ctypes.c_double)]
 
 
 class Seed(ctypes.Structure):
@@ -111,7 +115,8 @@ class DiagRow(ctypes.Structure):
                 ("probe_B", ctypes.c_double * 3), ("lost", ctypes.c_int64),
                 ("nonfinite", ctypes.c_int32), ("has_mesh_terms", ctypes.c_int32),
                 ("bunching", ctypes.c_double * 3), ("power_harmonic", ctypes.c_double * 3),
-                ("power_extra", ctypes.c_double * 3)]
+                ("power_extra", ctypes.c_double * 3), ("power_lab", ctypes.c_double),
+                ("z_undulator", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -128,7 +133,8 @@ DIAG_DTYPE = np.dtype([("step", np.int64), ("t", np.float64), ("total_charge", n
                        ("probe_E", np.float64, 3), ("probe_B", np.float64, 3),
                        ("lost", np.int64), ("nonfinite", np.int32),
                        ("has_mesh_terms", np.int32), ("bunching", np.float64, 3),
-                       ("power_harmonic", np.float64, 3), ("power_extra", np.float64, 3)])
+                       ("power_harmonic", np.float64, 3), ("power_extra", np.float64, 3),
+                       ("power_lab", np.float64), ("z_undulator", np.float64)])
 assert DIAG_DTYPE.itemsize == ctypes.sizeof(DiagRow)
 
 
@@ -190,6 +196,10 @@ def load_library(path: str = LIB_PATH):
         "mithra_batch_create": [I32, ctypes.POINTER(Mesh), ctypes.POINTER(Undulator), I32, P, pp],
         "mithra_batch_set_particles": [P, I32, I64, dp, dp, D, D],
         "mithra_batch_config_diag": [P, I32, ctypes.POINTER(DiagCfg)],
+        "mithra_set_spectrum": [P, dp, I32],
+        "mithra_get_spectrum": [P, I64, I64, dp, dp],
+        "mithra_batch_set_spectrum": [P, I32, dp, I32],
+        "mithra_batch_get_spectrum": [P, I32, I64, I64, dp, dp],
         "mithra_batch_tune": [P, I32],
         "mithra_batch_run": [P, I64],
         "mithra_batch_sync": [P],
@@ -292,8 +302,10 @@ def make_mesh(n, d, origin, courant=0.9, nsfd_A=-1.0, substeps=1, space_charge=1
     return m
 
 
-def make_undulator(lambda_u, K, gamma_beam, z_entrance) -> Undulator:
-    return Undulator(float(lambda_u), float(K), float(gamma_beam), float(z_entrance))
+def make_undulator(lambda_u, K, gamma_beam, z_entrance, length=0.0) -> Undulator:
+    """length: lab length of the undulator [m], whole periods; <= 0 unbounded."""
+    return Undulator(float(lambda_u), float(K), float(gamma_beam), float(z_entrance),
+                     float(length))
 
 
 assert DIAG_DTYPE.itemsize == ctypes.sizeof(DiagRow)
@@ -325,14 +337,15 @@ class Sim:
 
     def __init__(self, n, d, origin, courant=0.9, nsfd_A=-1.0, substeps=1, space_charge=1,
                  bc=(0, 0, 0), lambda_u=0.015, K=1.0, gamma_beam=100.0, z_entrance=0.0,
-                 precision: str = "f64", stream=None, torch_allocator: bool = True):
+                 precision: str = "f64", stream=None, torch_allocator: bool = True,
+                 length=0.0):
         self._lib = load_library()
         if torch_allocator:
             use_torch_allocator(True)
         self.n = tuple(int(v) for v in n)
         self.precision = {"f64": F64, "f32": F32_SPLIT, "f32_split": F32_SPLIT}[precision]
         mesh = make_mesh(n, d, origin, courant, nsfd_A, substeps, space_charge, bc)
-        und = make_undulator(lambda_u, K, gamma_beam, z_entrance)
+        und = make_undulator(lambda_u, K, gamma_beam, z_entrance, length)
         st = stream if stream is not None else _torch_stream()
         h = ctypes.c_void_p()
         _check(self._lib.mithra_create(ctypes.byref(mesh), ctypes.byref(und), self.precision, st,
@@ -398,6 +411,22 @@ class Sim:
     def config_diag(self, probe, kp, every=1, capacity=4096, spectrum=False, extra_planes=()):
         c = make_diag_cfg(probe, kp, every, capacity, spectrum, extra_planes)
         _check(self._lib.mithra_config_diag(self._h, ctypes.byref(c)))
+
+    def set_spectrum(self, nu):
+        """Normalized frequencies of the power spectrum (at most MAX_FREQ)."""
+        nu = np.ascontiguousarray(nu, dtype=np.float64).reshape(-1)
+        _check(self._lib.mithra_set_spectrum(self._h, _dptr(nu), int(nu.size)))
+        self._nfreq = int(nu.size)
+
+    def get_spectrum(self, first_step, count):
+        """(rest, lab), each (count, nfreq): the mean power at each frequency
+        for rows first_step .. first_step + count - 1."""
+        nf = getattr(self, "_nfreq", 3)
+        rest = np.empty((max(count, 1), nf))
+        lab = np.empty((max(count, 1), nf))
+        _check(self._lib.mithra_get_spectrum(self._h, int(first_step), int(count), _dptr(rest),
+                                             _dptr(lab)))
+        return rest[:count], lab[:count]
 
     def run(self, nsteps: int):
         _check(self._lib.mithra_run(self._h, int(nsteps)))
@@ -549,6 +578,21 @@ class Batch:
         c = make_diag_cfg(probe, kp, every, capacity, spectrum, extra_planes)
         _check(self._lib.mithra_batch_config_diag(self._h, int(s), ctypes.byref(c)))
 
+    def set_spectrum(self, s, nu):
+        nu = np.ascontiguousarray(nu, dtype=np.float64).reshape(-1)
+        _check(self._lib.mithra_batch_set_spectrum(self._h, int(s), _dptr(nu), int(nu.size)))
+        if not hasattr(self, "_nfreq"):
+            self._nfreq = [3] * self.nsim
+        self._nfreq[s] = int(nu.size)
+
+    def get_spectrum(self, s, first_step, count):
+        nf = getattr(self, "_nfreq", [3] * self.nsim)[s]
+        rest = np.empty((max(count, 1), nf))
+        lab = np.empty((max(count, 1), nf))
+        _check(self._lib.mithra_batch_get_spectrum(self._h, int(s), int(first_step), int(count),
+                                                   _dptr(rest), _dptr(lab)))
+        return rest[:count], lab[:count]
+
     def tune(self, trials: int = 5):
         _check(self._lib.mithra_batch_tune(self._h, int(trials)))
 
@@ -604,7 +648,8 @@ def sim_from_workload(w, precision: str = "f64", every: int = 1, capacity: int =
     """A simulation loaded with a workload from the seeded generator (every
     diagnostic on, the plane spectrum included, unless told otherwise)."""
     s = Sim(w.n, w.d, w.origin, w.courant, w.nsfd_A, w.substeps, w.space_charge, w.bc,
-            w.lambda_u, w.K, w.gamma_beam, w.z_e, precision=precision, **kw)
+            w.lambda_u, w.K, w.gamma_beam, w.z_e, precision=precision,
+            length=w.und_length, **kw)
     s.config_diag(w.probe, w.kp, every=every, capacity=capacity, spectrum=spectrum)
     s.set_particles(w.x, w.u, w.q, w.m)
     return s
@@ -614,7 +659,7 @@ def batch_from_workloads(ws, precision: str = "f32", every: int = 1, capacity: i
                          spectrum: bool = True, **kw) -> Batch:
     meshes = [make_mesh(w.n, w.d, w.origin, w.courant, w.nsfd_A, w.substeps, w.space_charge,
                         w.bc) for w in ws]
-    unds = [make_undulator(w.lambda_u, w.K, w.gamma_beam, w.z_e) for w in ws]
+    unds = [make_undulator(w.lambda_u, w.K, w.gamma_beam, w.z_e, w.und_length) for w in ws]
     b = Batch(meshes, unds, precision=precision, **kw)
     for s, w in enumerate(ws):
         b.config_diag(s, w.probe, w.kp, every=every, capacity=capacity, spectrum=spectrum)

@@ -2,8 +2,9 @@
  * stream the library creates).  Reads a workload from a binary file, runs
  * it and writes the diagnostic rows and A_x.  Input, all doubles: n[3],
  * d[3], origin[3], courant, nsfd_A, substeps, space_charge, bc[3],
- * lambda_u, K, gamma, z_entrance, q, m, np, steps, probe[3], kp, then the
- * positions [np][3] and momenta [np][3].  Output: int64 row count, the rows
+ * lambda_u, K, gamma, z_entrance, q, m, np, steps, probe[3], kp, the
+ * undulator length, a spare value, then the positions [np][3] and momenta
+ * [np][3].  Output: int64 row count, the rows
  * (mithra_diag_row), then A_x (n[0] n[1] n[2] doubles). */
 #include <stdio.h>
 #include <stdlib.h>
@@ -42,6 +43,7 @@ int main(int argc, char **argv)
     und.K = h[17];
     und.gamma_beam = h[18];
     und.z_entrance = h[19];
+    und.length = h[28];
     const double q = h[20], m = h[21];
     const int64_t np = (int64_t)h[22], steps = (int64_t)h[23];
     double *pos = malloc(sizeof(double) * 3 * (np > 0 ? np : 1));

@@ -33,11 +33,11 @@ def test_library_loads_and_exports_every_declared_symbol():
 def test_struct_layouts_match_the_header():
     # sizes implied by the C declarations (natural alignment on x86-64)
     assert ctypes.sizeof(native.Mesh) == 3 * 4 + 4 + 3 * 8 + 3 * 8 + 8 + 8 + 4 + 4 + 3 * 4 + 4
-    assert ctypes.sizeof(native.Undulator) == 32
+    assert ctypes.sizeof(native.Undulator) == 40
     assert ctypes.sizeof(native.Seed) == 8 * 8 + 4 + 4
     assert ctypes.sizeof(native.Beam) == 4 + 4 + 2 * 8 + 3 * 8
     assert ctypes.sizeof(native.DiagCfg) == 28 + 12
-    assert ctypes.sizeof(native.DiagRow) == 8 * 14 + 4 + 4 + 3 * 8 + 3 * 8 + 3 * 8
+    assert ctypes.sizeof(native.DiagRow) == 8 * 14 + 4 + 4 + 3 * 8 + 3 * 8 + 3 * 8 + 2 * 8
     assert ctypes.sizeof(native.Info) == 7 * 8 + 3 * 8 + 3 * 4 + 4
 
 

@@ -1245,10 +1245,12 @@ def test_run_before_particles_is_a_state_error():
 
 def test_device_bytes_follow_reallocations():
     """device_bytes is what the simulation holds: a re-laid diagnostic ring
-    replaces the old one, and re-loading particles leaves no blocks behind."""
+    (and its per-row spectra) replaces the old one, and re-loading particles
+    leaves no blocks behind."""
     w = W.config(0, steps=4)
-    sim = native.sim_from_workload(w)  # ring of 4096 rows of 27 doubles
-    row = 27 * 8  # bytes of one row of the device ring
+    sim = native.sim_from_workload(w)  # ring of 4096 rows of 29 doubles
+    row = 29 * 8  # bytes of one row of the device ring
+    srow = 2 * 3 * 8  # and of its spectrum row (3 frequencies, bunch frame and lab)
 
     def block(n):  # device blocks are sized in multiples of 256 bytes
         return (n + 255) // 256 * 256
@@ -1256,7 +1258,8 @@ def test_device_bytes_follow_reallocations():
     b0 = sim.info()["device_bytes"]
     sim.config_diag(w.probe, w.kp, capacity=100)
     b1 = sim.info()["device_bytes"]
-    assert b0 - b1 == block(4096 * row) - block(100 * row)
+    assert b0 - b1 == (block(4096 * row) - block(100 * row) + block(4096 * srow) -
+                       block(100 * srow))
     sim.config_diag(w.probe, w.kp, capacity=4096)
     assert sim.info()["device_bytes"] == b0
     sim.set_particles(w.x, w.u, w.q, w.m)
