@@ -213,8 +213,8 @@ def measure(w, precision, steps, warmup, torch, native, tune=True, every=100, se
         sim.tune(3)
     sim.run(max(warmup, 1))
     sim.sync()
-    log("  set-up + warm-up %.1f s, tile %s" % (time.perf_counter() - t_setup,
-                                                sim.info()["stencil_tile"]))
+    log("  set-up + warm-up %.1f s, tile %s, brick %s" % (
+        time.perf_counter() - t_setup, sim.info()["stencil_tile"], sim.info()["particle_brick"]))
     dt = timed_run(sim, steps, torch)
     sim.set_timing(True)
     sim.get_timing(reset=True)
@@ -548,7 +548,8 @@ def main():
                    "courant": w.courant, "nsfd_A": info["nsfd_A"], "substeps": w.substeps,
                    "space_charge": w.space_charge, "gamma": w.gamma_beam, "K": w.K,
                    "lambda_u": w.lambda_u, "mesh_diag_every": 100,
-                   "stencil_tile": info["stencil_tile"]},
+                   "stencil_tile": info["stencil_tile"],
+                   "particle_brick": info["particle_brick"]},
         "particle_pushes_per_s": pushes,
         "event_region_ms_per_step": round(dt_ev * 1e3 / K, 5),
         "whole_step_algorithmic_GBs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),

@@ -225,6 +225,9 @@ typedef struct {
     int64_t device_bytes;     /* device memory held */
     int32_t stencil_tile[3];  /* x, y columns per block and z planes per block */
     int32_t precision;        /* mithra_precision */
+    int32_t particle_brick[3]; /* tiles of 8^3 cells per brick along x, y, z: the push and the
+                                  deposit deal bricks of tiles to the XCDs (from the tuner) */
+    int32_t pad;
 } mithra_info;
 
 /* ---- single simulation -------------------------------------------------- */
@@ -423,8 +426,12 @@ mithra_status mithra_get_timing(mithra_sim *sim, double *ms, int64_t *calls, int
                                 int32_t reset);
 
 /* Autotuner: times trial_steps launches of the potential-update kernel for
-   each candidate tile shape (x and y columns per block, z planes per block)
-   and keeps the fastest.  The simulation state is unchanged. */
+   each candidate tile shape (x and y columns per block, z planes per block),
+   then of the push followed by the deposit for each candidate brick shape
+   (tiles per brick dealt to one XCD), and keeps the fastest of each.  The
+   simulation state is unchanged (the particle kernels' outputs are restored
+   after every trial), and later steps give the same results bit for bit
+   whatever shapes were chosen. */
 mithra_status mithra_tune(mithra_sim *sim, int32_t trial_steps);
 
 const char *mithra_last_error(void);

@@ -29,15 +29,27 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 }
 
 // Particle work is concentrated where the bunch is.  The tiles are dealt to
-// the XCDs in chunks (a few tile layers along z): XCD x takes chunks x, x + 8,
-// x + 16, ..., so every XCD gets a share of the dense region while the tiles
-// of a chunk still share halo lines in one L2.  The grid is padded to whole
-// rounds of 8 chunks; blocks past the last tile get -1.
-__device__ __forceinline__ int tile_deal(int b, int nb, int chunk)
+// the XCDs in bricks of bs.x x bs.y x bs.z tiles: XCD x takes bricks x, x + 8,
+// x + 16, ..., so every XCD gets a share of the dense region, while the tiles
+// of a brick, which run at about the same time on one XCD, share their halo
+// lines in its L2.  Inside a brick the tiles go x fastest.  The grid is
+// padded to whole rounds of 8 bricks; a block past the last brick, or on a
+// slot of an edge brick outside its simulation's grid, gets false.  sim and
+// t: the simulation and its tile; g: the global tile index (tile0 + t).
+__device__ __forceinline__ bool brick_tile(int b, const Brick *__restrict__ bricks, int nbricks,
+                                           int4 bs, int &sim, int &t, int &g)
 {
     const int x = b & 7, i = b >> 3;
-    const long long t = (long long)(x + 8 * (i / chunk)) * chunk + i % chunk;
-    return t < nb ? (int)t : -1;
+    const int B = x + 8 * (i / bs.w), w = i % bs.w;
+    if (B >= nbricks) return false;
+    const Brick br = bricks[B];
+    const int wx = w % bs.x, wy = (w / bs.x) % bs.y, wz = w / (bs.x * bs.y);
+    const int tx = br.t0[0] + wx, ty = br.t0[1] + wy, tz = br.t0[2] + wz;
+    if (tx >= br.nt[0] || ty >= br.nt[1] || tz >= br.nt[2]) return false;
+    sim = br.sim;
+    t = (tz * br.nt[1] + ty) * br.nt[0] + tx;
+    g = br.g0 + (wz * br.nt[1] + wy) * br.nt[0] + wx;
+    return true;
 }
 
 // index along an axis, wrapped on a periodic axis, clamped otherwise (clamped
@@ -893,11 +905,11 @@ __device__ __forceinline__ void count_runs(int *counts, int key, bool active)
 // transcendentals would otherwise raise the register count of every launch)
 template <typename R, bool OPTICAL>
 __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
-                                                 const int2 *__restrict__ items, int nitems,
-                                                 int chunk, Arena ar)
+                                                 const Brick *__restrict__ bricks, int nbricks,
+                                                 int4 bs, Arena ar)
 {
-    const int ti = tile_deal(blockIdx.x, nitems, chunk);  // global tile index
-    if (ti < 0) return;
+    int sim, tl, ti;  // ti: the global tile index
+    if (!brick_tile(blockIdx.x, bricks, nbricks, bs, sim, tl, ti)) return;
     // A tile that no particle entered in the previous step (flag written by
     // that step's push, or set for all tiles after particles are loaded) has
     // nothing to do: one round trip decides it.
@@ -905,7 +917,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
     const long long step = *ar.d_step;
     const int par = (int)(step & 1);
     if ((par ? occ1 : occ0) == 0) return;
-    const int2 it = items[ti];
+    const int2 it = make_int2(sim, tl);
     const SimDev &S = sims[it.x];
     const int *__restrict__ offs = ar.offs[par];
     if (it.y == 0 && threadIdx.x == 0) {
@@ -1322,8 +1334,8 @@ __device__ __forceinline__ long long fx_round(double v)
 
 template <typename R>
 __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ sims,
-                                                    const int2 *__restrict__ items, int nitems,
-                                                    int chunk, Arena ar, int init)
+                                                    const Brick *__restrict__ bricks, int nbricks,
+                                                    int4 bs, Arena ar, int init)
 {
     // The tile table lists the tiles of all simulations in order, so the
     // entry index is the global tile index.  A tile with no particle in its
@@ -1332,11 +1344,11 @@ __global__ __launch_bounds__(BLOCK) void k_deposit(const SimDev *__restrict__ si
     // the table entry and the step counter are read in one round trip.  (The
     // first deposit after loading particles has no push before it and takes
     // every tile.)
-    const int tg = tile_deal(blockIdx.x, nitems, chunk);
-    if (tg < 0) return;
+    int sim, tl, tg;  // tg: the global tile index
+    if (!brick_tile(blockIdx.x, bricks, nbricks, bs, sim, tl, tg)) return;
     const int act = ar.tact[tg];
     const int jd = ar.jdirty[tg], rd0 = ar.rdirty[0][tg], rd1 = ar.rdirty[1][tg];
-    const int2 it = items[tg];
+    const int2 it = make_int2(sim, tl);
     const long long step = *ar.d_step;
     const int par = (int)(step & 1);
     const int dst = init ? par : par ^ 1;
@@ -2208,32 +2220,32 @@ void launch_mur2(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg,
                        ar);
 }
 
-static int dealt_grid(int nitems, int chunk)
+// whole rounds of 8 bricks
+static int dealt_grid(int nbricks, int4 bs)
 {
-    const long long round = 8LL * chunk;
-    return (int)((nitems + round - 1) / round * round);
+    return (int)((nbricks + 7) / 8 * 8LL * bs.w);
 }
 
 template <typename R>
-void launch_push(hipStream_t st, const SimDev *sims, const int2 *items, int nitems, int chunk,
+void launch_push(hipStream_t st, const SimDev *sims, const Brick *bricks, int nbricks, int4 bs,
                  const Arena &ar, int optical)
 {
-    if (nitems <= 0) return;
+    if (nbricks <= 0) return;
     if (optical)
-        hipLaunchKernelGGL((k_push<R, true>), dim3(dealt_grid(nitems, chunk)), dim3(BLOCK), 0, st,
-                           sims, items, nitems, chunk, ar);
+        hipLaunchKernelGGL((k_push<R, true>), dim3(dealt_grid(nbricks, bs)), dim3(BLOCK), 0, st,
+                           sims, bricks, nbricks, bs, ar);
     else
-        hipLaunchKernelGGL((k_push<R, false>), dim3(dealt_grid(nitems, chunk)), dim3(BLOCK), 0, st,
-                           sims, items, nitems, chunk, ar);
+        hipLaunchKernelGGL((k_push<R, false>), dim3(dealt_grid(nbricks, bs)), dim3(BLOCK), 0, st,
+                           sims, bricks, nbricks, bs, ar);
 }
 
 template <typename R>
-void launch_deposit(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
-                    int chunk, const Arena &ar, int init)
+void launch_deposit(hipStream_t st, const SimDev *sims, const Brick *bricks, int nbricks, int4 bs,
+                    const Arena &ar, int init)
 {
-    if (nitems <= 0) return;
-    hipLaunchKernelGGL((k_deposit<R>), dim3(dealt_grid(nitems, chunk)), dim3(BLOCK), 0, st,
-                       sims, items, nitems, chunk, ar, init);
+    if (nbricks <= 0) return;
+    hipLaunchKernelGGL((k_deposit<R>), dim3(dealt_grid(nbricks, bs)), dim3(BLOCK), 0, st, sims,
+                       bricks, nbricks, bs, ar, init);
 }
 
 void launch_scan(hipStream_t st, const Arena &ar, long long nkeys_total, int *block_sums,
@@ -2302,9 +2314,9 @@ void launch_to_double(hipStream_t st, const float *src, long long count, double 
                                      const Arena &);                                            \
     template void launch_mur2<R>(hipStream_t, const SimDev *, const BSeg *, int, long long,     \
                                  const Arena &);                                                \
-    template void launch_push<R>(hipStream_t, const SimDev *, const int2 *, int, int,           \
+    template void launch_push<R>(hipStream_t, const SimDev *, const Brick *, int, int4,         \
                                  const Arena &, int);                                           \
-    template void launch_deposit<R>(hipStream_t, const SimDev *, const int2 *, int, int,        \
+    template void launch_deposit<R>(hipStream_t, const SimDev *, const Brick *, int, int4,      \
                                     const Arena &, int);                                        \
     template void launch_scatter<R>(hipStream_t, const Arena &, long long);                     \
     template void launch_diag<R>(hipStream_t, const SimDev *, int, const int2 *, int,           \

@@ -149,6 +149,16 @@ struct Arena {
     int *fin_ctr;       // row-writing blocks done in this step (back to 0 after it)
 };
 
+// The push and the deposit deal tiles to the XCDs in bricks of bx x by x bz
+// tiles (the brick shape, chosen by the tuner): the brick table lists, per
+// simulation, the bricks of its tile grid in order, x fastest.
+struct Brick {
+    int sim;   // simulation
+    int g0;    // global index of the brick's first tile
+    int t0[3]; // its first tile, in tile coordinates
+    int nt[3]; // the simulation's tiles per axis
+};
+
 struct BSeg {
     int sim, comp, group, pad;  // group: axis of the faces
     long long start, count;
@@ -174,14 +184,14 @@ void launch_boundary(hipStream_t st, const SimDev *sims, const BSeg *segs, int n
 template <typename R>
 void launch_mur2(hipStream_t st, const SimDev *sims, const BSeg *segs, int nseg, long long total,
                  const Arena &ar);
-// push and deposit: the tile table is dealt to the XCDs in chunks of `chunk`
-// tiles; optical: some simulation has the optical undulator on
+// push and deposit: bricks of bs.x x bs.y x bs.z tiles (bs.w tiles a brick)
+// dealt to the XCDs; optical: some simulation has the optical undulator on
 template <typename R>
-void launch_push(hipStream_t st, const SimDev *sims, const int2 *items, int nitems, int chunk,
+void launch_push(hipStream_t st, const SimDev *sims, const Brick *bricks, int nbricks, int4 bs,
                  const Arena &ar, int optical);
 template <typename R>
-void launch_deposit(hipStream_t st, const SimDev *sims, const int2 *items, int nitems,
-                    int chunk, const Arena &ar, int init);
+void launch_deposit(hipStream_t st, const SimDev *sims, const Brick *bricks, int nbricks, int4 bs,
+                    const Arena &ar, int init);
 void launch_scan(hipStream_t st, const Arena &ar, long long nkeys_total, int *block_sums,
                  int nblocks, const long long *d_step);
 template <typename R>
@@ -190,6 +200,8 @@ template <typename R>
 void launch_diag(hipStream_t st, const SimDev *sims, int nsim, const int2 *plane_items,
                  int nplane, const int2 *mesh_items, int nmesh, const int2 *kin_items, int nkin,
                  const Arena &ar);
+// E and B of cells g0 .. g0+count-1 of simulation `sim` into out6: component
+// a (Ex, Ey, Ez, Bx, By, Bz) of cell g0 + e at out6[a * count + e]
 // E and B of cells g0 .. g0+count-1 of simulation `sim` into out6: component
 // a (Ex, Ey, Ez, Bx, By, Bz) of cell g0 + e at out6[a * count + e]
 template <typename R>

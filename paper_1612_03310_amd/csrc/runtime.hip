@@ -116,9 +116,11 @@ struct Batch {
     BSeg *d_m2seg[3] = {nullptr, nullptr, nullptr};
     int nm2seg[3] = {0, 0, 0};
     long long nm2_total[3] = {0, 0, 0};
-    int2 *d_tiles = nullptr;
     int n_tiles = 0;
-    int tile_chunk = 1;  // tiles per chunk dealt to one XCD (push, deposit)
+    // push and deposit: bricks of tiles dealt to the XCDs (shape from the tuner)
+    int brick[3] = {4, 4, 4};
+    Brick *d_bricks = nullptr;
+    int n_bricks = 0;
     int2 *d_plane = nullptr, *d_mesh = nullptr, *d_kin = nullptr;
     int n_plane = 0, n_mesh = 0, n_kin = 0;
     int *d_bsum = nullptr;
@@ -534,6 +536,32 @@ static bool x_faces_fusable(const Batch &b, int tx)
     return true;
 }
 
+// the bricks of every simulation's tile grid, in order (x fastest)
+static void brick_table(const Batch &b, const int shape[3], std::vector<Brick> &out)
+{
+    out.clear();
+    for (int s = 0; s < b.nsim; ++s) {
+        const SimDev &S = b.sd[s];
+        for (int z = 0; z < S.nt[2]; z += shape[2])
+            for (int y = 0; y < S.nt[1]; y += shape[1])
+                for (int x = 0; x < S.nt[0]; x += shape[0]) {
+                    Brick br;
+                    br.sim = s;
+                    br.g0 = S.tile0 + (z * S.nt[1] + y) * S.nt[0] + x;
+                    br.t0[0] = x;
+                    br.t0[1] = y;
+                    br.t0[2] = z;
+                    for (int a = 0; a < 3; ++a) br.nt[a] = S.nt[a];
+                    out.push_back(br);
+                }
+    }
+}
+
+static int4 brick_shape(const int shape[3])
+{
+    return make_int4(shape[0], shape[1], shape[2], shape[0] * shape[1] * shape[2]);
+}
+
 static mithra_status build_tables(Batch &b)
 {
     (void)hipStreamSynchronize(b.stream);
@@ -619,13 +647,12 @@ static mithra_status build_tables(Batch &b)
         if ((st = upload_table(b, m2, &b.d_m2seg[stage]))) return st;
     }
     // tiles
-    std::vector<int2> tiles, plane, mesh, kin;
-    int slot = 0;
+    std::vector<int2> plane, mesh, kin;
+    int slot = 0, ntiles = 0;
     for (int s = 0; s < b.nsim; ++s) {
         SimDev &S = b.sd[s];
-        const int nt = S.nt[0] * S.nt[1] * S.nt[2];
-        S.tile0 = (int)tiles.size();
-        for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(s, t));
+        S.tile0 = ntiles;
+        ntiles += S.nt[0] * S.nt[1] * S.nt[2];
         const long long ncell = (long long)S.n[0] * S.n[1] * S.n[2];
         S.nb_plane = (S.n[0] * S.n[1] + BLOCK - 1) / BLOCK;
         S.nb_mesh = S.mesh_every > 0
@@ -646,16 +673,14 @@ static mithra_status build_tables(Batch &b)
         for (int i = 0; i < S.nb_mesh; ++i) mesh.push_back(make_int2(s, i));
         for (int i = 0; i < S.nb_kin; ++i) kin.push_back(make_int2(s, i));
     }
-    b.n_tiles = (int)tiles.size();
-    // chunks of two tile layers of the widest simulation, but at least 32
-    // chunks in all so that the dense region spreads over the XCDs
-    int layer = 1;
-    for (int s = 0; s < b.nsim; ++s) layer = std::max(layer, b.sd[s].nt[0] * b.sd[s].nt[1]);
-    b.tile_chunk = std::max(1, std::min(2 * layer, (b.n_tiles + 31) / 32));
+    b.n_tiles = ntiles;
+    std::vector<Brick> bricks;
+    brick_table(b, b.brick, bricks);
+    b.n_bricks = (int)bricks.size();
     b.n_plane = (int)plane.size();
     b.n_mesh = (int)mesh.size();
     b.n_kin = (int)kin.size();
-    if ((st = upload_table(b, tiles, &b.d_tiles))) return st;
+    if ((st = upload_table(b, bricks, &b.d_bricks))) return st;
     if ((st = upload_table(b, plane, &b.d_plane))) return st;
     if ((st = upload_table(b, mesh, &b.d_mesh))) return st;
     if ((st = upload_table(b, kin, &b.d_kin))) return st;
@@ -1059,7 +1084,7 @@ static mithra_status commit_impl(Batch &b)
     mithra_status s2 = build_tables(b);
     if (s2) return s2;
     // rho^{s+1/2} from the loaded positions; J^s = 0 (start = end position)
-    launch_deposit<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar, 1);
+    launch_deposit<R>(st, b.d_sims, b.d_bricks, b.n_bricks, brick_shape(b.brick), b.ar, 1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     b.committed = true;
@@ -1114,12 +1139,13 @@ static void enqueue_step(Batch &b, bool timed)
         launch_mur2<R>(st, b.d_sims, b.d_m2seg[stage], b.nm2seg[stage], b.nm2_total[stage], b.ar);
     mark(K_BOUNDARY, false);
     mark(K_PUSH, true);
-    launch_push<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar, any_optical(b));
+    launch_push<R>(st, b.d_sims, b.d_bricks, b.n_bricks, brick_shape(b.brick), b.ar,
+                   any_optical(b));
     mark(K_PUSH, false);
     if (timed) {
         // one stream, so that each kind's events bracket that kind alone
         mark(K_DEPOSIT, true);
-        launch_deposit<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar, 0);
+        launch_deposit<R>(st, b.d_sims, b.d_bricks, b.n_bricks, brick_shape(b.brick), b.ar, 0);
         mark(K_DEPOSIT, false);
         mark(K_SCAN, true);
         launch_scan(st, b.ar, b.total_keys, b.d_bsum, b.n_scan_blocks, b.ar.d_step);
@@ -1137,7 +1163,7 @@ static void enqueue_step(Batch &b, bool timed)
         launch_scan(b.side, b.ar, b.total_keys, b.d_bsum, b.n_scan_blocks, b.ar.d_step);
         launch_scatter<R>(b.side, b.ar, b.total_particles);
         (void)hipEventRecord(b.ev_join, b.side);
-        launch_deposit<R>(st, b.d_sims, b.d_tiles, b.n_tiles, b.tile_chunk, b.ar, 0);
+        launch_deposit<R>(st, b.d_sims, b.d_bricks, b.n_bricks, brick_shape(b.brick), b.ar, 0);
         (void)hipStreamWaitEvent(st, b.ev_join, 0);
     }
     mark(K_DIAG, true);
@@ -1776,6 +1802,8 @@ static mithra_status get_info(Batch &b, int s, mithra_info *info)
     info->stencil_tile[1] = b.tile_y;
     info->stencil_tile[2] = b.kz;
     info->precision = b.prec;
+    for (int a = 0; a < 3; ++a) info->particle_brick[a] = b.brick[a];
+    info->pad = 0;
     return MITHRA_OK;
 }
 
@@ -1783,6 +1811,93 @@ static mithra_status get_info(Batch &b, int s, mithra_info *info)
 // autotuner: the stencil rewrites level s+1 from levels s and s-1, so timing
 // it repeatedly leaves the state unchanged.
 // ---------------------------------------------------------------------------
+
+// The brick shape of the push and the deposit: each candidate times trials
+// launches of the push followed by the deposit on the simulation's current
+// particles.  Those kernels change the particle buffer in place and write J,
+// rho, the bin counts and the flags, so these are copied aside first and put
+// back after every trial; the tile flags are reset by the table rebuild
+// that follows (the results of a step never depend on the brick shape).
+template <typename R>
+static mithra_status tune_bricks(Batch &b, int trials)
+{
+    static const int shapes[][3] = {{2, 2, 2}, {4, 4, 2}, {4, 4, 4}, {8, 8, 2}, {8, 4, 4},
+                                    {4, 4, 8}, {8, 8, 4}, {2, 2, 16}, {16, 16, 2}, {32, 32, 2}};
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    const long long N = b.total_particles, M = b.total_cells;
+    const int par = (int)(b.step & 1), dst = par ^ 1;
+    struct Span {
+        void *p;
+        size_t bytes;
+    };
+    std::vector<Span> keep = {{b.ar.key[par], sizeof(int) * N}, {b.ar.rho[dst], sizeof(R) * M},
+                              {b.ar.flags, sizeof(int) * b.nsim}};
+    for (int a = 0; a < 3; ++a) {
+        keep.push_back({b.ar.off[par][a], sizeof(R) * N});
+        keep.push_back({b.ar.u[par][a], sizeof(R) * N});
+        keep.push_back({b.ar.J[a], sizeof(R) * M});
+    }
+    std::vector<Batch::Block> scratch;
+    std::vector<void *> copy;
+    for (const Span &k : keep) {
+        void *c = dev_alloc(b, std::max<size_t>(k.bytes, 1), scratch);
+        if (!c) {
+            dev_free_all(b, scratch);
+            return MITHRA_OK;  // no room to tune: keep the current shape
+        }
+        copy.push_back(c);
+        HIP_TRY(hipMemcpyAsync(c, k.p, k.bytes, hipMemcpyDeviceToDevice, b.stream));
+    }
+    auto restore = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; i < keep.size() && e == hipSuccess; ++i)
+            e = hipMemcpyAsync(keep[i].p, copy[i], keep[i].bytes, hipMemcpyDeviceToDevice, b.stream);
+        if (e == hipSuccess) e = hipMemsetAsync(b.ar.counts, 0, sizeof(int) * b.total_keys, b.stream);
+        return e;
+    };
+    int maxt[3] = {1, 1, 1};
+    for (int s = 0; s < b.nsim; ++s)
+        for (int a = 0; a < 3; ++a) maxt[a] = std::max(maxt[a], b.sd[s].nt[a]);
+    hipEvent_t e0 = new_event(), e1 = new_event();
+    float best = 1e30f;
+    int pick[3] = {b.brick[0], b.brick[1], b.brick[2]};
+    std::vector<Brick> table;
+    for (const auto &sh : shapes) {
+        int c[3];
+        for (int a = 0; a < 3; ++a) c[a] = std::min(sh[a], maxt[a]);
+        if (c[0] != sh[0] || c[1] != sh[1] || c[2] != sh[2]) continue;  // larger than every grid
+        brick_table(b, c, table);
+        Brick *d = (Brick *)dev_alloc(b, table.size() * sizeof(Brick), scratch);
+        if (!d) continue;
+        HIP_TRY(hipMemcpyAsync(d, table.data(), table.size() * sizeof(Brick),
+                               hipMemcpyHostToDevice, b.stream));
+        float ms_best = 1e30f;
+        for (int t = 0; t < trials + 1; ++t) {  // the first is a warm-up
+            HIP_TRY(restore());
+            HIP_TRY(hipEventRecord(e0, b.stream));
+            launch_push<R>(b.stream, b.d_sims, d, (int)table.size(), brick_shape(c), b.ar,
+                           any_optical(b));
+            launch_deposit<R>(b.stream, b.d_sims, d, (int)table.size(), brick_shape(c), b.ar, 0);
+            HIP_TRY(hipEventRecord(e1, b.stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipGetLastError());
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (t > 0) ms_best = std::min(ms_best, ms);
+        }
+        if (ms_best < best) {
+            best = ms_best;
+            for (int a = 0; a < 3; ++a) pick[a] = c[a];
+        }
+    }
+    HIP_TRY(restore());
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    dev_free_all(b, scratch);
+    for (int a = 0; a < 3; ++a) b.brick[a] = pick[a];
+    return MITHRA_OK;
+}
 
 template <typename R>
 static mithra_status tune_impl(Batch &b, int trials)
@@ -1847,6 +1962,10 @@ static mithra_status tune_impl(Batch &b, int trials)
     b.tile_x = bx;
     b.tile_y = by;
     b.kz = bk;
+    if (b.total_particles > 0) {
+        mithra_status st = tune_bricks<R>(b, trials);
+        if (st) return st;
+    }
     return build_tables(b);
 }
 

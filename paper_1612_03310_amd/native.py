@@ -124,7 +124,8 @@ class Info(ctypes.Structure):
                 ("gamma0", ctypes.c_double), ("beta0", ctypes.c_double), ("B0", ctypes.c_double),
                 ("ku", ctypes.c_double), ("step", ctypes.c_int64), ("np", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("stencil_tile", ctypes.c_int32 * 3),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("particle_brick", ctypes.c_int32 * 3),
+                ("pad", ctypes.c_int32)]
 
 
 DIAG_DTYPE = np.dtype([("step", np.int64), ("t", np.float64), ("total_charge", np.float64),
@@ -490,8 +491,8 @@ class Sim:
     def info(self) -> dict:
         i = Info()
         _check(self._lib.mithra_get_info(self._h, ctypes.byref(i)))
-        return {k: (list(getattr(i, k)) if k == "stencil_tile" else getattr(i, k))
-                for k, _ in Info._fields_}
+        return {k: (list(getattr(i, k)) if k in ("stencil_tile", "particle_brick") else getattr(i, k))
+                for k, _ in Info._fields_ if k != "pad"}
 
     def get_state(self) -> bytes:
         n = ctypes.c_size_t()
@@ -628,8 +629,8 @@ class Batch:
     def info(self, s) -> dict:
         i = Info()
         _check(self._lib.mithra_batch_get_info(self._h, int(s), ctypes.byref(i)))
-        return {k: (list(getattr(i, k)) if k == "stencil_tile" else getattr(i, k))
-                for k, _ in Info._fields_}
+        return {k: (list(getattr(i, k)) if k in ("stencil_tile", "particle_brick") else getattr(i, k))
+                for k, _ in Info._fields_ if k != "pad"}
 
     def set_timing(self, on: bool):
         _check(self._lib.mithra_batch_set_timing(self._h, 1 if on else 0))

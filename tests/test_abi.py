@@ -38,7 +38,7 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(native.Beam) == 4 + 4 + 2 * 8 + 3 * 8
     assert ctypes.sizeof(native.DiagCfg) == 28 + 12
     assert ctypes.sizeof(native.DiagRow) == 8 * 14 + 4 + 4 + 3 * 8 + 3 * 8 + 3 * 8 + 2 * 8
-    assert ctypes.sizeof(native.Info) == 7 * 8 + 3 * 8 + 3 * 4 + 4
+    assert ctypes.sizeof(native.Info) == 7 * 8 + 3 * 8 + 3 * 4 + 4 + 3 * 4 + 4
 
 
 def test_last_error_is_empty_string_before_any_failure():

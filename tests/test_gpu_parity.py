@@ -929,6 +929,33 @@ def test_run_twice_is_bitwise_identical(precision):
     assert outs[0][2].tobytes() == outs[1][2].tobytes()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tuned_shapes_do_not_change_the_bits(precision):
+    """The tuner picks the stencil tile and the brick of tiles dealt to each
+    XCD; neither changes any result: a tuned run after a few steps equals an
+    untuned run bit for bit (the 64x64x128 subcase, whose tile grid admits
+    several brick shapes, 24 steps)."""
+    w = W.mid_subcase(steps=24)
+    outs = []
+    for tuned in (False, True):
+        sim = native.sim_from_workload(w, precision=precision)
+        sim.run(6)
+        if tuned:
+            sim.tune(1)
+        sim.run(18)
+        sim.sync()
+        info = sim.info()
+        say("tuned" if tuned else "default", info["stencil_tile"], info["particle_brick"])
+        outs.append(([sim.get_field(f) for f in ("Ax", "Az", "phi", "Jx", "Jz", "rho")],
+                     sim.get_particles(), sim.get_diag()))
+        sim.close()
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b, equal_nan=True)
+    assert outs[0][2].tobytes() == outs[1][2].tobytes()
+
+
 def test_graph_with_two_streams_equals_kernel_by_kernel_bitwise():
     """The captured step runs the scan and scatter on a second stream beside
     the deposit; kernel-by-kernel execution on one stream (timing mode) must
