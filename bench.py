@@ -455,6 +455,10 @@ def main():
                          "particles, run to saturation, gain length fitted)")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline workload only (for profiling runs)")
+    ap.add_argument("--profile-leg", choices=("large", "large-f64", "mid"),
+                    help="run only this workload's timed regions (for counter runs under "
+                         "rocprofv3, with --copy-probe for the counter scale); prints no "
+                         "JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -479,6 +483,17 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 5 x 1 GiB read + 1 GiB written")
         del src, dst
+
+    if args.profile_leg:
+        wl = W.config(1) if args.profile_leg == "mid" else W.config(3)
+        prec = "f32" if args.profile_leg == "large" else "f64"
+        log("profile leg %s: %s, %d particles, %s, %d steps" % (args.profile_leg, wl.n, wl.np,
+                                                               prec, K))
+        dtp, _, perp, _, infop = measure(wl, prec, K, Wm, torch, native)
+        log("  %.4f ms/step, tile %s, brick %s, kernels %s" % (
+            dtp * 1e3 / K, infop["stencil_tile"], infop["particle_brick"],
+            {k: round(v, 4) for k, v in perp.items()}))
+        return
 
     # ---- headline: the large configuration, float split form -----------------
     w = W.config(3)

@@ -178,7 +178,8 @@ def _tapered_flat_top(u: np.ndarray, length: float, sigma: float) -> np.ndarray:
 
 def example1(*, n=(64, 64, 2800), n_particles: int = 131072, steps: int = 17900,
              seed: int = BASE_SEED + 10, bunching: float = 0.01,
-             substeps: int = 2, transverse: str = "gaussian") -> Workload:
+             substeps: int = 2, transverse: str = "gaussian", flat_top: float = 100.5e-6,
+             sigma_t: float = 260e-6) -> Workload:
     """The paper's infrared FEL example (section "Example 1: Infrared FEL"),
     lab parameters from its table and job file, taken into the rest frame.
 
@@ -202,6 +203,10 @@ def example1(*, n=(64, 64, 2800), n_particles: int = 131072, steps: int = 17900,
     The power plane sits 110 um (lab) ahead of the bunch centre.
     ``transverse="uniform"`` loads the table's reading instead: a uniform
     260 x 260 um square (the printed electron density 2.72e13 cm^-3).
+    ``flat_top`` and ``sigma_t`` (lab) change the flat top's length and the
+    transverse width at the same peak density (the charge scales with them):
+    a longer bunch slips fewer of its cooperation lengths, a wider one
+    diffracts less.  The plane then sits 59.75 um ahead of the flat top's head.
     """
     n = tuple(int(v) for v in n)
     gamma, K, lambda_u, sigma_delta = 100.41, 1.417, 0.03, 1e-4
@@ -214,14 +219,14 @@ def example1(*, n=(64, 64, 2800), n_particles: int = 131072, steps: int = 17900,
     z_e = origin[2] - d[2]
     # quiet start: Halton points, indices from 1; keep the first n_particles
     # whose transverse radius is inside the 4-sigma cut
-    sig_t, cut = 260e-6, 1040e-6
+    sig_t, cut = sigma_t, 4.0 * sigma_t
     idx = np.arange(1, int(n_particles * 1.01) + 64)
     r = sig_t * np.sqrt(-2.0 * np.log(halton(idx, 3)))
     keep = r <= cut
     idx = idx[keep][:n_particles]
     r = r[keep][:n_particles]
     th = 2.0 * math.pi * halton(idx, 5)
-    zl = _tapered_flat_top(halton(idx, 2), 100.5e-6, lam_r)
+    zl = _tapered_flat_top(halton(idx, 2), flat_top, lam_r)
     x = np.empty((n_particles, 3))
     if transverse == "uniform":
         x[:, 0] = (halton(idx, 3) - 0.5) * sig_t
@@ -235,9 +240,11 @@ def example1(*, n=(64, 64, 2800), n_particles: int = 131072, steps: int = 17900,
     rng = np.random.Generator(np.random.PCG64(seed))
     gp = gamma * (1.0 + sigma_delta * rng.standard_normal(n_particles))
     u, x[:, 0] = _matched(x, gp, gamma0, beta0, K, ku, z_e, 1.0 * d[2] / C_LIGHT, substeps)
-    q = -BUNCH_CHARGE / n_particles
-    m = M_E * (BUNCH_CHARGE / Q_E) / n_particles
-    kp = min(n[2] // 2 + int(round(gamma0 * 110e-6 / d[2])), n[2] - 3)
+    charge = BUNCH_CHARGE * (flat_top / 100.5e-6) * (sigma_t / 260e-6) ** 2
+    q = -charge / n_particles
+    m = M_E * (charge / Q_E) / n_particles
+    ahead = flat_top / 2.0 + 59.75e-6  # 110 um ahead of the centre for the job's bunch
+    kp = min(n[2] // 2 + int(round(gamma0 * ahead / d[2])), n[2] - 3)
     return Workload(name="example1-%dx%dx%d" % n, n=n, d=d, origin=origin, courant=1.0,
                     nsfd_A=-1.0, substeps=substeps, space_charge=0, bc=(2, 2, 2),
                     lambda_u=lambda_u, K=K, gamma_beam=gamma, z_e=z_e, x=x, u=u, q=q, m=m,

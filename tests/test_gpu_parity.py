@@ -1418,9 +1418,10 @@ def test_example1_grows_exponentially_and_saturates():
     transverse profile, tapered flat top, bunching 0.01, second-order Mur, no
     space charge), 6000 steps = 3 m of undulator.  The power through the plane
     ahead of the bunch grows exponentially and saturates; the fitted power gain
-    length lies between the one-dimensional value and twice M. Xie's
-    three-dimensional estimate for this beam.  (The paper reports 0.22 m,
-    about its one-dimensional value; this run gives about 0.5 m.)"""
+    length lies between M. Xie's three-dimensional estimate for this beam and
+    1.5 times it.  (The paper reports 0.22 m, about its one-dimensional value;
+    this run gives about 0.5 m: the bunch is only a few cooperation lengths
+    long, see the longer-bunch test below.)"""
     import bench
     w = W.example1(steps=6000)
     say("case example1", w.n, w.np)
@@ -1438,7 +1439,36 @@ def test_example1_grows_exponentially_and_saturates():
     assert dg["lost"][-1] < 0.01 * w.np
     assert 1.5 < z_sat < 2.95  # the peak lies inside the run, not at its end
     assert b - a > 1000  # more than half a metre of exponential growth
-    assert l1 < lg < 2.0 * l3, (lg, l1, l3)
+    assert l3 < lg < 1.5 * l3, (lg, l1, l3)
+
+
+def _example1_gain_length(**kw):
+    import bench
+    w = W.example1(steps=6000, **kw)
+    sim = native.sim_from_workload(w, precision="f64", every=100, capacity=6100, spectrum=False)
+    sim.run(6000)
+    sim.sync()
+    dg = sim.get_diag()
+    info = sim.info()
+    sim.close()
+    assert not dg["nonfinite"].any() and dg["lost"][-1] < 0.01 * w.np
+    dz_step = info["gamma0"] * info["beta0"] * C * info["dt"]
+    return bench.gain_length(dg["power"], dz_step)[0]
+
+
+def test_example1_longer_bunch_grows_faster():
+    """Slippage: the job's flat top (100.5 um) is only a few cooperation
+    lengths lambda_r / (4 pi rho) long, so the radiation leaves the bunch
+    before it has grown much.  Four times the flat top at the same density
+    (402 um, 524288 particles, 64x64x6400) grows clearly faster, and still no
+    faster than the one-dimensional limit of this density."""
+    import bench
+    lg1 = _example1_gain_length()
+    lg4 = _example1_gain_length(n=(64, 64, 6400), n_particles=524288, flat_top=402e-6)
+    rho, l1, l3 = bench.fel_theory(100.41, 1.417, 0.03, 260e-6, 88.5, 1e-4)
+    say("example1 gain length, job bunch", lg1, "four times longer", lg4, "1D", l1)
+    assert lg4 < 0.85 * lg1, (lg1, lg4)
+    assert lg4 > l1, (lg4, l1)
 
 
 def test_plain_c_caller_equals_the_binding_bitwise(tmp_path):
