@@ -1659,9 +1659,35 @@ __device__ __forceinline__ int4 load4(const int *__restrict__ a, long long i, lo
     return v;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int *__restrict__ counts,
-                                                        long long n, int *__restrict__ bsum)
+// A chunk of keys whose tiles no particle can occupy in the next step (their
+// occupancy flags, written by the push, are clear) and that holds no lost
+// bucket has only zero counts: the scan skips reading them.  chunks[b] =
+// (first global tile, last global tile, holds a lost bucket); the flags of
+// the next step are pocc[(step + 1) & 1].  Uniform over the block.
+__device__ __forceinline__ bool chunk_empty(const int4 *__restrict__ chunks, const Arena &ar)
 {
+    __shared__ int any;
+    const int4 ck = chunks[blockIdx.x];
+    const long long step = *ar.d_step;
+    const int *__restrict__ occ = ar.pocc[(step + 1) & 1];
+    if (threadIdx.x == 0) any = ck.z;
+    __syncthreads();
+    const int t = ck.x + (int)threadIdx.x;
+    if (t <= ck.y && occ[t]) any = 1;
+    __syncthreads();
+    const bool empty = any == 0;
+    __syncthreads();  // every thread has read the flag
+    return empty;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const int *__restrict__ counts,
+                                                        long long n, int *__restrict__ bsum,
+                                                        const int4 *__restrict__ chunks, Arena ar)
+{
+    if (chunk_empty(chunks, ar)) {
+        if (threadIdx.x == 0) bsum[blockIdx.x] = 0;
+        return;
+    }
     const long long base = (long long)blockIdx.x * SCAN_CHUNK + 4 * threadIdx.x;
     int4 v[SCAN_CHUNK / SCAN_ROW];
 #pragma unroll
@@ -1712,12 +1738,31 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(int *__restrict__ bsum, int 
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scan_down(const int *__restrict__ counts, long long n,
-                                                      const int *__restrict__ bsum, Arena ar)
+                                                      const int *__restrict__ bsum,
+                                                      const int4 *__restrict__ chunks, Arena ar)
 {
     const long long step = *ar.d_step;
     int *__restrict__ out = ar.offs[(step + 1) & 1];
     const long long chunk0 = (long long)blockIdx.x * SCAN_CHUNK;
     const long long base = chunk0 + 4 * threadIdx.x;
+    if (chunk_empty(chunks, ar)) {
+        // every count is zero: each start is the carry into the chunk
+        const int carry = bsum[blockIdx.x];
+        const int4 o = make_int4(carry, carry, carry, carry);
+#pragma unroll
+        for (int r = 0; r < SCAN_CHUNK / SCAN_ROW; ++r) {
+            const long long i = base + r * SCAN_ROW;
+            if (i + 3 < n) {
+                *reinterpret_cast<int4 *>(out + i) = o;
+            } else {
+                if (i < n) out[i] = carry;
+                if (i + 1 < n) out[i + 1] = carry;
+                if (i + 2 < n) out[i + 2] = carry;
+            }
+        }
+        if (threadIdx.x == 0 && chunk0 + SCAN_CHUNK >= n) out[n] = carry;  // total
+        return;
+    }
     int4 v[SCAN_CHUNK / SCAN_ROW];
 #pragma unroll
     for (int r = 0; r < SCAN_CHUNK / SCAN_ROW; ++r) v[r] = load4(counts, base + r * SCAN_ROW, n);
@@ -2249,13 +2294,13 @@ void launch_deposit(hipStream_t st, const SimDev *sims, const Brick *bricks, int
 }
 
 void launch_scan(hipStream_t st, const Arena &ar, long long nkeys_total, int *block_sums,
-                 int nblocks, const long long *)
+                 int nblocks, const int4 *chunks)
 {
     hipLaunchKernelGGL(k_scan_reduce, dim3(nblocks), dim3(BLOCK), 0, st, ar.counts, nkeys_total,
-                       block_sums);
+                       block_sums, chunks, ar);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, st, block_sums, nblocks);
     hipLaunchKernelGGL(k_scan_down, dim3(nblocks), dim3(BLOCK), 0, st, ar.counts, nkeys_total,
-                       block_sums, ar);
+                       block_sums, chunks, ar);
 }
 
 template <typename R>

@@ -192,8 +192,10 @@ void launch_push(hipStream_t st, const SimDev *sims, const Brick *bricks, int nb
 template <typename R>
 void launch_deposit(hipStream_t st, const SimDev *sims, const Brick *bricks, int nbricks, int4 bs,
                     const Arena &ar, int init);
+// chunks: per chunk of SCAN_CHUNK keys, (first global tile, last global tile,
+// holds a lost bucket), for skipping chunks of unoccupied tiles
 void launch_scan(hipStream_t st, const Arena &ar, long long nkeys_total, int *block_sums,
-                 int nblocks, const long long *d_step);
+                 int nblocks, const int4 *chunks);
 template <typename R>
 void launch_scatter(hipStream_t st, const Arena &ar, long long nparticles);
 template <typename R>
