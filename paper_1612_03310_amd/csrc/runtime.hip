@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -1845,9 +1846,14 @@ static mithra_status get_info(Batch &b, int s, mithra_info *info)
 // The brick shape of the push and the deposit: each candidate times trials
 // launches of the push followed by the deposit on the simulation's current
 // particles.  Those kernels change the particle buffer in place and write J,
-// rho, the bin counts and the flags, so these are copied aside first and put
-// back after every trial; the tile flags are reset by the table rebuild
-// that follows (the results of a step never depend on the brick shape).
+// rho, the bin counts, the error flags and the per-tile flags (occupancy,
+// active, dirty), so these are copied aside first and put back after every
+// trial: each trial does a step's work (with the occupancy flags left as the
+// first trial leaves them, the later pushes would find every tile empty).
+// During the trials the dirty flags are cleared, as in a running simulation
+// where the tiles away from the bunch hold zero sources and are skipped; the
+// copies put back at the end restore them.  The results of a step never
+// depend on the brick shape.
 template <typename R>
 static mithra_status tune_bricks(Batch &b, int trials)
 {
@@ -1867,6 +1873,10 @@ static mithra_status tune_bricks(Batch &b, int trials)
         keep.push_back({b.ar.u[par][a], sizeof(R) * N});
         keep.push_back({b.ar.J[a], sizeof(R) * M});
     }
+    const size_t tb = sizeof(int) * std::max(b.n_tiles, 1);
+    for (int *f : {b.ar.pocc[0], b.ar.pocc[1], b.ar.tact, b.ar.jdirty, b.ar.rdirty[0],
+                   b.ar.rdirty[1]})
+        keep.push_back({f, tb});
     std::vector<Batch::Block> scratch;
     std::vector<void *> copy;
     for (const Span &k : keep) {
@@ -1878,11 +1888,13 @@ static mithra_status tune_bricks(Batch &b, int trials)
         copy.push_back(c);
         HIP_TRY(hipMemcpyAsync(c, k.p, k.bytes, hipMemcpyDeviceToDevice, b.stream));
     }
-    auto restore = [&]() -> hipError_t {
+    auto restore = [&](bool trial) -> hipError_t {
         hipError_t e = hipSuccess;
         for (size_t i = 0; i < keep.size() && e == hipSuccess; ++i)
             e = hipMemcpyAsync(keep[i].p, copy[i], keep[i].bytes, hipMemcpyDeviceToDevice, b.stream);
         if (e == hipSuccess) e = hipMemsetAsync(b.ar.counts, 0, sizeof(int) * b.total_keys, b.stream);
+        for (int *f : {b.ar.jdirty, b.ar.rdirty[0], b.ar.rdirty[1]})
+            if (trial && e == hipSuccess) e = hipMemsetAsync(f, 0, tb, b.stream);
         return e;
     };
     int maxt[3] = {1, 1, 1};
@@ -1897,10 +1909,20 @@ static mithra_status tune_bricks(Batch &b, int trials)
     };
     std::vector<Cand> cands;
     std::vector<Brick> table;
-    for (const auto &sh : shapes) {
+    // the fixed shapes that fit in some grid, then whole tile layers of the
+    // largest grid, one, two and four deep
+    std::vector<std::array<int, 3>> cand_shapes;
+    for (const auto &sh : shapes)
+        if (sh[0] <= maxt[0] && sh[1] <= maxt[1] && sh[2] <= maxt[2])
+            cand_shapes.push_back({sh[0], sh[1], sh[2]});
+    for (int d : {1, 2, 4}) {
+        const std::array<int, 3> w = {maxt[0], maxt[1], std::min(d, maxt[2])};
+        if (std::find(cand_shapes.begin(), cand_shapes.end(), w) == cand_shapes.end())
+            cand_shapes.push_back(w);
+    }
+    for (const auto &sh : cand_shapes) {
         Cand k;
-        for (int a = 0; a < 3; ++a) k.c[a] = std::min(sh[a], maxt[a]);
-        if (k.c[0] != sh[0] || k.c[1] != sh[1] || k.c[2] != sh[2]) continue;  // larger than every grid
+        for (int a = 0; a < 3; ++a) k.c[a] = sh[a];
         brick_table(b, k.c, table);
         k.d = (Brick *)dev_alloc(b, table.size() * sizeof(Brick), scratch);
         if (!k.d) continue;
@@ -1912,13 +1934,12 @@ static mithra_status tune_bricks(Batch &b, int trials)
         cands.push_back(k);
     }
     // two passes, the second in reverse order, each candidate keeping its
-    // best trial: the timings of neighbouring shapes are close, and a single
-    // pass in one order let drift pick the slower one
+    // best trial, so that a slow spell of the device does not decide
     for (int pass = 0; pass < 2; ++pass) {
         for (size_t q = 0; q < cands.size(); ++q) {
             Cand &k = cands[pass ? cands.size() - 1 - q : q];
             for (int t = 0; t < trials + 1; ++t) {  // the first is a warm-up
-                HIP_TRY(restore());
+                HIP_TRY(restore(true));
                 HIP_TRY(hipEventRecord(e0, b.stream));
                 launch_push<R>(b.stream, b.d_sims, k.d, k.n, brick_shape(k.c), b.ar,
                                any_optical(b));
@@ -1939,7 +1960,7 @@ static mithra_status tune_bricks(Batch &b, int trials)
             best = k.ms;
             for (int a = 0; a < 3; ++a) pick[a] = k.c[a];
         }
-    HIP_TRY(restore());
+    HIP_TRY(restore(false));
     HIP_TRY(hipStreamSynchronize(b.stream));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
