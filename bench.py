@@ -200,16 +200,20 @@ def timed_run(sim, steps, torch):
     return time.perf_counter() - t0
 
 
-def measure(w, precision, steps, warmup, torch, native, tune=True, every=100, seed=None):
+def measure(w, precision, steps, warmup, torch, native, tune=True, every=100, seed=None,
+            shapes=None):
     """Graph-replayed timed region, then an event-timed region of the same
     length for the per-kernel durations.  The library captures its step graph
-    on the first run, so the warm-up run builds it before timing starts."""
+    on the first run, so the warm-up run builds it before timing starts.
+    shapes: (stencil tile, particle brick) set instead of tuning."""
     t_setup = time.perf_counter()
     sim = native.sim_from_workload(w, precision=precision, every=every, spectrum=False,
                                    capacity=2 * steps + warmup + 8)
     if seed is not None:
         sim.set_seed(**seed)
-    if tune:
+    if shapes is not None:
+        sim.set_shapes(*shapes)
+    elif tune:
         sim.tune(3)
     sim.run(max(warmup, 1))
     sim.sync()
@@ -459,6 +463,10 @@ def main():
                     help="run only this workload's timed regions (for counter runs under "
                          "rocprofv3, with --copy-probe for the counter scale); prints no "
                          "JSON line")
+    ap.add_argument("--shapes", metavar="TX,TY,KZ,BX,BY,BZ",
+                    help="with --profile-leg: set this stencil tile and particle brick "
+                         "instead of tuning (the tuner's timings mean little under a "
+                         "profiler that serializes kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -489,7 +497,13 @@ def main():
         prec = "f32" if args.profile_leg == "large" else "f64"
         log("profile leg %s: %s, %d particles, %s, %d steps" % (args.profile_leg, wl.n, wl.np,
                                                                prec, K))
-        dtp, _, perp, _, infop = measure(wl, prec, K, Wm, torch, native)
+        shapes = None
+        if args.shapes:
+            v = [int(x) for x in args.shapes.split(",")]
+            if len(v) != 6:
+                ap.error("--shapes takes six integers: TX,TY,KZ,BX,BY,BZ")
+            shapes = (v[:3], v[3:])
+        dtp, _, perp, _, infop = measure(wl, prec, K, Wm, torch, native, shapes=shapes)
         log("  %.4f ms/step, tile %s, brick %s, kernels %s" % (
             dtp * 1e3 / K, infop["stencil_tile"], infop["particle_brick"],
             {k: round(v, 4) for k, v in perp.items()}))

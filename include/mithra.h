@@ -434,6 +434,18 @@ mithra_status mithra_get_timing(mithra_sim *sim, double *ms, int64_t *calls, int
    whatever shapes were chosen. */
 mithra_status mithra_tune(mithra_sim *sim, int32_t trial_steps);
 
+/* Sets the shapes the autotuner chooses, without timing anything: for runs
+   that reuse what an earlier mithra_tune found (mithra_get_info reports it),
+   and for profilers, under which trial timings mean little.  stencil_tile:
+   x and y columns per block, one of 64x4, 32x8, 128x2, 64x2, 32x4, 16x16,
+   256x1, 128x1, 128x4, 256x2, 64x8, and z planes per block (>= 1);
+   particle_brick: tiles per brick along x, y, z (each >= 1, clipped to the
+   largest tile grid).  Results do not depend on the shapes.  Returns
+   MITHRA_EINVAL (and changes nothing) for a NULL array or a shape outside
+   these sets. */
+mithra_status mithra_set_shapes(mithra_sim *sim, const int32_t stencil_tile[3],
+                                const int32_t particle_brick[3]);
+
 const char *mithra_last_error(void);
 void mithra_destroy(mithra_sim *sim);
 
@@ -460,6 +472,10 @@ mithra_status mithra_batch_set_seed_beam(mithra_batch *b, int32_t sim, const mit
 /* Autotuner of the batch (see mithra_tune): one tile shape for all
    simulations, chosen by timing the whole batched launch. */
 mithra_status mithra_batch_tune(mithra_batch *b, int32_t trial_steps);
+/* mithra_set_shapes for the batch: one stencil tile and one brick for all
+   simulations. */
+mithra_status mithra_batch_set_shapes(mithra_batch *b, const int32_t stencil_tile[3],
+                                      const int32_t particle_brick[3]);
 mithra_status mithra_batch_run(mithra_batch *b, int64_t nsteps);
 mithra_status mithra_batch_sync(mithra_batch *b);
 mithra_status mithra_batch_get_diag(mithra_batch *b, int32_t sim, mithra_diag_row *rows,

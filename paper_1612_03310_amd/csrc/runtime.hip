@@ -2050,6 +2050,23 @@ static mithra_status tune(Batch &b, int trials)
     return b.prec == MITHRA_F64 ? tune_impl<double>(b, trials) : tune_impl<float>(b, trials);
 }
 
+// the tuner's choice set directly (nothing is timed)
+static mithra_status set_shapes(Batch &b, const int32_t *tile, const int32_t *brick)
+{
+    if (!tile || !brick) return fail(MITHRA_EINVAL, "stencil_tile and particle_brick must not be NULL");
+    if (!stencil_shape_supported(tile[0], tile[1]))
+        return fail(MITHRA_EINVAL, "stencil tile %dx%d is not one of the built shapes", tile[0], tile[1]);
+    if (tile[2] < 1) return fail(MITHRA_EINVAL, "z planes per stencil block must be >= 1");
+    if (brick[0] < 1 || brick[1] < 1 || brick[2] < 1)
+        return fail(MITHRA_EINVAL, "brick sides must be >= 1");
+    HIP_TRY(hipSetDevice(b.device));
+    b.tile_x = tile[0];
+    b.tile_y = tile[1];
+    b.kz = tile[2];
+    for (int a = 0; a < 3; ++a) b.brick[a] = brick[a];
+    return b.committed ? build_tables(b) : MITHRA_OK;  // else the commit builds them
+}
+
 // ---------------------------------------------------------------------------
 // checkpoint
 // ---------------------------------------------------------------------------
@@ -2486,6 +2503,13 @@ mithra_status mithra_tune(mithra_sim *sim, int32_t trial_steps)
     return tune(*sim->b, trial_steps);
 }
 
+mithra_status mithra_set_shapes(mithra_sim *sim, const int32_t stencil_tile[3],
+                                const int32_t particle_brick[3])
+{
+    if (!sim) return fail(MITHRA_EINVAL, "sim is NULL");
+    return set_shapes(*sim->b, stencil_tile, particle_brick);
+}
+
 void mithra_destroy(mithra_sim *sim)
 {
     if (!sim) return;
@@ -2577,6 +2601,13 @@ mithra_status mithra_batch_tune(mithra_batch *bb, int32_t trial_steps)
 {
     if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
     return tune(*bb->b, trial_steps);
+}
+
+mithra_status mithra_batch_set_shapes(mithra_batch *bb, const int32_t stencil_tile[3],
+                                      const int32_t particle_brick[3])
+{
+    if (!bb) return fail(MITHRA_EINVAL, "batch is NULL");
+    return set_shapes(*bb->b, stencil_tile, particle_brick);
 }
 
 mithra_status mithra_batch_run(mithra_batch *bb, int64_t nsteps)

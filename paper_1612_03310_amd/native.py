@@ -40,7 +40,8 @@ ABI_FUNCTIONS = (
     "mithra_set_optical_beam", "mithra_batch_set_optical_beam",
     "mithra_set_seed_beam", "mithra_batch_set_seed_beam", "mithra_set_background",
     "mithra_get_bins", "mithra_get_field_noalloc", "mithra_set_spectrum", "mithra_get_spectrum",
-    "mithra_batch_set_spectrum", "mithra_batch_get_spectrum",
+    "mithra_batch_set_spectrum", "mithra_batch_get_spectrum", "mithra_set_shapes",
+    "mithra_batch_set_shapes",
 )
 
 MAX_FREQ = 32
@@ -194,6 +195,7 @@ def load_library(path: str = LIB_PATH):
         "mithra_set_timing": [P, I32],
         "mithra_get_timing": [P, dp, ctypes.POINTER(ctypes.c_int64), I32, I32],
         "mithra_tune": [P, I32],
+        "mithra_set_shapes": [P, ctypes.POINTER(I32), ctypes.POINTER(I32)],
         "mithra_batch_create": [I32, ctypes.POINTER(Mesh), ctypes.POINTER(Undulator), I32, P, pp],
         "mithra_batch_set_particles": [P, I32, I64, dp, dp, D, D],
         "mithra_batch_config_diag": [P, I32, ctypes.POINTER(DiagCfg)],
@@ -202,6 +204,7 @@ def load_library(path: str = LIB_PATH):
         "mithra_batch_set_spectrum": [P, I32, dp, I32],
         "mithra_batch_get_spectrum": [P, I32, I64, I64, dp, dp],
         "mithra_batch_tune": [P, I32],
+        "mithra_batch_set_shapes": [P, ctypes.POINTER(I32), ctypes.POINTER(I32)],
         "mithra_batch_run": [P, I64],
         "mithra_batch_sync": [P],
         "mithra_batch_get_diag": [P, I32, ctypes.POINTER(DiagRow), I64,
@@ -519,6 +522,11 @@ class Sim:
     def tune(self, trials: int = 5):
         _check(self._lib.mithra_tune(self._h, int(trials)))
 
+    def set_shapes(self, stencil_tile: Sequence[int], particle_brick: Sequence[int]):
+        t = (ctypes.c_int32 * 3)(*map(int, stencil_tile))
+        b = (ctypes.c_int32 * 3)(*map(int, particle_brick))
+        _check(self._lib.mithra_set_shapes(self._h, t, b))
+
 
 class Batch:
     """Independent simulations advanced in lockstep with shared launches."""
@@ -596,6 +604,11 @@ class Batch:
 
     def tune(self, trials: int = 5):
         _check(self._lib.mithra_batch_tune(self._h, int(trials)))
+
+    def set_shapes(self, stencil_tile: Sequence[int], particle_brick: Sequence[int]):
+        t = (ctypes.c_int32 * 3)(*map(int, stencil_tile))
+        b = (ctypes.c_int32 * 3)(*map(int, particle_brick))
+        _check(self._lib.mithra_batch_set_shapes(self._h, t, b))
 
     def run(self, nsteps: int):
         _check(self._lib.mithra_batch_run(self._h, int(nsteps)))

@@ -956,6 +956,59 @@ def test_tuned_shapes_do_not_change_the_bits(precision):
     assert outs[0][2].tobytes() == outs[1][2].tobytes()
 
 
+def test_set_shapes_applies_them_and_keeps_the_bits():
+    """Shapes set directly (what a profiler run or a tuned deployment uses)
+    are the ones the launches take, give the default run's bits, and a shape
+    outside the built set is refused without changing the current ones (the
+    64x64x128 subcase, 16 steps, float)."""
+    w = W.mid_subcase(steps=16)
+    outs = []
+    for shapes in (None, ([128, 2, 32], [8, 8, 1]), ([32, 8, 16], [2, 2, 16])):
+        sim = native.sim_from_workload(w, precision="f32")
+        if shapes is not None:
+            sim.run(4)
+            sim.set_shapes(*shapes)
+            info = sim.info()
+            assert info["stencil_tile"] == shapes[0] and info["particle_brick"] == shapes[1]
+            for bad in (([100, 2, 32], [8, 8, 1]), ([128, 2, 0], [8, 8, 1]),
+                        ([128, 2, 32], [0, 8, 1])):
+                with pytest.raises(native.MithraError):
+                    sim.set_shapes(*bad)
+            assert sim.info()["stencil_tile"] == shapes[0]
+            sim.run(12)
+        else:
+            sim.run(16)
+        sim.sync()
+        outs.append(([sim.get_field(f) for f in ("Ax", "Az", "phi", "Jx", "rho")],
+                     sim.get_particles(), sim.get_diag()))
+        sim.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0][0], o[0]):
+            assert np.array_equal(a, b)
+        for a, b in zip(outs[0][1], o[1]):
+            assert np.array_equal(a, b, equal_nan=True)
+        assert outs[0][2].tobytes() == o[2].tobytes()
+    # the batch form: one shape for every simulation
+    ws = [W.make_workload("s%d" % i, n, npart, g, K, 0.015, 1e-4, 300 + i, 12)
+          for i, (n, npart, g, K) in enumerate([((32, 32, 128), 3000, 90.0, 0.9),
+                                                  ((48, 48, 96), 6000, 150.0, 1.6)])]
+    res = []
+    for shapes in (None, ([64, 2, 16], [2, 2, 2])):
+        b = native.batch_from_workloads(ws, precision="f32")
+        if shapes is not None:
+            b.set_shapes(*shapes)
+            with pytest.raises(native.MithraError):
+                b.set_shapes([64, 3, 16], [2, 2, 2])
+            assert b.info(1)["stencil_tile"] == shapes[0]
+        b.run(12)
+        b.sync()
+        res.append([b.get_field(s, f) for s in range(2) for f in ("Ax", "phi", "Jz")] +
+                   [b.get_diag(s).tobytes() for s in range(2)])
+        b.close()
+    for x, y in zip(res[0], res[1]):
+        assert np.array_equal(x, y) if isinstance(x, np.ndarray) else x == y
+
+
 def test_graph_with_two_streams_equals_kernel_by_kernel_bitwise():
     """The captured step runs the scan and scatter on a second stream beside
     the deposit; kernel-by-kernel execution on one stream (timing mode) must
