@@ -181,11 +181,22 @@ def example1_run(steps, torch, native, W):
     dz_step = info["gamma0"] * info["beta0"] * 299792458.0 * info["dt"]
     lg, z_sat, p_sat, a, b = gain_length(dg["power"], dz_step)
     rho, l1, l3 = fel_theory(w.gamma_beam, w.K, w.lambda_u, 260e-6, 88.5, 1e-4)
+    # lab-frame power through the plate, smoothed like the rest-frame one; the
+    # one-dimensional saturation estimate rho * P_beam (beam power: the
+    # electrons' energy times the current) and M. Xie's three-dimensional one,
+    # 1.6 rho (L_1D / L_G)^2 P_beam with the fitted gain length
+    lab = np.convolve(dg["power_lab"], np.ones(60) / 60, mode="valid")
+    p_beam = (w.gamma_beam * 0.51099895e6) * 88.5
+    p_3d = 1.6 * rho * (l1 / lg) ** 2 * p_beam if lg else None
     return {"workload": w.name, "particles": w.np, "steps": steps,
             "ms_per_step": round(dt * 1e3 / (steps - 8), 5),
             "gain_length_m": None if lg is None else round(lg, 4),
             "fit_steps": [a, b], "saturation_at_m": round(z_sat, 3),
-            "peak_power_rest_frame_W": round(p_sat, 2), "lost": int(dg["lost"][-1]),
+            "peak_power_rest_frame_W": round(p_sat, 2),
+            "peak_power_lab_W": float("%.4g" % lab.max()),
+            "saturation_power_1d_W": float("%.4g" % (rho * p_beam)),
+            "saturation_power_3d_W": None if p_3d is None else float("%.4g" % p_3d),
+            "lost": int(dg["lost"][-1]),
             "bunching_max": round(float(dg["bunching"][:, 0].max()), 4),
             "rho_1d": round(rho, 5), "gain_length_1d_m": round(l1, 4),
             "gain_length_3d_xie_m": round(l3, 4), "gain_length_paper_m": 0.22}
