@@ -902,11 +902,16 @@ __device__ __forceinline__ void count_runs(int *counts, int key, bool active)
 }
 
 // OPTICAL: the variant that also evaluates the optical undulator (its FP64
-// transcendentals would otherwise raise the register count of every launch)
+// transcendentals would otherwise raise the register count of every launch).
+// The single-precision kernel is held to 80 registers, six waves per SIMD:
+// the push gains from every tile in flight on a compute unit (it contends
+// for the vector-memory pipeline), and 80 is what it needs without spilling
+// once no particle is held in registers while the field table is built.
 template <typename R, bool OPTICAL>
-__global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
-                                                 const Brick *__restrict__ bricks, int nbricks,
-                                                 int4 bs, Arena ar)
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(OPTICAL ? 1 : sizeof(R) == 4 ? 6 : 1))) void k_push(
+    const SimDev *__restrict__ sims, const Brick *__restrict__ bricks, int nbricks, int4 bs,
+    Arena ar)
 {
     int sim, tl, ti;  // ti: the global tile index
     if (!brick_tile(blockIdx.x, bricks, nbricks, bs, sim, tl, ti)) return;
@@ -955,20 +960,11 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
     R *__restrict__ u1 = (R *)ar.u[par][1];
     R *__restrict__ u2 = (R *)ar.u[par][2];
 
-    // The thread's first particle is loaded together with the fields, so a
-    // block waits for memory once before the E, B table is built.
+    // the particle's key, offset and momentum (loaded in the particle loop,
+    // after the field table: held across the table they would cost the
+    // registers of a sixth wave)
     int gk = 0;
     R f[3] = {0, 0, 0}, u[3] = {0, 0, 0};
-    if (p_lo + (int)threadIdx.x < p_hi) {
-        const int p = p_lo + threadIdx.x;
-        gk = key[p];
-        f[0] = o0[p];
-        f[1] = o1[p];
-        f[2] = o2[p];
-        u[0] = u0[p];
-        u[1] = u1[p];
-        u[2] = u2[p];
-    }
 
     // E and B at the tile's 9^3 vertices, from the potentials of the box
     // [L-1, L+9]^3 in two passes over one LDS staging area of 4 x 11^3
@@ -1170,15 +1166,13 @@ __global__ __launch_bounds__(BLOCK) void k_push(const SimDev *__restrict__ sims,
         const bool active = p < p_hi;
         int ngk = 0;
         if (active) {
-            if (base != p_lo) {
-                gk = key[p];
-                f[0] = o0[p];
-                f[1] = o1[p];
-                f[2] = o2[p];
-                u[0] = u0[p];
-                u[1] = u1[p];
-                u[2] = u2[p];
-            }
+            gk = key[p];
+            f[0] = o0[p];
+            f[1] = o1[p];
+            f[2] = o2[p];
+            u[0] = u0[p];
+            u[1] = u1[p];
+            u[2] = u2[p];
             const int lkey = (gk - (int)S.key0) & (TILE_CELLS - 1);
             const int li = lkey & 7, lj = (lkey >> 3) & 7, lk = lkey >> 6;
             int c[3] = {L0 + li, L1 + lj, L2 + lk};
