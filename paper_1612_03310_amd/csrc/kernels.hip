@@ -960,11 +960,26 @@ __attribute__((amdgpu_waves_per_eu(OPTICAL ? 1 : sizeof(R) == 4 ? 6 : 1))) void 
     R *__restrict__ u1 = (R *)ar.u[par][1];
     R *__restrict__ u2 = (R *)ar.u[par][2];
 
-    // the particle's key, offset and momentum (loaded in the particle loop,
-    // after the field table: held across the table they would cost the
-    // registers of a sixth wave)
+    // The particle's key, offset and momentum.  In the single-precision
+    // kernel they are loaded in the particle loop, after the field table:
+    // held across the table they would cost the registers of a sixth wave.
+    // The double-precision kernel (held by its LDS to three blocks per
+    // compute unit) and the optical one (by its registers to two waves) lose
+    // no wave by holding them: there the thread's first particle is loaded
+    // with the potentials, so that the block waits for memory once.
+    constexpr bool PRELOAD = sizeof(R) == 8 || OPTICAL;
     int gk = 0;
     R f[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+    if (PRELOAD && p_lo + (int)threadIdx.x < p_hi) {
+        const int p = p_lo + threadIdx.x;
+        gk = key[p];
+        f[0] = o0[p];
+        f[1] = o1[p];
+        f[2] = o2[p];
+        u[0] = u0[p];
+        u[1] = u1[p];
+        u[2] = u2[p];
+    }
 
     // E and B at the tile's 9^3 vertices, from the potentials of the box
     // [L-1, L+9]^3 in two passes over one LDS staging area of 4 x 11^3
@@ -1166,13 +1181,15 @@ __attribute__((amdgpu_waves_per_eu(OPTICAL ? 1 : sizeof(R) == 4 ? 6 : 1))) void 
         const bool active = p < p_hi;
         int ngk = 0;
         if (active) {
-            gk = key[p];
-            f[0] = o0[p];
-            f[1] = o1[p];
-            f[2] = o2[p];
-            u[0] = u0[p];
-            u[1] = u1[p];
-            u[2] = u2[p];
+            if (!PRELOAD || base != p_lo) {
+                gk = key[p];
+                f[0] = o0[p];
+                f[1] = o1[p];
+                f[2] = o2[p];
+                u[0] = u0[p];
+                u[1] = u1[p];
+                u[2] = u2[p];
+            }
             const int lkey = (gk - (int)S.key0) & (TILE_CELLS - 1);
             const int li = lkey & 7, lj = (lkey >> 3) & 7, lk = lkey >> 6;
             int c[3] = {L0 + li, L1 + lj, L2 + lk};
